@@ -1,0 +1,454 @@
+"""Plain, slow, FP64 CPU oracle of the IFU datacube forward model (arXiv:2412.08265).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the benchmark's CPU-baseline
+leg, never by the product path. It shares no code with the HIP library (no kernels, headers,
+helpers, tables or constants); it reads the same FP32 input arrays (promoted to FP64).
+
+The paper describes the method in one paragraph of Sec. 3 ("RUBIX Codebase"): orient the galaxy in
+the field of view, assign particles to IFU spaxels, look each star's spectrum up in an SSP library,
+Doppler-shift it by the line-of-sight velocity (and galaxy distance), resample it to the telescope
+wavelength grid, sum the spectra per spaxel, then convolve with a PSF and an LSF (Gaussian, Sec. 4
+"Qualitative Analysis"). Gradients through the whole pipeline are the paper's second claim
+(Abstract, Sec. 1). The paper gives no formula for any step; the readings this oracle takes where
+it is silent are stated at each function and collected in the design notes of the repository.
+
+Conventions (all readings):
+  * rotation R = Rz(phi3) Ry(phi2) Rx(phi1), column vectors; phi1 is the inclination;
+  * line of sight = rotated +z, v_los = (R v)_z, positive = receding = redshift;
+  * spaxel index ix = floor(x'/s + nx/2) (grid centred on the origin, half-open cells);
+  * SSP lookup = bilinear interpolation in (log10 age/Gyr, [M/H]), clamped to the node range;
+  * Doppler: a rest-frame wavelength lam_r is observed at lam_r (1+z_sys)(1+v_los/c); the observed
+    flux density is f_obs(lam) = J f_rest(lam / ((1+z_sys)(1+beta))), J = 1/((1+z_sys)(1+beta));
+  * resampling = linear interpolation of the shifted spectrum at telescope bin centres, zero outside
+    the SSP wavelength range;
+  * PSF / LSF = sampled, normalised Gaussians truncated at radius int(4 sigma + 0.5), zero padding;
+  * loss (differentiation workload) = 0.5 || A C_raw - T* ||^2 with A = PSF o LSF.
+"""
+from __future__ import annotations
+
+import math
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+C_KMS = 299792.458  # km/s
+
+__all__ = [
+    "C_KMS", "rotation_matrix", "rotation_matrix_derivs", "rotate_positions", "los_velocity",
+    "spaxel_keys", "sort_by_key", "ssp_cell", "ssp_weights", "interp_templates",
+    "doppler_index", "resample_linear", "particle_spectra", "cube_raw", "gaussian_weights",
+    "convolve_axis", "psf_lsf", "forward", "loss", "loss_grad_cube", "adjoint",
+    "OracleConfig", "config_from_workload",
+]
+
+
+# --------------------------------------------------------------------------------------------------
+# configuration
+# --------------------------------------------------------------------------------------------------
+class OracleConfig:
+    """Plain container of the run's hyper-parameters (the paper's JSON configuration, Sec. 3)."""
+
+    def __init__(self, angles_rad, nx, ny, spaxel_kpc, tel_start, tel_step, n_tel,
+                 log_age_nodes, met_nodes, ssp_lam_start, ssp_lam_step, ssp_flux,
+                 psf_sigma_spx=0.0, lsf_sigma_A=0.0, z_sys=0.0, flux_scale=1.0):
+        self.angles_rad = tuple(float(a) for a in angles_rad)
+        self.nx, self.ny = int(nx), int(ny)
+        self.spaxel_kpc = float(spaxel_kpc)
+        self.tel_start, self.tel_step, self.n_tel = float(tel_start), float(tel_step), int(n_tel)
+        self.log_age_nodes = np.asarray(log_age_nodes, dtype=np.float64)
+        self.met_nodes = np.asarray(met_nodes, dtype=np.float64)
+        self.ssp_lam_start, self.ssp_lam_step = float(ssp_lam_start), float(ssp_lam_step)
+        self.ssp_flux = np.asarray(ssp_flux, dtype=np.float64)
+        self.psf_sigma_spx = float(psf_sigma_spx)
+        self.lsf_sigma_A = float(lsf_sigma_A)
+        self.z_sys = float(z_sys)
+        self.flux_scale = float(flux_scale)
+
+    @property
+    def n_spaxels(self):
+        return self.nx * self.ny
+
+    def tel_lambda(self):
+        return self.tel_start + self.tel_step * np.arange(self.n_tel, dtype=np.float64)
+
+    def lsf_sigma_bins(self):
+        return self.lsf_sigma_A / self.tel_step
+
+
+def config_from_workload(w) -> OracleConfig:
+    """Adapter from a synthetic workload description (plain attribute access only)."""
+    s = w.ssp
+    return OracleConfig(w.angles_rad, w.nx, w.ny, w.spaxel_kpc, w.tel_start, w.tel_step, w.n_tel,
+                        s.log_age_nodes, s.met_nodes, s.lam_start, s.lam_step, s.flux,
+                        w.psf_sigma_spx, w.lsf_sigma_A, w.z_sys, w.flux_scale)
+
+
+def _p64(p, name):
+    return np.asarray(getattr(p, name), dtype=np.float64)
+
+
+# --------------------------------------------------------------------------------------------------
+# step 1: orientation (Sec. 3, "orientate the galaxy in the field of view")
+# --------------------------------------------------------------------------------------------------
+def rotation_matrix(phi1: float, phi2: float, phi3: float) -> np.ndarray:
+    """R = Rz(phi3) @ Ry(phi2) @ Rx(phi1), entries written out as the closed-form product.
+
+    cos/sin come from the C math library through Python's `math` module. The closed form fixes
+    the floating-point grouping of each entry, so any other implementation that writes the same
+    products reaches the same doubles.
+    """
+    c1, s1 = math.cos(phi1), math.sin(phi1)
+    c2, s2 = math.cos(phi2), math.sin(phi2)
+    c3, s3 = math.cos(phi3), math.sin(phi3)
+    return np.array([
+        [c3 * c2, (c3 * s2) * s1 - s3 * c1, (c3 * s2) * c1 + s3 * s1],
+        [s3 * c2, (s3 * s2) * s1 + c3 * c1, (s3 * s2) * c1 - c3 * s1],
+        [-s2, c2 * s1, c2 * c1],
+    ], dtype=np.float64)
+
+
+def rotation_matrix_derivs(phi1: float, phi2: float, phi3: float) -> np.ndarray:
+    """dR/dphi_k for k = 0, 1, 2 (array [3, 3, 3]), from the same closed form."""
+    c1, s1 = math.cos(phi1), math.sin(phi1)
+    c2, s2 = math.cos(phi2), math.sin(phi2)
+    c3, s3 = math.cos(phi3), math.sin(phi3)
+    d1 = np.array([
+        [0.0, c3 * s2 * c1 + s3 * s1, -c3 * s2 * s1 + s3 * c1],
+        [0.0, s3 * s2 * c1 - c3 * s1, -s3 * s2 * s1 - c3 * c1],
+        [0.0, c2 * c1, -c2 * s1],
+    ])
+    d2 = np.array([
+        [-c3 * s2, c3 * c2 * s1, c3 * c2 * c1],
+        [-s3 * s2, s3 * c2 * s1, s3 * c2 * c1],
+        [-c2, -s2 * s1, -s2 * c1],
+    ])
+    d3 = np.array([
+        [-s3 * c2, -s3 * s2 * s1 - c3 * c1, -s3 * s2 * c1 + c3 * s1],
+        [c3 * c2, c3 * s2 * s1 - s3 * c1, c3 * s2 * c1 + s3 * s1],
+        [0.0, 0.0, 0.0],
+    ])
+    return np.stack([d1, d2, d3])
+
+
+def rotate_positions(p, R: np.ndarray):
+    """x' = R x in FP64, each component summed left to right without fused multiply-add:
+    x'_a = ((R[a,0] x + R[a,1] y) + R[a,2] z)."""
+    x, y, z = _p64(p, "x"), _p64(p, "y"), _p64(p, "z")
+    xp = R[0, 0] * x + R[0, 1] * y + R[0, 2] * z
+    yp = R[1, 0] * x + R[1, 1] * y + R[1, 2] * z
+    zp = R[2, 0] * x + R[2, 1] * y + R[2, 2] * z
+    return xp, yp, zp
+
+
+def los_velocity(p, R: np.ndarray) -> np.ndarray:
+    """v_los = (R v)_z in km/s (positive = receding)."""
+    vx, vy, vz = _p64(p, "vx"), _p64(p, "vy"), _p64(p, "vz")
+    return R[2, 0] * vx + R[2, 1] * vy + R[2, 2] * vz
+
+
+# --------------------------------------------------------------------------------------------------
+# step 2: spaxel assignment (Sec. 3, "particles are assigned to the IFU spaxels")
+# --------------------------------------------------------------------------------------------------
+def spaxel_keys(xp: np.ndarray, yp: np.ndarray, nx: int, ny: int, spaxel: float) -> np.ndarray:
+    """Nearest-grid-point binning on an nx x ny grid of square spaxels of side `spaxel` centred on
+    the origin. ix = floor(x'/s + nx/2), iy likewise; in the field iff 0 <= ix < nx and
+    0 <= iy < ny (half-open: a particle exactly on the upper border is outside).
+    key = iy*nx + ix for particles in the field, nx*ny (the sentinel) otherwise."""
+    tx = xp / spaxel + nx / 2.0
+    ty = yp / spaxel + ny / 2.0
+    ix = np.floor(tx)
+    iy = np.floor(ty)
+    inside = (ix >= 0) & (ix < nx) & (iy >= 0) & (iy < ny)
+    key = np.full(xp.shape, nx * ny, dtype=np.int64)
+    key[inside] = iy[inside].astype(np.int64) * nx + ix[inside].astype(np.int64)
+    return key
+
+
+def sort_by_key(key: np.ndarray, n_spaxels: int):
+    """perm = stable argsort of the keys (equal keys keep input order, the sentinel sorts last);
+    seg_off[s] = number of particles with key < s, for s = 0..n_spaxels."""
+    perm = np.argsort(key, kind="stable")
+    seg_off = np.searchsorted(key[perm], np.arange(n_spaxels + 1), side="left")
+    return perm.astype(np.int64), seg_off.astype(np.int64)
+
+
+# --------------------------------------------------------------------------------------------------
+# step 3: SSP lookup (Sec. 3, "lookup from a simple stellar population library")
+# --------------------------------------------------------------------------------------------------
+def ssp_cell(u: np.ndarray, nodes: np.ndarray):
+    """Cell index j and fraction t of u on strictly increasing nodes, after clamping u to
+    [nodes[0], nodes[-1]]; j = clamp(searchsorted(nodes, u, 'right') - 1, 0, n-2),
+    t = (u - nodes[j]) / (nodes[j+1] - nodes[j]). Also returns the clamp mask (True = inside)."""
+    n = nodes.shape[0]
+    inside = (u >= nodes[0]) & (u <= nodes[-1])
+    uc = np.clip(u, nodes[0], nodes[-1])
+    j = np.clip(np.searchsorted(nodes, uc, side="right") - 1, 0, n - 2)
+    t = (uc - nodes[j]) / (nodes[j + 1] - nodes[j])
+    return j, t, inside
+
+
+def ssp_weights(age: np.ndarray, met: np.ndarray, log_age_nodes, met_nodes):
+    """Bilinear weights on the (log10 age/Gyr, [M/H]) grid. Corner order:
+    (ja, jz), (ja, jz+1), (ja+1, jz), (ja+1, jz+1). Returns ja, jz, ta, tz, w[n, 4] and masks."""
+    ua = np.log10(np.asarray(age, dtype=np.float64))
+    uz = np.asarray(met, dtype=np.float64)
+    ja, ta, ina = ssp_cell(ua, np.asarray(log_age_nodes, dtype=np.float64))
+    jz, tz, inz = ssp_cell(uz, np.asarray(met_nodes, dtype=np.float64))
+    w = np.stack([(1 - ta) * (1 - tz), (1 - ta) * tz, ta * (1 - tz), ta * tz], axis=-1)
+    return ja, jz, ta, tz, w, ina, inz
+
+
+def interp_templates(flux: np.ndarray, ja, jz, w) -> np.ndarray:
+    """S_i = sum over the 4 corners of w_ic * T[corner_c], shape [n, n_lam_ssp]."""
+    return (w[:, 0:1] * flux[ja, jz] + w[:, 1:2] * flux[ja, jz + 1]
+            + w[:, 2:3] * flux[ja + 1, jz] + w[:, 3:4] * flux[ja + 1, jz + 1])
+
+
+# --------------------------------------------------------------------------------------------------
+# steps 4-5: Doppler shift and resampling (Sec. 3)
+# --------------------------------------------------------------------------------------------------
+def doppler_index(lam_tel: np.ndarray, vlos: np.ndarray, z_sys: float, ssp_start: float,
+                  ssp_step: float) -> np.ndarray:
+    """Fractional SSP node index of the rest-frame wavelength seen at each telescope bin centre:
+    q_ij = (lam_j / ((1+z_sys)(1+beta_i)) - lam0_ssp) / dlam_ssp, shape [n, n_tel]."""
+    beta = np.asarray(vlos, dtype=np.float64) / C_KMS
+    lam_rest = lam_tel[None, :] / ((1.0 + z_sys) * (1.0 + beta[:, None]))
+    return (lam_rest - ssp_start) / ssp_step
+
+
+def resample_linear(S: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Piecewise-linear interpolation of row i of S at fractional node positions q[i, :];
+    zero where q < 0 or q > n-1. The last node maps to (k = n-2, tau = 1)."""
+    n = S.shape[1]
+    valid = (q >= 0.0) & (q <= n - 1)
+    qc = np.where(valid, q, 0.0)
+    k = np.minimum(np.floor(qc).astype(np.int64), n - 2)
+    tau = qc - k
+    s0 = np.take_along_axis(S, k, axis=1)
+    s1 = np.take_along_axis(S, k + 1, axis=1)
+    return np.where(valid, (1.0 - tau) * s0 + tau * s1, 0.0)
+
+
+def particle_spectra(p, idx: np.ndarray, vlos: np.ndarray, cfg: OracleConfig) -> np.ndarray:
+    """Observed spectrum of each particle in `idx` on the telescope grid, shape [len(idx), n_tel]:
+    f_i(lam_j) = flux_scale * m_i * J_i * Slin_i(q_ij), J_i = 1/((1+z_sys)(1+beta_i))."""
+    age = _p64(p, "age")[idx]
+    met = _p64(p, "met")[idx]
+    mass = _p64(p, "mass")[idx]
+    v = vlos[idx]
+    ja, jz, ta, tz, w, _, _ = ssp_weights(age, met, cfg.log_age_nodes, cfg.met_nodes)
+    S = interp_templates(cfg.ssp_flux, ja, jz, w)
+    q = doppler_index(cfg.tel_lambda(), v, cfg.z_sys, cfg.ssp_lam_start, cfg.ssp_lam_step)
+    J = 1.0 / ((1.0 + cfg.z_sys) * (1.0 + v / C_KMS))
+    return (cfg.flux_scale * mass * J)[:, None] * resample_linear(S, q)
+
+
+# --------------------------------------------------------------------------------------------------
+# step 6: spaxel sum (Sec. 3, "the stellar spectra in each spaxel are summed up")
+# --------------------------------------------------------------------------------------------------
+def _cube_rows(args):
+    s_lo, s_hi, chunk = args
+    st = _POOL_STATE
+    p, key, perm, seg_off, vlos, cfg = (st["p"], st["key"], st["perm"], st["seg_off"],
+                                        st["vlos"], st["cfg"])
+    out = np.zeros((s_hi - s_lo, cfg.n_tel))
+    i0, i1 = int(seg_off[s_lo]), int(seg_off[s_hi])
+    for c0 in range(i0, i1, chunk):
+        idx = perm[c0:min(i1, c0 + chunk)]
+        f = particle_spectra(p, idx, vlos, cfg)
+        k = key[idx] - s_lo
+        starts = np.flatnonzero(np.r_[True, k[1:] != k[:-1]])
+        out[k[starts]] += np.add.reduceat(f, starts, axis=0)
+    return s_lo, out
+
+
+_POOL_STATE: Dict = {}
+
+
+def cube_raw(p, key, perm, seg_off, vlos, cfg: OracleConfig, workers: Optional[int] = None,
+             chunk: int = 1024) -> np.ndarray:
+    """C_raw[s, j] = sum over particles with key s of f_i(lam_j), FP64, shape [ny*nx, n_tel].
+
+    Works over spaxel ranges; with workers > 1 the ranges run in forked processes."""
+    n_s = cfg.n_spaxels
+    n_in = int(seg_off[n_s])
+    workers = workers if workers is not None else int(os.environ.get("ORACLE_WORKERS", "1"))
+    _POOL_STATE.update(p=p, key=key, perm=perm, seg_off=seg_off, vlos=vlos, cfg=cfg)
+    # split spaxels into ranges holding roughly equal particle counts
+    n_ranges = max(1, workers * 8) if workers > 1 else 1
+    bounds = np.searchsorted(seg_off, np.linspace(0, n_in, n_ranges + 1), side="left")
+    bounds[0], bounds[-1] = 0, n_s
+    bounds = np.unique(np.clip(bounds, 0, n_s))
+    tasks = [(int(a), int(b), chunk) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    out = np.zeros((n_s, cfg.n_tel))
+    if workers > 1 and len(tasks) > 1:
+        import multiprocessing as mp
+        ctx = mp.get_context("fork")
+        with ctx.Pool(workers) as pool:
+            for s_lo, rows in pool.imap_unordered(_cube_rows, tasks):
+                out[s_lo:s_lo + rows.shape[0]] = rows
+    else:
+        for t in tasks:
+            s_lo, rows = _cube_rows(t)
+            out[s_lo:s_lo + rows.shape[0]] = rows
+    _POOL_STATE.clear()
+    return out
+
+
+# --------------------------------------------------------------------------------------------------
+# step 7: PSF and LSF (Sec. 3 "point-spread function (PSF) and line-spread function (LSF)
+# convolution"; Gaussian per Sec. 4 "Qualitative Analysis")
+# --------------------------------------------------------------------------------------------------
+def gaussian_weights(sigma: float) -> np.ndarray:
+    """Sampled Gaussian exp(-k^2 / (2 sigma^2)) for |k| <= r, r = int(4 sigma + 0.5), normalised
+    to unit sum. sigma = 0 gives the identity kernel [1]."""
+    if sigma <= 0.0:
+        return np.ones(1)
+    r = int(4.0 * sigma + 0.5)
+    k = np.arange(-r, r + 1, dtype=np.float64)
+    w = np.exp(-0.5 * (k / sigma) ** 2)
+    return w / w.sum()
+
+
+def convolve_axis(a: np.ndarray, w: np.ndarray, axis: int) -> np.ndarray:
+    """out[..., i, ...] = sum_k w[k + r] a[..., i + k, ...], zero outside the array."""
+    r = (w.shape[0] - 1) // 2
+    a = np.moveaxis(np.asarray(a, dtype=np.float64), axis, 0)
+    n = a.shape[0]
+    out = np.zeros_like(a)
+    for k in range(-r, r + 1):
+        lo, hi = max(0, -k), min(n, n - k)
+        if hi > lo:
+            out[lo:hi] += w[k + r] * a[lo + k:hi + k]
+    return np.moveaxis(out, 0, axis)
+
+
+def psf_lsf(c_raw: np.ndarray, cfg: OracleConfig) -> np.ndarray:
+    """A C_raw: LSF along lambda (sigma in bins = sigma_A / dlam_tel), then the PSF along y and
+    along x (sigma in spaxels). Input/output shape [ny*nx, n_tel]."""
+    c = c_raw.reshape(cfg.ny, cfg.nx, cfg.n_tel)
+    c = convolve_axis(c, gaussian_weights(cfg.lsf_sigma_bins()), 2)
+    wp = gaussian_weights(cfg.psf_sigma_spx)
+    c = convolve_axis(c, wp, 0)
+    c = convolve_axis(c, wp, 1)
+    return c.reshape(cfg.ny * cfg.nx, cfg.n_tel)
+
+
+# --------------------------------------------------------------------------------------------------
+# whole forward pass
+# --------------------------------------------------------------------------------------------------
+def forward(p, cfg: OracleConfig, workers: Optional[int] = None, frozen_key=None,
+            with_cube=True) -> Dict[str, np.ndarray]:
+    """Run steps 1-7. Returns key, perm, seg_off, vlos (FP64), cube_raw and cube (FP64).
+
+    `frozen_key` replaces the binning result (used when differentiating w.r.t. angles)."""
+    R = rotation_matrix(*cfg.angles_rad)
+    xp, yp, _ = rotate_positions(p, R)
+    vlos = los_velocity(p, R)
+    key = spaxel_keys(xp, yp, cfg.nx, cfg.ny, cfg.spaxel_kpc) if frozen_key is None \
+        else np.asarray(frozen_key, dtype=np.int64)
+    perm, seg_off = sort_by_key(key, cfg.n_spaxels)
+    out = dict(R=R, key=key, perm=perm, seg_off=seg_off, vlos=vlos)
+    if with_cube:
+        c = cube_raw(p, key, perm, seg_off, vlos, cfg, workers=workers)
+        out["cube_raw"] = c
+        out["cube"] = psf_lsf(c, cfg)
+    return out
+
+
+# --------------------------------------------------------------------------------------------------
+# loss and adjoint (gradients through the pipeline: Abstract, Sec. 1)
+# --------------------------------------------------------------------------------------------------
+def loss(cube: np.ndarray, target: np.ndarray) -> float:
+    """L = 0.5 * || A C_raw - T* ||^2 (cube = A C_raw)."""
+    r = np.asarray(cube, dtype=np.float64) - np.asarray(target, dtype=np.float64)
+    return 0.5 * float(np.sum(r * r))
+
+
+def loss_grad_cube(cube: np.ndarray, target: np.ndarray, cfg: OracleConfig) -> np.ndarray:
+    """G = dL/dC_raw = A^T (A C_raw - T*) = A (A C_raw - T*), since A is a symmetric operator."""
+    return psf_lsf(np.asarray(cube, dtype=np.float64) - np.asarray(target, dtype=np.float64), cfg)
+
+
+def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
+            idx: Optional[np.ndarray] = None, chunk: int = 512) -> Dict[str, np.ndarray]:
+    """Analytic gradients of L given G = dL/dC_raw, for particles `idx` (default: all).
+
+    Per particle i in the field (spaxel s), with a_ic = flux_scale m_i J_i w_ic and
+    X_ic = sum_j G[s, j] Tlin_c(q_ij):
+      dL/dm_i      = flux_scale J_i sum_c w_ic X_ic
+      dL/dage_i    = flux_scale m_i J_i sum_c (dw_c/dt_a) X_ic / (du_a) / (age_i ln 10)
+      dL/dmet_i    = flux_scale m_i J_i sum_c (dw_c/dt_z) X_ic / (du_z)
+      dL/dvlos_i   = (1/c) sum_j G[s,j] flux_scale m_i [dJ/dbeta Slin_i(q_ij)
+                                          + J_i Slin_i'(q_ij) dq_ij/dbeta]
+    with Slin' the slope of the linear interpolant on the right-hand cell (one-sided at nodes),
+    zero outside the SSP range, and clamped axes giving zero. Angles use frozen keys:
+      dL/dphi_k = sum_i dL/dvlos_i (dR/dphi_k v_i)_z,   dL/dv_i = dL/dvlos_i R[2, :].
+    Particles outside the field get zero. Positions get no gradient (binning is piecewise
+    constant)."""
+    if fw is None:
+        fw = forward(p, cfg, with_cube=False)
+    R, key, vlos = fw["R"], fw["key"], fw["vlos"]
+    n = key.shape[0]
+    if idx is None:
+        idx = np.arange(n)
+    idx = np.asarray(idx, dtype=np.int64)
+    n_s = cfg.n_spaxels
+    out = {k: np.zeros(idx.shape[0]) for k in ("mass", "age", "met", "vlos")}
+    lam = cfg.tel_lambda()
+    nl = cfg.ssp_flux.shape[2]
+    T = cfg.ssp_flux
+    la_nodes, mz_nodes = cfg.log_age_nodes, cfg.met_nodes
+    inf = key[idx] < n_s
+    for c0 in range(0, idx.shape[0], chunk):
+        sel = np.arange(c0, min(idx.shape[0], c0 + chunk))
+        sel = sel[inf[sel]]
+        if sel.size == 0:
+            continue
+        ii = idx[sel]
+        age, met, mass = _p64(p, "age")[ii], _p64(p, "met")[ii], _p64(p, "mass")[ii]
+        v = vlos[ii]
+        beta = v / C_KMS
+        ja, jz, ta, tz, w, ina, inz = ssp_weights(age, met, la_nodes, mz_nodes)
+        q = doppler_index(lam, v, cfg.z_sys, cfg.ssp_lam_start, cfg.ssp_lam_step)
+        valid = (q >= 0.0) & (q <= nl - 1)
+        qc = np.where(valid, q, 0.0)
+        k = np.minimum(np.floor(qc).astype(np.int64), nl - 2)
+        tau = qc - k
+        g = G[key[ii]]                                   # [m, n_tel]
+        corners = [(ja, jz), (ja, jz + 1), (ja + 1, jz), (ja + 1, jz + 1)]
+        X = np.zeros((ii.shape[0], 4))
+        Sl = np.zeros_like(q)                            # Slin_i(q)
+        dS = np.zeros_like(q)                            # Slin_i'(q) per index unit
+        for c, (a_, z_) in enumerate(corners):
+            row = T[a_, z_]                               # [m, nl]
+            t0 = np.take_along_axis(row, k, axis=1)
+            t1 = np.take_along_axis(row, k + 1, axis=1)
+            tl = np.where(valid, (1.0 - tau) * t0 + tau * t1, 0.0)
+            X[:, c] = np.sum(g * tl, axis=1)
+            Sl += w[:, c:c + 1] * tl
+            dS += w[:, c:c + 1] * np.where(valid, t1 - t0, 0.0)
+        fs = cfg.flux_scale
+        J = 1.0 / ((1.0 + cfg.z_sys) * (1.0 + beta))
+        out["mass"][sel] = fs * J * np.sum(w * X, axis=1)
+        dwa = np.stack([-(1 - tz), -tz, (1 - tz), tz], axis=-1)
+        dwz = np.stack([-(1 - ta), (1 - ta), -ta, ta], axis=-1)
+        du_a = la_nodes[ja + 1] - la_nodes[ja]
+        du_z = mz_nodes[jz + 1] - mz_nodes[jz]
+        d_ua = fs * mass * J * np.sum(dwa * X, axis=1) / du_a
+        d_uz = fs * mass * J * np.sum(dwz * X, axis=1) / du_z
+        out["age"][sel] = np.where(ina, d_ua / (age * math.log(10.0)), 0.0)
+        out["met"][sel] = np.where(inz, d_uz, 0.0)
+        dJ = -J / (1.0 + beta)
+        dq = -lam[None, :] / ((1.0 + cfg.z_sys) * (1.0 + beta[:, None]) ** 2
+                              * cfg.ssp_lam_step)
+        dbeta = fs * mass * np.sum(g * (dJ[:, None] * Sl + J[:, None] * dS * dq), axis=1)
+        out["vlos"][sel] = dbeta / C_KMS
+    dR = rotation_matrix_derivs(*cfg.angles_rad)
+    vx, vy, vz = _p64(p, "vx")[idx], _p64(p, "vy")[idx], _p64(p, "vz")[idx]
+    dv = out["vlos"]
+    out["angles"] = np.array([np.sum(dv * (dR[k, 2, 0] * vx + dR[k, 2, 1] * vy
+                                           + dR[k, 2, 2] * vz)) for k in range(3)])
+    out["vel"] = dv[None, :] * R[2, :, None]
+    return out

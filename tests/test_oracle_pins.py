@@ -1,0 +1,478 @@
+"""Pins of the FP64 oracle against things other than itself: closed forms, library routines
+(numpy, scipy), brute-force loops on tiny inputs, invariants and finite differences.
+
+Every step of the oracle has at least one pin here that a plausible mistake (dropped term, wrong
+sign or index, transposed operand, wrong boundary rule) would fail.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.interpolate
+import scipy.ndimage
+
+import oracle as O
+from oracle import brute
+from paper_2412_08265_amd import synth
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _cfg(nx=8, ny=8, s=1.0, angles=(0.0, 0.0, 0.0), ssp=None, tel=None, psf=0.0, lsf=0.0,
+         z_sys=0.0, flux_scale=1.0):
+    ssp = ssp or synth.make_ssp(6, 4, 4000.0, 2.0, 300)
+    tel = tel or (ssp.lam_start, ssp.lam_step, ssp.n_lam)
+    return O.OracleConfig(angles, nx, ny, s, tel[0], tel[1], tel[2], ssp.log_age_nodes,
+                          ssp.met_nodes, ssp.lam_start, ssp.lam_step, ssp.flux, psf, lsf,
+                          z_sys, flux_scale)
+
+
+def _parts(n, seed=0, r=5.0, vmax=300.0):
+    rng = np.random.default_rng(seed)
+    f = lambda a: np.asarray(a, dtype=np.float32)
+    return synth.Particles(f(rng.uniform(-r, r, n)), f(rng.uniform(-r, r, n)),
+                           f(rng.uniform(-1, 1, n)), f(rng.uniform(-vmax, vmax, n)),
+                           f(rng.uniform(-vmax, vmax, n)), f(rng.uniform(-vmax, vmax, n)),
+                           f(10 ** rng.uniform(4, 6, n)), f(rng.uniform(0.1, 13, n)),
+                           f(rng.uniform(-2, 0.3, n)))
+
+
+# ------------------------------------------------------------------ inputs
+def test_generators_are_seeded_fp32():
+    a = synth.make_galaxy(5000, 7)
+    b = synth.make_galaxy(5000, 7)
+    c = synth.make_galaxy(5000, 8)
+    assert a.digest() == b.digest() and a.digest() != c.digest()
+    assert all(x.dtype == np.float32 for x in a.arrays())
+    assert a.n == 5000
+    # 20 % bulge: the last 1000 particles are the Hernquist sphere (isotropic, no net rotation)
+    assert abs(float(np.mean(a.vy[:4000] * a.x[:4000] - a.vx[:4000] * a.y[:4000]))) > 100.0
+    s = synth.make_ssp(5, 3, 3600.0, 7.615230460921844, 500)
+    assert s.flux.dtype == np.float32 and s.flux.shape == (5, 3, 500)
+    assert np.all(np.diff(s.log_age_nodes) > 0) and np.all(np.diff(s.met_nodes) > 0)
+
+
+# ------------------------------------------------------------------ step 1: rotation
+def _elem(phi1, phi2, phi3):
+    c, s = math.cos, math.sin
+    rx = np.array([[1, 0, 0], [0, c(phi1), -s(phi1)], [0, s(phi1), c(phi1)]])
+    ry = np.array([[c(phi2), 0, s(phi2)], [0, 1, 0], [-s(phi2), 0, c(phi2)]])
+    rz = np.array([[c(phi3), -s(phi3), 0], [s(phi3), c(phi3), 0], [0, 0, 1]])
+    return rz @ ry @ rx
+
+
+@pytest.mark.parametrize("ang", [(0.3, -1.1, 2.0), (math.radians(60), 0, 0), (1.0, 2.0, 3.0)])
+def test_rotation_matches_matrix_product(ang):
+    R = O.rotation_matrix(*ang)
+    np.testing.assert_allclose(R, _elem(*ang), rtol=0, atol=2e-16)
+    np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-15)
+    assert abs(np.linalg.det(R) - 1) < 1e-15
+    np.testing.assert_allclose(R, np.array(brute.rotation(*ang)), atol=2e-16)
+
+
+def test_rotation_order_and_axes():
+    h = math.pi / 2
+    R = O.rotation_matrix(h, 0.0, 0.0)            # inclination tips +y onto the line of sight
+    np.testing.assert_allclose(R @ [0, 1, 0], [0, 0, 1], atol=1e-15)
+    np.testing.assert_allclose(R @ [0, 0, 1], [0, -1, 0], atol=1e-15)
+    R = O.rotation_matrix(h, 0.0, h)              # Rx first, then Rz
+    np.testing.assert_allclose(R @ [1, 0, 0], [0, 1, 0], atol=1e-15)
+    np.testing.assert_allclose(R @ [0, 1, 0], [0, 0, 1], atol=1e-15)
+    np.testing.assert_allclose(O.rotation_matrix(0, 0, 0), np.eye(3), atol=0)
+
+
+def test_rotation_derivatives_fd():
+    ang = np.array([0.7, -0.4, 1.9])
+    dR = O.rotation_matrix_derivs(*ang)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1e-6
+        fd = (O.rotation_matrix(*(ang + e)) - O.rotation_matrix(*(ang - e))) / 2e-6
+        np.testing.assert_allclose(dR[k], fd, atol=1e-9)
+
+
+def test_disk_los_velocity_closed_form():
+    """Zero-dispersion disk: v_los = v_c sin(incl) cos(azimuth), receding positive."""
+    phi = np.linspace(0, 2 * np.pi, 37)
+    f = lambda a: np.asarray(a, dtype=np.float32)
+    n = phi.size
+    vx, vy = -200 * np.sin(phi), 200 * np.cos(phi)
+    p = synth.Particles(f(5 * np.cos(phi)), f(5 * np.sin(phi)), f(np.zeros(n)), f(vx), f(vy),
+                        f(np.zeros(n)), f(np.ones(n)), f(np.ones(n)), f(np.zeros(n)))
+    incl = math.radians(60)
+    v = O.los_velocity(p, O.rotation_matrix(incl, 0, 0))
+    np.testing.assert_allclose(v, math.sin(incl) * np.asarray(f(vy), dtype=np.float64),
+                               rtol=1e-15, atol=1e-12)
+    np.testing.assert_allclose(v, 200 * math.sin(incl) * np.cos(phi), atol=1e-4)
+
+
+def test_rotation_preserves_norm():
+    p = _parts(1000, 3)
+    R = O.rotation_matrix(0.3, 0.2, 0.1)
+    xp, yp, zp = O.rotate_positions(p, R)
+    r0 = np.sqrt(p.x.astype(float) ** 2 + p.y.astype(float) ** 2 + p.z.astype(float) ** 2)
+    np.testing.assert_allclose(np.sqrt(xp ** 2 + yp ** 2 + zp ** 2), r0, rtol=1e-14)
+
+
+# ------------------------------------------------------------------ step 2: spaxel keys, sort
+def test_keys_bruteforce_with_edge_particles():
+    rng = np.random.default_rng(5)
+    nx, ny, s = 7, 5, 0.5
+    edges_x = (np.arange(nx + 1) - nx / 2.0) * s
+    edges_y = (np.arange(ny + 1) - ny / 2.0) * s
+    xs = np.concatenate([rng.uniform(-3, 3, 400), edges_x, np.nextafter(edges_x, -np.inf),
+                         np.nextafter(edges_x, np.inf), rng.choice(edges_x, 100)])
+    ys = np.concatenate([rng.uniform(-2, 2, 400), rng.choice(edges_y, nx + 1),
+                         rng.uniform(-2, 2, 2 * (nx + 1)), rng.choice(edges_y, 100)])
+    key = O.spaxel_keys(xs, ys, nx, ny, s)
+    ref = [brute.spaxel_index(x, y, nx, ny, s) for x, y in zip(xs, ys)]
+    np.testing.assert_array_equal(key, ref)
+
+
+def test_keys_hand_placed():
+    nx = ny = 4
+    s = 0.5
+    pts = {  # (x', y') -> expected key, written from the geometry of a centred 4x4 grid
+        (0.0, 0.0): 2 * 4 + 2,          # origin lies on the lower-left corner of cell (2, 2)
+        (-1.0, -1.0): 0,                # lower-left FoV corner belongs to cell (0, 0)
+        (0.9999, 0.9999): 15,           # just inside the upper-right corner
+        (1.0, 0.0): 16,                 # upper x border is outside (half-open)
+        (0.0, 1.0): 16,
+        (-1.0000001, 0.0): 16,
+        (-0.75, 0.25): 2 * 4 + 0,
+        (0.25, -0.75): 0 * 4 + 2,
+    }
+    xs = np.array([k[0] for k in pts])
+    ys = np.array([k[1] for k in pts])
+    np.testing.assert_array_equal(O.spaxel_keys(xs, ys, nx, ny, s), list(pts.values()))
+
+
+def test_sort_is_stable_and_offsets_count():
+    rng = np.random.default_rng(1)
+    n_s = 30
+    key = rng.integers(0, n_s + 1, 700)           # includes sentinel n_s
+    perm, seg_off = O.sort_by_key(key, n_s)
+    assert list(perm) == brute.stable_sort(list(key))
+    assert list(perm) == sorted(range(700), key=lambda i: key[i])
+    for s in range(n_s + 1):
+        assert seg_off[s] == sum(1 for k in key if k < s)
+
+
+def test_sort_edge_cases():
+    perm, seg_off = O.sort_by_key(np.zeros(0, dtype=np.int64), 4)
+    assert perm.size == 0 and list(seg_off) == [0] * 5
+    perm, seg_off = O.sort_by_key(np.full(5, 4), 4)   # everything outside the field
+    assert list(perm) == [0, 1, 2, 3, 4] and list(seg_off) == [0] * 5
+
+
+# ------------------------------------------------------------------ step 3: SSP lookup
+def test_ssp_on_nodes_is_exact():
+    la = np.array([-1.0, 0.0, 1.0])               # ages 0.1, 1, 10 Gyr
+    mz = np.array([-2.0, -1.0, 0.0, 0.25])
+    flux = np.random.default_rng(0).uniform(0.5, 2, (3, 4, 11))
+    ja, jz, ta, tz, w, _, _ = O.ssp_weights(np.array([1.0, 10.0, 1.0]),
+                                            np.array([-1.0, 0.25, -2.0]), la, mz)
+    S = O.interp_templates(flux, ja, jz, w)
+    np.testing.assert_array_equal(S[0], flux[1, 1])
+    np.testing.assert_array_equal(S[1], flux[2, 3])
+    np.testing.assert_array_equal(S[2], flux[1, 0])
+
+
+def test_ssp_matches_scipy_regular_grid():
+    ssp = synth.make_ssp(9, 4, 4000.0, 2.0, 50)     # asymmetric axes catch a transposition
+    rng = np.random.default_rng(2)
+    age = rng.uniform(0.05, 14.0, 500)              # includes clamped values at both ends
+    met = rng.uniform(-2.3, 0.5, 500)
+    la, mz = ssp.log_age_nodes.astype(float), ssp.met_nodes.astype(float)
+    ja, jz, ta, tz, w, ina, inz = O.ssp_weights(age, met, la, mz)
+    S = O.interp_templates(ssp.flux.astype(float), ja, jz, w)
+    interp = scipy.interpolate.RegularGridInterpolator((la, mz), ssp.flux.astype(float),
+                                                       method="linear")
+    ua = np.clip(np.log10(age), la[0], la[-1])
+    uz = np.clip(met, mz[0], mz[-1])
+    np.testing.assert_allclose(S, interp(np.stack([ua, uz], -1)), rtol=1e-12)
+    np.testing.assert_allclose(w.sum(1), 1.0, rtol=1e-15)
+    assert not ina.all() and not inz.all() and ina.any()
+
+
+# ------------------------------------------------------------------ steps 4-5: Doppler, resample
+def _single(age=3.0, met=-0.5, mass=1.0, vlos=0.0):
+    f = lambda a: np.asarray([a], dtype=np.float32)
+    # particle at the origin, velocity along +z so that v_los = vz at zero angles
+    return synth.Particles(f(0.1), f(0.1), f(0), f(0), f(0), f(vlos), f(mass), f(age), f(met))
+
+
+def test_at_rest_reproduces_template_np_interp():
+    ssp = synth.make_ssp(6, 4, 4000.0, 2.0, 300)
+    cfg = _cfg(ssp=ssp, tel=(4013.3, 1.37, 450))   # other start/step, runs past the SSP end
+    p = _single(mass=3.0)
+    f = O.particle_spectra(p, np.array([0]), np.zeros(1), cfg)[0]
+    ja, jz, ta, tz, w, _, _ = O.ssp_weights(p.age, p.met, cfg.log_age_nodes, cfg.met_nodes)
+    S = O.interp_templates(cfg.ssp_flux, ja, jz, w)[0]
+    ref = 3.0 * np.interp(cfg.tel_lambda(), ssp.lam(), S, left=0.0, right=0.0)
+    np.testing.assert_allclose(f, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    assert f[-1] == 0.0 and f[0] != 0.0
+
+
+def test_identical_grids_at_rest_give_template():
+    ssp = synth.make_ssp(6, 4, 4000.0, 2.0, 300)
+    cfg = _cfg(ssp=ssp)
+    p = _single(mass=2.0)
+    f = O.particle_spectra(p, np.array([0]), np.zeros(1), cfg)[0]
+    ja, jz, ta, tz, w, _, _ = O.ssp_weights(p.age, p.met, cfg.log_age_nodes, cfg.met_nodes)
+    S = O.interp_templates(cfg.ssp_flux, ja, jz, w)[0]
+    np.testing.assert_allclose(f, 2.0 * S, rtol=1e-13)
+
+
+@pytest.mark.parametrize("v", [300.0, -450.0])
+def test_narrow_line_moves_to_redshifted_position(v):
+    ssp = synth.make_line_ssp(5000.0, 0.5, 4000, 6000.0, 0.6)
+    cfg = _cfg(ssp=ssp)
+    p = _single(vlos=v)
+    f = O.particle_spectra(p, np.array([0]), np.array([v]), cfg)[0]
+    lam = cfg.tel_lambda()
+    expect = 6000.0 * (1 + v / O.C_KMS)
+    assert abs(lam[np.argmax(f)] - expect) <= 0.25 + 1e-9
+    # a blueshift moves it the other way
+    assert (lam[np.argmax(f)] - 6000.0) * v > 0
+
+
+def test_line_at_bin_centre_value():
+    """If lam_c (1+beta) is a telescope bin centre, f there = m J S(lam_c)."""
+    ssp = synth.make_line_ssp(5000.0, 0.5, 4000, 6000.0, 3.0)
+    beta = 12.5 / 6000.0                          # shifts 6000 A onto the centre 6012.5 A
+    v = beta * O.C_KMS
+    cfg = _cfg(ssp=ssp)
+    f = O.particle_spectra(_single(mass=2.0), np.array([0]), np.array([v]), cfg)[0]
+    j = int(round((6012.5 - 5000.0) / 0.5))
+    peak = float(ssp.flux[0, 0, int(round((6000.0 - 5000.0) / 0.5))])
+    np.testing.assert_allclose(f[j], 2.0 * peak / (1 + beta), rtol=1e-9)
+
+
+def test_delta_template_gives_triangle():
+    n = 200
+    ssp = synth.make_line_ssp(5000.0, 1.0, n, 5100.0, 1.0)
+    flux = np.zeros_like(ssp.flux)
+    flux[:, :, 100] = 1.0
+    ssp.flux = flux
+    cfg = _cfg(ssp=ssp)
+    v = 400.0
+    f = O.particle_spectra(_single(mass=1.0), np.array([0]), np.array([v]), cfg)[0]
+    beta = v / O.C_KMS
+    q = (cfg.tel_lambda() / (1 + beta) - 5000.0) / 1.0
+    ref = np.maximum(0.0, 1.0 - np.abs(q - 100.0)) / (1 + beta)
+    np.testing.assert_allclose(f, ref, atol=1e-13)
+
+
+def test_flux_conserved_for_shifts_inside_band():
+    """Identical uniform grids, compact line: the samples q_j step by h = 1/(1+beta), and the
+    hat-function weights sum_j Lambda(q_j - n) each node receives equal 1/h except for the one
+    node per 1/|beta| run whose phase lies within |beta| of a sample, which gets up to |beta| more.
+    With the Jacobian J = h this gives |F(v) - F(0)| / F(0) <= 2 |beta| max(S)/sum(S) + 4 beta^2.
+    Dropping J would leave an error of ~|beta| F(0), far outside the bound."""
+    for sig in (1.0, 3.0, 10.0, 50.0):
+        for mu in (5995.3, 6000.0, 6003.71):
+            ssp = synth.make_line_ssp(5000.0, 1.0, 2000, mu, sig)
+            S = ssp.flux[0, 0].astype(np.float64)
+            cfg = _cfg(ssp=ssp)
+            F0 = O.particle_spectra(_single(), np.array([0]), np.zeros(1), cfg).sum()
+            for v in (-600.0, -150.0, 40.0, 150.0, 600.0):
+                F = O.particle_spectra(_single(), np.array([0]), np.array([v]), cfg).sum()
+                beta = v / O.C_KMS
+                bound = 2 * abs(beta) * S.max() / S.sum() + 4 * beta * beta
+                assert abs(F - F0) / F0 <= bound
+                if sig >= 3.0 and abs(v) >= 150.0:             # the Jacobian matters
+                    assert abs(F * (1 + beta) - F0) / F0 > bound
+
+
+def test_out_of_band_is_zero_and_last_node_is_included():
+    ssp = synth.make_ssp(3, 3, 5000.0, 1.0, 10)
+    cfg = _cfg(ssp=ssp, tel=(4995.0, 1.0, 20))
+    S = np.arange(10, dtype=float)[None, :] + 1
+    q = np.array([[-0.5, 0.0, 8.5, 9.0, 9.0000001, 12.0]])
+    out = O.resample_linear(S, q)
+    np.testing.assert_array_equal(out, [[0.0, 1.0, 9.5, 10.0, 0.0, 0.0]])
+
+
+# ------------------------------------------------------------------ step 6: spaxel sum
+def test_cube_matches_bruteforce_loops():
+    ssp = synth.make_ssp(5, 3, 4000.0, 4.0, 60)
+    cfg = _cfg(nx=5, ny=4, s=1.5, angles=(0.9, 0.3, -0.4), ssp=ssp, tel=(4010.5, 3.3, 70))
+    p = _parts(150, 11, r=4.0)
+    fw = O.forward(p, cfg)
+    parts = list(zip(*[a.astype(float).tolist() for a in p.arrays()]))
+    ref = brute.cube(parts, cfg.angles_rad, cfg.nx, cfg.ny, cfg.spaxel_kpc,
+                     cfg.tel_lambda().tolist(), cfg.log_age_nodes.tolist(),
+                     cfg.met_nodes.tolist(), cfg.ssp_flux.tolist(), cfg.ssp_lam_start,
+                     cfg.ssp_lam_step)
+    np.testing.assert_allclose(fw["cube_raw"], np.array(ref), rtol=1e-12,
+                               atol=1e-12 * np.abs(ref).max())
+    assert (fw["key"] < cfg.n_spaxels).sum() > 50 and (fw["key"] == cfg.n_spaxels).sum() > 5
+
+
+def test_cube_reduction_paths_agree():
+    w = synth.tiny_workload()
+    cfg = O.config_from_workload(w)
+    fw = O.forward(w.particles, cfg, workers=1)
+    c2 = O.cube_raw(w.particles, fw["key"], fw["perm"], fw["seg_off"], fw["vlos"], cfg,
+                    workers=3, chunk=37)
+    np.testing.assert_allclose(fw["cube_raw"], c2, rtol=1e-13)
+    # np.add.at over unsorted particles as a third path
+    inside = np.flatnonzero(fw["key"] < cfg.n_spaxels)
+    f = O.particle_spectra(w.particles, inside, fw["vlos"], cfg)
+    c3 = np.zeros_like(c2)
+    np.add.at(c3, fw["key"][inside], f)
+    np.testing.assert_allclose(fw["cube_raw"], c3, rtol=1e-12)
+
+
+def test_cube_is_linear_in_mass():
+    w = synth.tiny_workload()
+    cfg = O.config_from_workload(w)
+    p = w.particles
+    c1 = O.forward(p, cfg)["cube_raw"]
+    c2 = O.forward(p.replace(mass=p.mass.astype(np.float64) * 2), cfg)["cube_raw"]
+    np.testing.assert_array_equal(c2, 2 * c1)
+    # additivity over particles: the cube of a union is the sum of the cubes
+    half = p.n // 2
+    ca = O.forward(p.subset(slice(0, half)), cfg)["cube_raw"]
+    cb = O.forward(p.subset(slice(half, p.n)), cfg)["cube_raw"]
+    np.testing.assert_allclose(ca + cb, c1, rtol=1e-12, atol=1e-12 * np.abs(c1).max())
+
+
+# ------------------------------------------------------------------ step 7: PSF/LSF
+@pytest.mark.parametrize("sig", [1.5, 2.0, 2.5 / 1.2671, 2.7 / 1.25, 0.4])
+def test_gaussian_convolution_matches_scipy(sig):
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=(9, 11, 40))
+    for ax in range(3):
+        ours = O.convolve_axis(a, O.gaussian_weights(sig), ax)
+        ref = scipy.ndimage.gaussian_filter1d(a, sig, axis=ax, mode="constant", cval=0.0,
+                                              truncate=4.0)
+        np.testing.assert_allclose(ours, ref, atol=1e-14)
+    seq = a[3, 4].tolist()
+    np.testing.assert_allclose(O.convolve_axis(a[3, 4], O.gaussian_weights(sig), 0),
+                               brute.gauss_conv_1d(seq, sig), atol=1e-14)
+
+
+def test_psf_lsf_delta_flux_and_adjoint():
+    ssp = synth.make_ssp(3, 3, 5000.0, 1.25, 80)
+    cfg = _cfg(nx=25, ny=21, ssp=ssp, psf=2.0, lsf=2.7)
+    c = np.zeros((cfg.n_spaxels, cfg.n_tel))
+    c[10 * 25 + 12, 40] = 1.0
+    out = O.psf_lsf(c, cfg).reshape(21, 25, 80)
+    wp, wl = O.gaussian_weights(2.0), O.gaussian_weights(2.7 / 1.25)
+    rp, rl = (wp.size - 1) // 2, (wl.size - 1) // 2
+    ref = np.zeros_like(out)
+    ref[10 - rp:10 + rp + 1, 12 - rp:12 + rp + 1, 40 - rl:40 + rl + 1] = \
+        wp[:, None, None] * wp[None, :, None] * wl[None, None, :]
+    np.testing.assert_allclose(out, ref, atol=1e-16)
+    assert abs(out.sum() - 1.0) < 1e-14               # interior content keeps its flux
+    rng = np.random.default_rng(4)
+    x, y = rng.normal(size=c.shape), rng.normal(size=c.shape)
+    assert abs(np.vdot(O.psf_lsf(x, cfg), y) - np.vdot(x, O.psf_lsf(y, cfg))) < 1e-10
+    cid = _cfg(nx=25, ny=21, ssp=ssp)                 # sigma = 0: identity
+    np.testing.assert_array_equal(O.psf_lsf(x, cid), x)
+
+
+# ------------------------------------------------------------------ adjoint
+def _grad_setup(seed=21, n=300):
+    ssp = synth.make_ssp(7, 5, 4000.0, 2.0, 220)
+    cfg = _cfg(nx=9, ny=8, s=1.0, angles=(math.radians(55), 0.2, 0.3), ssp=ssp, psf=1.2,
+               lsf=3.1)
+    p = _parts(n, seed, r=4.5)
+    pt = p.replace(mass=p.mass.astype(float) * 1.1, age=np.minimum(p.age + 0.5, 13.0),
+                   met=p.met + 0.1)
+    cfg_t = _cfg(nx=9, ny=8, s=1.0, angles=(math.radians(60), 0.2, 0.3), ssp=ssp, psf=1.2,
+                 lsf=3.1)
+    target = O.forward(pt, cfg_t)["cube"]
+    fw = O.forward(p, cfg)
+    G = O.loss_grad_cube(fw["cube"], target, cfg)
+    return p, cfg, fw, target, G
+
+
+def _delta_L(cfg, fw, target, key_s, f_plus, f_minus):
+    """L(+) - L(-) when one particle's spectrum changes: <A(d+ - d-), r> + (|Ad+|^2-|Ad-|^2)/2."""
+    r = fw["cube"] - target
+    out = []
+    for d in (f_plus, f_minus):
+        c = np.zeros_like(fw["cube_raw"])
+        c[key_s] = d
+        Ad = O.psf_lsf(c, cfg)
+        out.append(np.vdot(Ad, r) + 0.5 * np.vdot(Ad, Ad))
+    return out[0] - out[1]
+
+
+def test_adjoint_matches_central_differences():
+    p, cfg, fw, target, G = _grad_setup()
+    g = O.adjoint(p, cfg, G, fw)
+    key, vlos = fw["key"], fw["vlos"]
+    rng = np.random.default_rng(0)
+    cand = np.flatnonzero(key < cfg.n_spaxels)
+    checked = 0
+    for i in rng.permutation(cand)[:40]:
+        base = O.particle_spectra(p, np.array([i]), vlos, cfg)[0]
+
+        def spec(**kw):
+            q = p.subset(np.array([i]))
+            vv = np.array([vlos[i]])
+            if "vlos" in kw:
+                vv = np.array([kw.pop("vlos")])
+            q = synth.Particles(*[np.asarray(kw.get(f, getattr(q, f)), dtype=np.float64)
+                                  if f in kw else getattr(q, f).astype(np.float64)
+                                  for f in synth.Particles.FIELDS])
+            return O.particle_spectra(q, np.array([0]), vv, cfg)[0] - base
+
+        m, a, z, v = float(p.mass[i]), float(p.age[i]), float(p.met[i]), float(vlos[i])
+        ua = math.log10(a)
+        la, mz = cfg.log_age_nodes, cfg.met_nodes
+        # stay clear of kinks (nodes, clamps) so the central difference sees one linear piece
+        if np.min(np.abs(la - ua)) < 1e-4 or np.min(np.abs(mz - z)) < 1e-4:
+            continue
+        for name, h, kw_p, kw_m in (
+                ("mass", 1e-6 * m, dict(mass=[m + 1e-6 * m]), dict(mass=[m - 1e-6 * m])),
+                ("age", 1e-6, dict(age=[a + 1e-6]), dict(age=[a - 1e-6])),
+                ("met", 1e-6, dict(met=[z + 1e-6]), dict(met=[z - 1e-6])),
+                ("vlos", 1e-4, dict(vlos=v + 1e-4), dict(vlos=v - 1e-4))):
+            dl = _delta_L(cfg, fw, target, key[i], spec(**kw_p), spec(**kw_m))
+            fd = dl / (2 * h)
+            an = g[name][i]
+            scale = max(abs(fd), 1e-3 * np.abs(g[name]).max())
+            assert abs(an - fd) <= 2e-5 * scale, (name, i, an, fd)
+        checked += 1
+    assert checked >= 25
+
+
+def test_angle_gradient_fd_frozen_keys_and_phi3_zero():
+    p, cfg, fw, target, G = _grad_setup(seed=5, n=200)
+    g = O.adjoint(p, cfg, G, fw)
+    assert g["angles"][2] == 0.0
+    for k in (0, 1):
+        vals = []
+        for sgn in (1, -1):
+            ang = list(cfg.angles_rad)
+            ang[k] += sgn * 1e-6
+            c2 = O.OracleConfig(ang, cfg.nx, cfg.ny, cfg.spaxel_kpc, cfg.tel_start,
+                                cfg.tel_step, cfg.n_tel, cfg.log_age_nodes, cfg.met_nodes,
+                                cfg.ssp_lam_start, cfg.ssp_lam_step, cfg.ssp_flux,
+                                cfg.psf_sigma_spx, cfg.lsf_sigma_A)
+            vals.append(O.loss(O.forward(p, c2, frozen_key=fw["key"])["cube"], target))
+        fd = (vals[0] - vals[1]) / 2e-6
+        assert abs(fd - g["angles"][k]) <= 1e-4 * abs(fd), (k, fd, g["angles"][k])
+
+
+def test_adjoint_identities():
+    p, cfg, fw, target, G = _grad_setup(seed=9, n=250)
+    g = O.adjoint(p, cfg, G, fw)
+    # Euler: the raw cube is homogeneous of degree 1 in the masses
+    lhs = np.sum(p.mass.astype(float) * g["mass"])
+    rhs = np.vdot(G, fw["cube_raw"])
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+    out = fw["key"] == cfg.n_spaxels
+    assert out.any() and np.all(g["mass"][out] == 0) and np.all(g["vlos"][out] == 0)
+    # clamped ages / metallicities get no gradient along the clamped axis
+    q = p.replace(age=np.where(np.arange(p.n) % 3 == 0, 20.0, p.age),
+                  met=np.where(np.arange(p.n) % 4 == 0, -3.0, p.met))
+    gq = O.adjoint(q, cfg, G, fw)
+    assert np.all(gq["age"][np.arange(p.n) % 3 == 0] == 0)
+    assert np.all(gq["met"][np.arange(p.n) % 4 == 0] == 0)
+    np.testing.assert_allclose(g["vel"], g["vlos"][None, :] * fw["R"][2][:, None])
