@@ -1,0 +1,185 @@
+#!/usr/bin/env python
+"""Benchmark of the MI355X datacube forward model.
+
+One step = one pass of the whole forward path over the 1e7-particle workload (80 % exponential
+disk + 20 % Hernquist bulge, 150 x 150 spaxels of 0.2 kpc, 4563 telescope bins of 1.25 A from
+4700 A, SSP 106 x 12 x 4563, PSF sigma 2 spaxels, LSF sigma 2.7 A): rotate + bin + stable sort,
+SSP lookup + Doppler + resampling + spaxel sum, LSF + PSF. Inputs are resident in HBM before the
+timed region. Metric: particle x lambda-bins per second into the cube (in-field particles x bins
+/ step time).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+CUBE_FLOP_PER_UNIT = 16        # 4 SSP corners x 2 resampling taps x 1 multiply-add (2 FLOP)
+ROTBIN_BYTES_PER_PARTICLE = 100  # rotate + key + vlos + two radix passes + offsets (design figure)
+PSF_BYTES_PER_VOXEL = 24       # three 1-D passes, each reads and writes the cube once (FP32)
+
+
+def err(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def source_digest(*names) -> str:
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2412_08265_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(units_kernel: str):
+    """HBM bytes per launch of the cube kernel from the committed counter summary, or None when
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_cube_disk_bulge_1e7_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_digest") != units_kernel:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, n_in_full: int, sample_particles: int):
+    """The FP64 oracle on a seeded random sample of the same galaxy, scaled to the full workload:
+    t = t_particles(sample) * N_in/N_in(sample) + t_psf_lsf(row band) * n_s/rows."""
+    import numpy as np
+    import oracle as O
+    cores = min(os.cpu_count() or 1, 16)
+    cfg = O.config_from_workload(w)
+    rng = np.random.default_rng(12345)
+    idx = np.sort(rng.choice(w.particles.n, sample_particles, replace=False))
+    sub = w.particles.subset(idx)
+    t0 = time.perf_counter()
+    fo = O.forward(sub, cfg, workers=cores, with_cube=False)
+    c = O.cube_raw(sub, fo["key"], fo["perm"], fo["seg_off"], fo["vlos"], cfg, workers=cores)
+    t_part = time.perf_counter() - t0
+    n_in_s = int(fo["seg_off"][-1])
+    # PSF/LSF on a band of 10 y-rows (plus the PSF halo), scaled by rows
+    rows = 10
+    r = int(4 * w.psf_sigma_spx + 0.5)
+    band_cfg = O.OracleConfig(cfg.angles_rad, cfg.nx, rows + 2 * r, cfg.spaxel_kpc,
+                              cfg.tel_start, cfg.tel_step, cfg.n_tel, cfg.log_age_nodes,
+                              cfg.met_nodes, cfg.ssp_lam_start, cfg.ssp_lam_step, cfg.ssp_flux,
+                              cfg.psf_sigma_spx, cfg.lsf_sigma_A)
+    band = c[: (rows + 2 * r) * cfg.nx]
+    t1 = time.perf_counter()
+    O.psf_lsf(band, band_cfg)
+    t_psf = time.perf_counter() - t1
+    t_total = t_part * (n_in_full / max(1, n_in_s)) + t_psf * (cfg.ny / (rows + 2 * r))
+    value = n_in_full * cfg.n_tel / t_total
+    return {"value": value, "unit": "particle*lambda-bins/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{sample_particles} random particles of the same galaxy ({n_in_s} in "
+                       f"field, all {cfg.n_tel} bins, {t_part:.1f} s on {cores} processes) plus "
+                       f"PSF/LSF of a {rows + 2 * r}-row band ({t_psf:.1f} s), scaled to "
+                       f"{n_in_full} in-field particles and {cfg.ny} rows: {t_total:.0f} s "
+                       "for the full step")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=10_000_000, help="particles (default: full 1e7)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=300_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the lambda-sharded "
+              "design is documented, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2412_08265_amd import ops, synth
+
+    err("generating the 1e7-particle workload")
+    w = synth.large_workload(n=args.n)
+    dev = "cuda"
+    gal = ops.DeviceGalaxy.from_host(w.particles, dev)
+    ssp = ops.DeviceSSP.from_grid(w.ssp, dev)
+    obs = ops.Observation.from_workload(w)
+    fw = ops.Forward(gal, obs, ssp, dev)
+    torch.cuda.synchronize()
+    err(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        fw()
+    torch.cuda.synchronize()
+    n_in = int(fw.buf.seg_off[-1].item())
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    err(f"timing {K} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        e = evs[k]
+        e[0].record()
+        fw.rotate_bin()
+        e[1].record()
+        fw.cube_raw()
+        e[2].record()
+        fw.psf_lsf()
+        e[3].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / K
+    st = [sum(evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(K)) / K for i in range(3)]
+    value = n_in * w.n_tel / (ms_step * 1e-3)
+    units = n_in * w.n_tel
+    achieved = CUBE_FLOP_PER_UNIT * units / (st[1] * 1e-3) / 1e12
+    digest = source_digest("k_cube.hip")
+    traffic = traffic_from_profile(digest)
+    rot_gbs = ROTBIN_BYTES_PER_PARTICLE * w.particles.n / (st[0] * 1e-3) / 1e9
+    psf_gbs = PSF_BYTES_PER_VOXEL * w.n_spaxels * w.n_tel / (st[2] * 1e-3) / 1e9
+    out = {
+        "metric": "particle*lambda-bins/sec into cube (1 GPU)",
+        "value": value,
+        "unit": "particle*lambda-bins/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded disk+bulge galaxy and SSP grid)",
+        "config": {"workload": (f"disk+bulge-{w.particles.n:.0e}: {w.particles.n} particles "
+                                f"({n_in} in field), {w.nx}x{w.ny} spaxels of {w.spaxel_kpc} kpc, "
+                                f"{w.n_tel} bins of {w.tel_step} A from {w.tel_start} A, SSP "
+                                f"{w.ssp.n_age}x{w.ssp.n_met}x{w.ssp.n_lam}, PSF {w.psf_sigma_spx} "
+                                f"spx, LSF {w.lsf_sigma_A} A"),
+                   "particles": w.particles.n, "in_field": n_in, "spaxels": w.n_spaxels,
+                   "bins": w.n_tel, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "alu", "kernel": "k_cube (rubix_cube stage)",
+                     "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+                     "flop_per_unit": CUBE_FLOP_PER_UNIT, "units_per_launch": units,
+                     "avg_ms": st[1], "source_digest": digest},
+        "stages_ms": {"rotate_bin": st[0], "cube": st[1], "psf_lsf": st[2]},
+        "stages_hbm": {"rotate_bin_GBs": rot_gbs, "rotate_bin_frac": rot_gbs / PEAK_HBM_GBS,
+                       "psf_lsf_GBs": psf_gbs, "psf_lsf_frac": psf_gbs / PEAK_HBM_GBS},
+    }
+    err(f"step {ms_step:.3f} ms, stages {st}")
+    if not args.no_cpu_baseline:
+        err("cpu baseline (oracle on a sample)")
+        out["cpu_baseline"] = cpu_baseline(w, n_in, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * rubix.h -- C ABI of the MI355X (gfx950) IFU datacube forward model.
+ *
+ * The operations follow the pipeline of arXiv:2412.08265, Sec. 3 ("RUBIX Codebase"): orient the
+ * galaxy, assign particles to spaxels, look up SSP spectra, Doppler-shift them by the line-of-sight
+ * velocity, resample to the telescope wavelength grid, sum per spaxel, convolve with a PSF and an
+ * LSF (Gaussian, Sec. 4 "Qualitative Analysis"); plus the gradient of a cube loss with respect to
+ * the particle properties and viewing angles (Abstract and Sec. 1: gradients through the whole
+ * pipeline). The paper fixes no formula; the conventions taken are stated per entry point.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers marked DEVICE are HIP device pointers owned by the caller; HOST pointers are read
+ *    during the call only. The library allocates nothing and keeps no state between calls.
+ *  - Every call runs asynchronously on `stream` (a hipStream_t; NULL = the null stream) and returns
+ *    once its kernels are enqueued. Device faults surface at the caller's next synchronisation.
+ *  - Every call takes an array of `n_jobs` job descriptors (1 <= n_jobs <= RUBIX_MAX_JOBS) and
+ *    processes all of them in the same launches; a single galaxy is a batch of one. Each job's
+ *    results depend only on that job's inputs (bitwise identical alone or in a batch).
+ *  - `ws` is a caller-owned DEVICE workspace of at least rubix_workspace_size() bytes, 256-byte
+ *    aligned. Its contents need not survive between calls. Concurrent calls need distinct
+ *    workspaces.
+ *  - Return value: RUBIX_OK (0) or a negative status; rubix_last_error() then returns a message
+ *    (thread-local, valid until the next call on the same thread). Host-visible arguments are
+ *    validated before any launch; device data is not inspected (NaN in gives NaN out).
+ *  - Sizes: particle counts up to 2^31-1 per job; int32 spaxel keys and offsets.
+ */
+#ifndef RUBIX_H
+#define RUBIX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RUBIX_OK          0
+#define RUBIX_EINVAL     -1   /* bad argument (null pointer, bad size, non-increasing nodes ...) */
+#define RUBIX_EWORKSPACE -2   /* workspace missing, misaligned or too small                      */
+#define RUBIX_EDEVICE    -3   /* a HIP call failed; the message carries hipGetErrorString        */
+#define RUBIX_ERANGE     -4   /* a size exceeds what the library supports                        */
+
+#define RUBIX_MAX_JOBS       64
+#define RUBIX_MAX_AGE_NODES  256
+#define RUBIX_MAX_MET_NODES  64
+#define RUBIX_MAX_RADIUS     64   /* PSF/LSF kernel radius int(4 sigma + 0.5) must not exceed it */
+
+/* Square spaxels of side `spaxel_kpc` on an nx x ny grid centred on the origin of the rotated
+ * frame; spaxel (ix, iy) has key iy*nx + ix; particles outside the grid get key nx*ny. */
+typedef struct {
+  int32_t nx, ny;
+  double  spaxel_kpc;
+} rubix_grid;
+
+/* Uniform wavelength grid: value k is start + k*step [Angstrom], k = 0..n-1, step > 0. */
+typedef struct {
+  double  start;
+  double  step;
+  int32_t n;
+} rubix_lgrid;
+
+/* SSP template library (the paper's "simple stellar population (SSP) library", Sec. 3).
+ * flux[ia][iz][k]: template of age node ia and metallicity node iz at wavelength node k, FP32,
+ * wavelength contiguous. Age nodes are log10(age / Gyr); metallicity nodes are [M/H] in dex; both
+ * strictly increasing, n_age, n_met >= 2. lam.n >= 2. */
+typedef struct {
+  int32_t      n_age, n_met;
+  const float *log_age_nodes;   /* HOST  [n_age] */
+  const float *met_nodes;       /* HOST  [n_met] */
+  rubix_lgrid  lam;
+  const float *flux;            /* DEVICE [n_age][n_met][lam.n] */
+} rubix_ssp;
+
+/* Star particles, structure of arrays, FP32, all DEVICE [n]. */
+typedef struct {
+  int64_t      n;
+  const float *x, *y, *z;       /* kpc */
+  const float *vx, *vy, *vz;    /* km/s */
+  const float *mass;            /* Msun */
+  const float *age;             /* Gyr, > 0 */
+  const float *met;             /* [M/H] = log10(Z/Zsun), dex */
+} rubix_particles;
+
+/* One galaxy observation. Outputs are DEVICE buffers owned by the caller; a call writes only the
+ * outputs it documents and reads the ones an earlier call produced. */
+typedef struct {
+  rubix_particles p;
+  double      angles_rad[3];    /* phi1 about x (inclination), phi2 about y, phi3 about z      */
+  rubix_grid  grid;
+  rubix_lgrid tel;              /* telescope bin centres, tel.n >= 1                            */
+  double      z_sys;            /* systemic redshift (> -1); 0 for a galaxy at rest            */
+  double      flux_scale;       /* overall flux factor (e.g. distance dimming); 1 by default   */
+  double      psf_sigma_spx;    /* Gaussian PSF sigma in spaxels; 0 = none                     */
+  double      lsf_sigma_A;      /* Gaussian LSF sigma in Angstrom; 0 = none                    */
+  int32_t    *key;              /* [n]           written by rubix_rotate_bin                   */
+  int32_t    *perm;             /* [n]           written by rubix_rotate_bin                   */
+  int32_t    *seg_off;          /* [nx*ny + 1]   written by rubix_rotate_bin                   */
+  float      *vlos;             /* [n]           written by rubix_rotate_bin                   */
+  float      *cube_raw;         /* [ny][nx][tel.n] written by rubix_cube                       */
+  float      *cube;             /* [ny][nx][tel.n] optional; rubix_psf_lsf may write it        */
+} rubix_job;
+
+/* Bytes of workspace that every entry point below needs for these jobs (the maximum over all
+ * entry points, so one workspace serves a whole forward + backward sequence).
+ * Returns RUBIX_OK and sets *bytes, or an error for invalid jobs / SSP. */
+int rubix_workspace_size(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
+                         size_t *bytes);
+
+/* Steps 1-2 of Sec. 3: orientation and spaxel assignment.
+ *  - R = Rz(phi3) Ry(phi2) Rx(phi1) (column vectors), entries from the C library's cos/sin;
+ *    x' = ((R00 x + R01 y) + R02 z), y' likewise, in FP64 without fused multiply-add.
+ *  - key[i] = iy*nx + ix with ix = floor(x'/s + nx/2), iy = floor(y'/s + ny/2) when
+ *    0 <= ix < nx and 0 <= iy < ny (half-open cells), else nx*ny.
+ *  - vlos[i] = ((R20 vx + R21 vy) + R22 vz) in FP64, rounded to FP32; positive = receding.
+ *  - perm = stable ascending sort of the indices by key (equal keys keep input order; the
+ *    out-of-field sentinel sorts last); seg_off[s] = number of particles with key < s,
+ *    s = 0..nx*ny, so spaxel s owns sorted positions [seg_off[s], seg_off[s+1]).
+ * key, perm, seg_off are exact integers (bit-reproducible). */
+int rubix_rotate_bin(const rubix_job *jobs, int n_jobs, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Steps 3-6 of Sec. 3: SSP lookup, Doppler shift, resampling, spaxel sum. Reads perm, seg_off
+ * and vlos from rubix_rotate_bin and writes cube_raw (every voxel; empty spaxels get 0).
+ *  - SSP lookup: bilinear in (u_a = log10(age/Gyr), u_z = [M/H]), clamped to the node range.
+ *    The age cell is chosen by comparing age with the node ages 10^node (FP64); the fraction in
+ *    the cell is linear in u_a. The metallicity cell compares [M/H] with the nodes directly.
+ *  - Doppler + resampling: f_i(lam_j) = flux_scale m_i J_i Slin_i(q_ij) with
+ *    q_ij = (lam_j / ((1+z_sys)(1+beta_i)) - lam0_ssp) / dlam_ssp, beta_i = vlos_i / c,
+ *    J_i = 1/((1+z_sys)(1+beta_i)) (flux-density Jacobian), Slin the linear interpolant of the
+ *    bilinear SSP spectrum between wavelength nodes, 0 for q < 0 or q > n-1.
+ *  - cube_raw[s][j] = sum of f_i(lam_j) over the particles of spaxel s, FP32, accumulated per
+ *    work item in a fixed order (deterministic; independent of the other jobs in the batch). */
+int rubix_cube(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, void *ws,
+               size_t ws_bytes, void *stream);
+
+/* Step 7 of Sec. 3: LSF then PSF, out[j] = A in[j] for each job j (in[j], out[j] DEVICE cubes of
+ * that job's shape, not overlapping). Separable sampled Gaussians exp(-k^2/(2 sigma^2)),
+ * |k| <= int(4 sigma + 0.5), normalised to unit sum, zero padding outside the cube: along lambda
+ * with sigma = lsf_sigma_A / tel.step bins, then along y and along x with sigma = psf_sigma_spx.
+ * sigma = 0 skips that axis. The operator is symmetric, so the same call applies its adjoint. */
+int rubix_psf_lsf(const rubix_job *jobs, int n_jobs, const float *const *in, float *const *out,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of rubix_cube (gradients through the pipeline, Abstract / Sec. 1). Given
+ * grad_raw[j] = dL/dcube_raw (DEVICE, cube shape), writes per particle, in input order:
+ *   d_mass, d_age (per Gyr), d_met (per dex), d_vlos (per km/s)   DEVICE [n] each;
+ *   d_vel  (optional, may be NULL)  DEVICE [3][n], dL/dv = d_vlos * R[2][:] (SoA x, y, z);
+ *   d_angles DEVICE double [3 * n_jobs], dL/dphi_k = sum_i d_vlos_i (dR/dphi_k v_i)_z with the
+ *   spaxel assignment held fixed (binning is piecewise constant).
+ * Particles outside the field get 0. Derivatives at SSP nodes / wavelength nodes take the
+ * right-hand cell; clamped age or metallicity gives 0 along that axis. Positions get no gradient.
+ * Reads key, perm, seg_off, vlos from rubix_rotate_bin. Per-particle dot products are reduced in
+ * FP64 in a fixed order (deterministic). */
+int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
+                        const float *const *grad_raw, float *const *d_mass,
+                        float *const *d_age, float *const *d_met, float *const *d_vlos,
+                        float *const *d_vel, double *d_angles, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* Message for the last non-zero status returned on this thread ("" if none). */
+const char *rubix_last_error(void);
+
+/* Version string of the library build. */
+const char *rubix_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RUBIX_H */

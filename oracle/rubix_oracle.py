@@ -176,24 +176,36 @@ def sort_by_key(key: np.ndarray, n_spaxels: int):
 # --------------------------------------------------------------------------------------------------
 # step 3: SSP lookup (Sec. 3, "lookup from a simple stellar population library")
 # --------------------------------------------------------------------------------------------------
-def ssp_cell(u: np.ndarray, nodes: np.ndarray):
-    """Cell index j and fraction t of u on strictly increasing nodes, after clamping u to
-    [nodes[0], nodes[-1]]; j = clamp(searchsorted(nodes, u, 'right') - 1, 0, n-2),
-    t = (u - nodes[j]) / (nodes[j+1] - nodes[j]). Also returns the clamp mask (True = inside)."""
+def ssp_cell(u: np.ndarray, nodes: np.ndarray, x: Optional[np.ndarray] = None,
+             thr: Optional[np.ndarray] = None):
+    """Cell index j and fraction t of u on strictly increasing nodes, clamped to the node range.
+
+    The cell is decided by comparing x with thresholds thr (by default x = u, thr = nodes):
+    j = largest k in [0, n-2] with thr[k] <= x; x <= thr[0] gives (j=0, t=0) and x >= thr[-1]
+    gives (j=n-2, t=1). Inside the range t = (u - nodes[j]) / (nodes[j+1] - nodes[j]), clipped to
+    [0, 1]. Also returns the mask of values inside [thr[0], thr[-1]] (not clamped)."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    x = u if x is None else x
+    thr = nodes if thr is None else np.asarray(thr, dtype=np.float64)
     n = nodes.shape[0]
-    inside = (u >= nodes[0]) & (u <= nodes[-1])
-    uc = np.clip(u, nodes[0], nodes[-1])
-    j = np.clip(np.searchsorted(nodes, uc, side="right") - 1, 0, n - 2)
-    t = (uc - nodes[j]) / (nodes[j + 1] - nodes[j])
+    j = np.clip(np.searchsorted(thr, x, side="right") - 1, 0, n - 2)
+    t = np.clip((u - nodes[j]) / (nodes[j + 1] - nodes[j]), 0.0, 1.0)
+    t = np.where(x <= thr[0], 0.0, np.where(x >= thr[-1], 1.0, t))
+    inside = (x >= thr[0]) & (x <= thr[-1])
     return j, t, inside
 
 
 def ssp_weights(age: np.ndarray, met: np.ndarray, log_age_nodes, met_nodes):
     """Bilinear weights on the (log10 age/Gyr, [M/H]) grid. Corner order:
-    (ja, jz), (ja, jz+1), (ja+1, jz), (ja+1, jz+1). Returns ja, jz, ta, tz, w[n, 4] and masks."""
-    ua = np.log10(np.asarray(age, dtype=np.float64))
+    (ja, jz), (ja, jz+1), (ja+1, jz), (ja+1, jz+1). Returns ja, jz, ta, tz, w[n, 4] and masks.
+
+    The age cell is found by comparing the age with the node ages 10^node (FP64), the fraction
+    is linear in log10(age); the [M/H] cell compares [M/H] with its nodes directly."""
+    age = np.asarray(age, dtype=np.float64)
+    la = np.asarray(log_age_nodes, dtype=np.float64)
+    ua = np.log10(age)
     uz = np.asarray(met, dtype=np.float64)
-    ja, ta, ina = ssp_cell(ua, np.asarray(log_age_nodes, dtype=np.float64))
+    ja, ta, ina = ssp_cell(ua, la, x=age, thr=10.0 ** la)
     jz, tz, inz = ssp_cell(uz, np.asarray(met_nodes, dtype=np.float64))
     w = np.stack([(1 - ta) * (1 - tz), (1 - ta) * tz, ta * (1 - tz), ta * tz], axis=-1)
     return ja, jz, ta, tz, w, ina, inz
@@ -372,7 +384,8 @@ def loss_grad_cube(cube: np.ndarray, target: np.ndarray, cfg: OracleConfig) -> n
 
 
 def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
-            idx: Optional[np.ndarray] = None, chunk: int = 512) -> Dict[str, np.ndarray]:
+            idx: Optional[np.ndarray] = None, chunk: int = 512,
+            workers: int = 1) -> Dict[str, np.ndarray]:
     """Analytic gradients of L given G = dL/dC_raw, for particles `idx` (default: all).
 
     Per particle i in the field (spaxel s), with a_ic = flux_scale m_i J_i w_ic and
@@ -394,6 +407,16 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
     if idx is None:
         idx = np.arange(n)
     idx = np.asarray(idx, dtype=np.int64)
+    if workers > 1 and idx.shape[0] > 4 * chunk:
+        # the per-particle gradients are independent: evaluate index ranges in forked processes
+        import multiprocessing as mp
+        parts = np.array_split(idx, workers * 4)
+        _POOL_STATE.update(adj=(p, cfg, G, fw, chunk))
+        with mp.get_context("fork").Pool(workers) as pool:
+            res = pool.map(_adjoint_part, parts)
+        _POOL_STATE.clear()
+        out = {k: np.concatenate([r[k] for r in res]) for k in ("mass", "age", "met", "vlos")}
+        return _adjoint_angles(p, cfg, R, idx, out)
     n_s = cfg.n_spaxels
     out = {k: np.zeros(idx.shape[0]) for k in ("mass", "age", "met", "vlos")}
     lam = cfg.tel_lambda()
@@ -445,6 +468,16 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
                               * cfg.ssp_lam_step)
         dbeta = fs * mass * np.sum(g * (dJ[:, None] * Sl + J[:, None] * dS * dq), axis=1)
         out["vlos"][sel] = dbeta / C_KMS
+    return _adjoint_angles(p, cfg, R, idx, out)
+
+
+def _adjoint_part(part):
+    p, cfg, G, fw, chunk = _POOL_STATE["adj"]
+    return adjoint(p, cfg, G, fw, idx=part, chunk=chunk, workers=1)
+
+
+def _adjoint_angles(p, cfg, R, idx, out):
+    """dL/dphi_k = sum_i dL/dvlos_i (dR/dphi_k v_i)_z and dL/dv_i = dL/dvlos_i R[2, :]."""
     dR = rotation_matrix_derivs(*cfg.angles_rad)
     vx, vy, vz = _p64(p, "vx")[idx], _p64(p, "vy")[idx], _p64(p, "vz")[idx]
     dv = out["vlos"]

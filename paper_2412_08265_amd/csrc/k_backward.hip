@@ -1,0 +1,237 @@
+// Adjoint of the cube (gradients through the pipeline: arXiv:2412.08265, Abstract and Sec. 1).
+//
+// Given G = dL/dC_raw, each in-field particle i of spaxel s needs five dot products over the
+// telescope bins j of its spaxel's gradient row:
+//   X_c = sum_j G[s,j] Tlin_c(q_ij)                  (c = the 4 SSP corners)
+//   Y   = sum_j G[s,j] lam_j sum_c w_c dT_c(q_ij)    (dT_c = right-cell slope per node)
+// from which the per-particle gradients follow in closed form (k_bwd_final).
+//
+// Layout: one wave per particle; its 64 lanes stride over the bins, accumulate FP32 partials
+// (at most n_tel/64 terms each) and reduce across the wave in FP64. Consecutive particles of a
+// work item mostly share a spaxel, so the G row stays in L1/L2. The rest is a per-particle
+// streaming pass and an FP64 tree over particles for the angle gradient, both in fixed order.
+#include "rubix_internal.h"
+
+namespace rubix {
+
+constexpr double kCkmsB = 299792.458;
+
+hipError_t launch_prep_backward(const Table *dt, const TableHeader &h, int cap, hipStream_t s);
+
+__global__ __launch_bounds__(256) void k_bintab(const Table *__restrict__ T) {
+  const SspDev &S = T->h.ssp;
+  const JobDev *jobs = table_jobs(T);
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_BINTAB]; vb += gridDim.x) {
+    const int jj = find_job(T, K_BINTAB, vb);
+    const JobDev &J = jobs[jj];
+    const int jb = (int)((vb - J.vb_start[K_BINTAB]) * 256 + threadIdx.x);
+    if (jb >= J.n_tel) continue;
+    const double lam = J.tel_start + (double)jb * J.tel_step;
+    const double Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
+    const double Qfl = floor(Q);
+    const int qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
+    J.bintab[jb] = make_float4(__int_as_float(qi), (float)(Q - Qfl), (float)lam, 0.f);
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
+  const SspDev &S = T->h.ssp;
+  const JobDev *jobs = table_jobs(T);
+  const float *__restrict__ flux = S.flux;
+  const int nl = S.n_lam;
+  const int o1 = nl, o2 = S.n_met * nl, o3 = o2 + nl;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_BWD]; vb += gridDim.x) {
+    const int jj = find_job(T, K_BWD, vb);
+    const JobDev &J = jobs[jj];
+    const int64_t pbase = (vb - J.vb_start[K_BWD]) * kBwdParticles;
+    const int n_in = J.seg_off[J.n_s];
+    for (int q = w; q < kBwdParticles; q += 4) {
+      const int64_t p = pbase + q;
+      if (p >= n_in) break;
+      const PrepRec r = J.prep[p];
+      const float *__restrict__ G = J.grad_raw + (int64_t)r.spaxel * J.n_tel;
+      float x0 = 0.f, x1 = 0.f, x2 = 0.f, x3 = 0.f, y = 0.f;
+      for (int jb = lane; jb < J.n_tel; jb += 64) {
+        const float4 bt = J.bintab[jb];
+        const float tq = fmaf(-bt.z, r.g, bt.y);
+        const float fl = floorf(tq);
+        const float tau = tq - fl;
+        const int k = __float_as_int(bt.x) + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
+        const bool ok = (k >= 0) && ((k < nl - 1) || (k == nl - 1 && tau == 0.f));
+        if (ok) {
+          const int kk = min(k, nl - 2);
+          const float tt = (k > kk) ? 1.f : tau;
+          const float *b = flux + r.row + kk;
+          const float g = G[jb];
+          const float d0 = b[1] - b[0], d1 = b[o1 + 1] - b[o1];
+          const float d2 = b[o2 + 1] - b[o2], d3 = b[o3 + 1] - b[o3];
+          x0 = fmaf(g, fmaf(tt, d0, b[0]), x0);
+          x1 = fmaf(g, fmaf(tt, d1, b[o1]), x1);
+          x2 = fmaf(g, fmaf(tt, d2, b[o2]), x2);
+          x3 = fmaf(g, fmaf(tt, d3, b[o3]), x3);
+          const float sp = r.a[0] * d0 + r.a[1] * d1 + r.a[2] * d2 + r.a[3] * d3;
+          y = fmaf(g * bt.z, sp, y);
+        }
+      }
+      const double X0 = wave_sum(x0), X1 = wave_sum(x1), X2 = wave_sum(x2), X3 = wave_sum(x3);
+      const double Y = wave_sum(y);
+      if (lane == 0) {
+        double *d = J.dots + p * 5;
+        d[0] = X0; d[1] = X1; d[2] = X2; d[3] = X3; d[4] = Y;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int cell_of_b(const double *thr, int n, double x) {
+  if (!(x > thr[0])) return 0;
+  if (x >= thr[n - 1]) return n - 2;
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (thr[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_bwd_final(const Table *__restrict__ T) {
+  __shared__ double red[3][kFinThreads];
+  const SspDev &S = T->h.ssp;
+  const JobDev *jobs = table_jobs(T);
+  const int t = threadIdx.x;
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_FIN]; vb += gridDim.x) {
+    const int jj = find_job(T, K_FIN, vb);
+    const JobDev &J = jobs[jj];
+    const int64_t blk = vb - J.vb_start[K_FIN];
+    const int64_t i = blk * kFinThreads + t;
+    const int n_in = J.seg_off[J.n_s];
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+    if (i < J.n) {
+      const int j = J.perm[i];
+      float gm = 0.f, ga = 0.f, gz = 0.f, gv = 0.f;
+      if (i < n_in) {
+        const double age = J.age[j], m = J.mass[j], met = J.met[j], v = J.vlos[j];
+        const int na = S.n_age, nz = S.n_met;
+        const bool in_a = (age >= S.age_thr[0]) && (age <= S.age_thr[na - 1]);
+        const bool in_z = (met >= S.met[0]) && (met <= S.met[nz - 1]);
+        const int ja = cell_of_b(S.age_thr, na, age);
+        const int jz = cell_of_b(S.met, nz, met);
+        double ta, tz;
+        if (!(age > S.age_thr[0])) ta = 0.0;
+        else if (age >= S.age_thr[na - 1]) ta = 1.0;
+        else ta = fmin(1.0, fmax(0.0, (log10(age) - S.log_age[ja]) /
+                                          (S.log_age[ja + 1] - S.log_age[ja])));
+        if (!(met > S.met[0])) tz = 0.0;
+        else if (met >= S.met[nz - 1]) tz = 1.0;
+        else tz = fmin(1.0, fmax(0.0, (met - S.met[jz]) / (S.met[jz + 1] - S.met[jz])));
+        const double *X = J.dots + i * 5;
+        const double x0 = X[0], x1 = X[1], x2 = X[2], x3 = X[3], Y = X[4];
+        const double w0 = (1 - ta) * (1 - tz), w1 = (1 - ta) * tz, w2 = ta * (1 - tz), w3 = ta * tz;
+        const double wx = w0 * x0 + w1 * x1 + w2 * x2 + w3 * x3;
+        const double beta = v / kCkmsB;
+        const double opz = 1.0 + J.z_sys;
+        const double jac = 1.0 / (opz * (1.0 + beta));
+        const double fs = J.flux_scale;
+        const double A = fs * m * jac;
+        gm = (float)(fs * jac * wx);
+        if (in_a) {
+          const double dwa = -(1 - tz) * x0 - tz * x1 + (1 - tz) * x2 + tz * x3;
+          ga = (float)(A * dwa / (S.log_age[ja + 1] - S.log_age[ja]) / (age * 2.302585092994046));
+        }
+        if (in_z) {
+          const double dwz = -(1 - ta) * x0 + (1 - ta) * x1 - ta * x2 + ta * x3;
+          gz = (float)(A * dwz / (S.met[jz + 1] - S.met[jz]));
+        }
+        const double dJ = -jac / (1.0 + beta);
+        const double dq = -1.0 / (opz * (1.0 + beta) * (1.0 + beta) * S.lam_step);
+        const double dbeta = fs * m * (dJ * wx + jac * dq * Y);
+        const double dv = dbeta / kCkmsB;
+        gv = (float)dv;
+        const double vx = J.vx[j], vy = J.vy[j], vz = J.vz[j];
+        c0 = dv * (J.dR2[0] * vx + J.dR2[1] * vy + J.dR2[2] * vz);
+        c1 = dv * (J.dR2[3] * vx + J.dR2[4] * vy + J.dR2[5] * vz);
+        c2 = dv * (J.dR2[6] * vx + J.dR2[7] * vy + J.dR2[8] * vz);
+      }
+      J.d_mass[j] = gm;
+      J.d_age[j] = ga;
+      J.d_met[j] = gz;
+      J.d_vlos[j] = gv;
+      if (J.d_vel) {
+        J.d_vel[j] = (float)((double)gv * J.R[6]);
+        J.d_vel[(int64_t)J.n + j] = (float)((double)gv * J.R[7]);
+        J.d_vel[2 * (int64_t)J.n + j] = (float)((double)gv * J.R[8]);
+      }
+    }
+    red[0][t] = c0; red[1][t] = c1; red[2][t] = c2;
+    __syncthreads();
+    for (int off = kFinThreads / 2; off > 0; off >>= 1) {
+      if (t < off) {
+        red[0][t] += red[0][t + off];
+        red[1][t] += red[1][t + off];
+        red[2][t] += red[2][t + off];
+      }
+      __syncthreads();
+    }
+    if (t < 3) J.ang_part[blk * 3 + t] = red[t][0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bwd_angles(const Table *__restrict__ T) {
+  __shared__ double red[3][256];
+  const JobDev *jobs = table_jobs(T);
+  const int t = threadIdx.x;
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_ANG]; vb += gridDim.x) {
+    const int jj = find_job(T, K_ANG, vb);
+    const JobDev &J = jobs[jj];
+    const int nb = J.n_fin_blocks;
+    const int per = (nb + 255) / 256;
+    const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int b = b0; b < b1; ++b) {
+      a0 += J.ang_part[b * 3 + 0];
+      a1 += J.ang_part[b * 3 + 1];
+      a2 += J.ang_part[b * 3 + 2];
+    }
+    red[0][t] = a0; red[1][t] = a1; red[2][t] = a2;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (t < off) {
+        red[0][t] += red[0][t + off];
+        red[1][t] += red[1][t + off];
+        red[2][t] += red[2][t + off];
+      }
+      __syncthreads();
+    }
+    if (t < 3) J.d_angles[t] = red[t][0];
+    __syncthreads();
+  }
+}
+
+static inline int grid_for(int64_t total, int cap) {
+  if (total <= 0) return 0;
+  int64_t g = total;
+  if (cap > 0 && g > cap) g = cap;
+  if (g > 0x7fffffff) g = 0x7fffffff;
+  return (int)g;
+}
+
+hipError_t launch_backward(const Table *dt, const TableHeader &h, int cap, hipStream_t s) {
+  hipError_t e = launch_prep_backward(dt, h, cap, s);
+  if (e != hipSuccess) return e;
+  int g;
+  if ((g = grid_for(h.total[K_BINTAB], cap))) hipLaunchKernelGGL(k_bintab, dim3(g), dim3(256), 0, s, dt);
+  if ((g = grid_for(h.total[K_BWD], cap))) hipLaunchKernelGGL(k_bwd_dots, dim3(g), dim3(256), 0, s, dt);
+  if ((g = grid_for(h.total[K_FIN], cap))) hipLaunchKernelGGL(k_bwd_final, dim3(g), dim3(kFinThreads), 0, s, dt);
+  if ((g = grid_for(h.total[K_ANG], cap))) hipLaunchKernelGGL(k_bwd_angles, dim3(g), dim3(256), 0, s, dt);
+  return hipGetLastError();
+}
+
+}  // namespace rubix

@@ -1,0 +1,480 @@
+// Host side of the C ABI declared in include/rubix.h: argument validation, workspace layout, the
+// device job table and the launch sequences. No allocation, no host<->device copies of data; the
+// job table reaches the device through kernel arguments (k_upload), so a call can be captured in
+// a HIP graph as is.
+#include <math.h>
+#include <stdarg.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "rubix_internal.h"
+
+namespace rubix {
+
+hipError_t launch_prep_backward(const Table *dt, const TableHeader &h, int cap, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+// ---------------------------------------------------------------------------------------------
+// upload of the job table through kernel arguments
+// ---------------------------------------------------------------------------------------------
+struct UploadChunk {
+  uint32_t offset_words, n_words;
+  uint32_t w[880];
+};
+
+__global__ void k_upload(UploadChunk c, uint32_t *dst) {
+  for (uint32_t i = threadIdx.x; i < c.n_words; i += blockDim.x) dst[c.offset_words + i] = c.w[i];
+}
+
+hipError_t launch_upload(const void *host_table, size_t bytes, void *dev_table, hipStream_t s) {
+  const uint32_t *src = static_cast<const uint32_t *>(host_table);
+  const size_t words = (bytes + 3) / 4;
+  UploadChunk c;
+  for (size_t off = 0; off < words; off += 880) {
+    c.offset_words = (uint32_t)off;
+    c.n_words = (uint32_t)std::min<size_t>(880, words - off);
+    memcpy(c.w, src + off, c.n_words * 4);
+    hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, c, static_cast<uint32_t *>(dev_table));
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// sizes and layout
+// ---------------------------------------------------------------------------------------------
+static inline size_t al(size_t b) { return (b + 255) & ~size_t(255); }
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+enum Call { CALL_ROTATE, CALL_CUBE, CALL_PSF, CALL_BWD, CALL_SIZE, CALL_PACK };
+
+struct JobSizes {
+  int64_t n, n_s, n_tel, cube_elems;
+  int passes, n_sort_tiles, n_tiles, n_chunk_ub, n_comb_ub, n_slot_ub;
+  int lsf_r, psf_r, n_psf_tiles, n_psf_seg_y, n_psf_seg_x, n_fin_blocks;
+  double lsf_sigma_bins;
+  // byte offsets inside the job's workspace region
+  size_t o_k0, o_k1, o_v0, o_v1, o_hist, o_dtot;                       // sort
+  size_t o_prep, o_chunks, o_combs, o_counts, o_partial;              // cube
+  size_t o_tmp;                                                       // psf/lsf
+  size_t o_bintab, o_dots, o_ang;                                     // backward (+ o_prep)
+  size_t region;
+};
+
+static int radius_of(double sigma) { return sigma > 0.0 ? (int)(4.0 * sigma + 0.5) : 0; }
+
+static JobSizes sizes_of(const rubix_job &j) {
+  JobSizes z{};
+  z.n = j.p.n;
+  z.n_s = (int64_t)j.grid.nx * j.grid.ny;
+  z.n_tel = j.tel.n;
+  z.cube_elems = z.n_s * z.n_tel;
+  int bits = 0;
+  while ((int64_t(1) << bits) <= z.n_s) ++bits;      // keys are 0..n_s
+  z.passes = std::max(1, (bits + 7) / 8);
+  z.n_sort_tiles = (int)cdiv(z.n, kSortTile);
+  z.n_tiles = (int)cdiv(z.n_tel, kCubeTL);
+  z.n_chunk_ub = (int)(z.n_s + cdiv(z.n, kCubeChunk));
+  z.n_comb_ub = z.n > kCubeChunk ? (int)(z.n / (kCubeChunk + 1) + 1) : 0;
+  z.n_slot_ub = (int)(2 * cdiv(z.n, kCubeChunk) + 2);
+  z.lsf_sigma_bins = j.lsf_sigma_A / j.tel.step;
+  z.lsf_r = radius_of(z.lsf_sigma_bins);
+  z.psf_r = radius_of(j.psf_sigma_spx);
+  z.n_psf_tiles = (int)cdiv(z.n_tel, kPsfLanes);
+  z.n_psf_seg_y = (int)cdiv(j.grid.ny, kPsfSeg);
+  z.n_psf_seg_x = (int)cdiv(j.grid.nx, kPsfSeg);
+  z.n_fin_blocks = (int)cdiv(z.n, kFinThreads);
+  const size_t n4 = al(4 * (size_t)z.n);
+  // sort region
+  size_t o = 0;
+  z.o_k0 = o; o += n4;
+  z.o_k1 = o; o += n4;
+  z.o_v0 = o; o += n4;
+  z.o_v1 = o; o += n4;
+  z.o_hist = o; o += al(4ull * 256 * z.n_sort_tiles);
+  z.o_dtot = o; o += al(4 * 256);
+  size_t sort_end = o;
+  // cube region
+  o = 0;
+  z.o_prep = o; o += al(sizeof(PrepRec) * (size_t)z.n);
+  z.o_chunks = o; o += al(sizeof(ChunkRec) * (size_t)z.n_chunk_ub);
+  z.o_combs = o; o += al(sizeof(CombRec) * (size_t)std::max(1, z.n_comb_ub));
+  z.o_counts = o; o += al(16);
+  z.o_partial = o; o += z.n_comb_ub > 0 ? al(4ull * z.n_slot_ub * z.n_tel) : 0;
+  size_t cube_end = o;
+  // psf/lsf region
+  z.o_tmp = 0;
+  size_t psf_end = al(4ull * z.cube_elems);
+  // backward region (prep at the same offset as in the cube region)
+  o = al(sizeof(PrepRec) * (size_t)z.n);
+  z.o_bintab = o; o += al(16ull * z.n_tel);
+  z.o_dots = o; o += al(40ull * z.n);
+  z.o_ang = o; o += al(24ull * std::max(1, z.n_fin_blocks));
+  size_t bwd_end = o;
+  z.region = std::max(std::max(sort_end, cube_end), std::max(psf_end, bwd_end));
+  return z;
+}
+
+static bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+static int validate_ssp(const rubix_ssp *ssp) {
+  if (!ssp) return fail(RUBIX_EINVAL, "ssp is NULL");
+  if (ssp->n_age < 2 || ssp->n_age > RUBIX_MAX_AGE_NODES)
+    return fail(RUBIX_EINVAL, "ssp.n_age=%d outside [2, %d]", ssp->n_age, RUBIX_MAX_AGE_NODES);
+  if (ssp->n_met < 2 || ssp->n_met > RUBIX_MAX_MET_NODES)
+    return fail(RUBIX_EINVAL, "ssp.n_met=%d outside [2, %d]", ssp->n_met, RUBIX_MAX_MET_NODES);
+  if (!ssp->log_age_nodes || !ssp->met_nodes || !ssp->flux)
+    return fail(RUBIX_EINVAL, "ssp node or flux pointer is NULL");
+  for (int i = 0; i < ssp->n_age; ++i) {
+    if (!isfinite(ssp->log_age_nodes[i]) || (i && !(ssp->log_age_nodes[i] > ssp->log_age_nodes[i - 1])))
+      return fail(RUBIX_EINVAL, "ssp.log_age_nodes must be finite and strictly increasing (index %d)", i);
+  }
+  for (int i = 0; i < ssp->n_met; ++i) {
+    if (!isfinite(ssp->met_nodes[i]) || (i && !(ssp->met_nodes[i] > ssp->met_nodes[i - 1])))
+      return fail(RUBIX_EINVAL, "ssp.met_nodes must be finite and strictly increasing (index %d)", i);
+  }
+  if (ssp->lam.n < 2) return fail(RUBIX_EINVAL, "ssp.lam.n=%d < 2", ssp->lam.n);
+  if (!finite_pos(ssp->lam.step) || !isfinite(ssp->lam.start))
+    return fail(RUBIX_EINVAL, "ssp.lam start/step invalid");
+  if ((int64_t)ssp->n_age * ssp->n_met * ssp->lam.n > INT32_MAX)
+    return fail(RUBIX_ERANGE, "ssp grid has more than 2^31-1 values");
+  return RUBIX_OK;
+}
+
+static int validate_jobs(const rubix_job *jobs, int n_jobs, Call call) {
+  if (!jobs) return fail(RUBIX_EINVAL, "jobs is NULL");
+  if (n_jobs < 1 || n_jobs > RUBIX_MAX_JOBS)
+    return fail(RUBIX_EINVAL, "n_jobs=%d outside [1, %d]", n_jobs, RUBIX_MAX_JOBS);
+  for (int k = 0; k < n_jobs; ++k) {
+    const rubix_job &j = jobs[k];
+    if (j.p.n < 0) return fail(RUBIX_EINVAL, "job %d: n=%lld < 0", k, (long long)j.p.n);
+    if (j.p.n > INT32_MAX) return fail(RUBIX_ERANGE, "job %d: more than 2^31-1 particles", k);
+    if (j.grid.nx < 1 || j.grid.ny < 1)
+      return fail(RUBIX_EINVAL, "job %d: grid %dx%d is empty", k, j.grid.nx, j.grid.ny);
+    if ((int64_t)j.grid.nx * j.grid.ny >= INT32_MAX)
+      return fail(RUBIX_ERANGE, "job %d: too many spaxels", k);
+    if (!finite_pos(j.grid.spaxel_kpc)) return fail(RUBIX_EINVAL, "job %d: spaxel_kpc must be > 0", k);
+    if (j.tel.n < 1) return fail(RUBIX_EINVAL, "job %d: tel.n=%d < 1", k, j.tel.n);
+    if (!finite_pos(j.tel.step) || !isfinite(j.tel.start))
+      return fail(RUBIX_EINVAL, "job %d: telescope grid start/step invalid", k);
+    if (!(j.z_sys > -1.0) || !isfinite(j.z_sys)) return fail(RUBIX_EINVAL, "job %d: z_sys must be > -1", k);
+    if (!isfinite(j.flux_scale)) return fail(RUBIX_EINVAL, "job %d: flux_scale not finite", k);
+    for (int a = 0; a < 3; ++a)
+      if (!isfinite(j.angles_rad[a])) return fail(RUBIX_EINVAL, "job %d: angle %d not finite", k, a);
+    if (!(j.psf_sigma_spx >= 0.0) || !(j.lsf_sigma_A >= 0.0) || !isfinite(j.psf_sigma_spx) ||
+        !isfinite(j.lsf_sigma_A))
+      return fail(RUBIX_EINVAL, "job %d: PSF/LSF sigma must be finite and >= 0", k);
+    if (radius_of(j.psf_sigma_spx) > RUBIX_MAX_RADIUS ||
+        radius_of(j.lsf_sigma_A / j.tel.step) > RUBIX_MAX_RADIUS)
+      return fail(RUBIX_ERANGE, "job %d: PSF/LSF radius exceeds %d", k, RUBIX_MAX_RADIUS);
+    if (call == CALL_SIZE) continue;
+    const bool need_pos = call == CALL_ROTATE || call == CALL_PACK;
+    const bool need_props = call == CALL_CUBE || call == CALL_BWD || call == CALL_PACK;
+    const bool need_vel = need_pos || call == CALL_BWD;
+    if (j.p.n > 0) {
+      if (need_pos && (!j.p.x || !j.p.y || !j.p.z))
+        return fail(RUBIX_EINVAL, "job %d: position pointer is NULL", k);
+      if (need_vel && (!j.p.vx || !j.p.vy || !j.p.vz))
+        return fail(RUBIX_EINVAL, "job %d: velocity pointer is NULL", k);
+      if (need_props && (!j.p.mass || !j.p.age || !j.p.met))
+        return fail(RUBIX_EINVAL, "job %d: mass/age/met pointer is NULL", k);
+    }
+    if (call == CALL_ROTATE || call == CALL_CUBE || call == CALL_BWD || call == CALL_PACK) {
+      if ((!j.key || !j.perm || !j.vlos) && j.p.n > 0)
+        return fail(RUBIX_EINVAL, "job %d: key/perm/vlos pointer is NULL", k);
+      if (!j.seg_off) return fail(RUBIX_EINVAL, "job %d: seg_off is NULL", k);
+    }
+    if ((call == CALL_CUBE || call == CALL_PACK) && !j.cube_raw)
+      return fail(RUBIX_EINVAL, "job %d: cube_raw is NULL", k);
+    if (call == CALL_PACK && !j.cube) return fail(RUBIX_EINVAL, "job %d: cube is NULL", k);
+  }
+  return RUBIX_OK;
+}
+
+static size_t workspace_bytes(const rubix_job *jobs, int n_jobs) {
+  size_t b = al(table_bytes(n_jobs));
+  for (int k = 0; k < n_jobs; ++k) b += al(sizes_of(jobs[k]).region);
+  return b;
+}
+
+static int check_ws(const rubix_job *jobs, int n_jobs, void *ws, size_t ws_bytes) {
+  const size_t need = workspace_bytes(jobs, n_jobs);
+  if (!ws) return fail(RUBIX_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(RUBIX_EWORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < need) return fail(RUBIX_EWORKSPACE, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+  return RUBIX_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// table construction
+// ---------------------------------------------------------------------------------------------
+static void rotation(const double ang[3], double R[9], double dR2[9]) {
+#pragma clang fp contract(off)
+  const double c1 = cos(ang[0]), s1 = sin(ang[0]);
+  const double c2 = cos(ang[1]), s2 = sin(ang[1]);
+  const double c3 = cos(ang[2]), s3 = sin(ang[2]);
+  // R = Rz(phi3) Ry(phi2) Rx(phi1), each entry written as the closed-form product
+  R[0] = c3 * c2;  R[1] = (c3 * s2) * s1 - s3 * c1;  R[2] = (c3 * s2) * c1 + s3 * s1;
+  R[3] = s3 * c2;  R[4] = (s3 * s2) * s1 + c3 * c1;  R[5] = (s3 * s2) * c1 - c3 * s1;
+  R[6] = -s2;      R[7] = c2 * s1;                   R[8] = c2 * c1;
+  // d(row 2)/dphi_k
+  dR2[0] = 0.0;  dR2[1] = c2 * c1;  dR2[2] = -c2 * s1;
+  dR2[3] = -c2;  dR2[4] = -s2 * s1; dR2[5] = -s2 * c1;
+  dR2[6] = 0.0;  dR2[7] = 0.0;      dR2[8] = 0.0;
+}
+
+static void gauss_weights(double sigma, int r, float *w) {
+  if (r == 0) { w[0] = 1.f; return; }
+  double tmp[2 * RUBIX_MAX_RADIUS + 1], sum = 0.0;
+  for (int k = -r; k <= r; ++k) { tmp[k + r] = exp(-0.5 * (k / sigma) * (k / sigma)); sum += tmp[k + r]; }
+  for (int k = 0; k <= 2 * r; ++k) w[k] = (float)(tmp[k] / sum);
+}
+
+static void fill_ssp(SspDev &S, const rubix_ssp *ssp) {
+  memset(&S, 0, sizeof S);
+  if (!ssp) return;
+  S.flux = ssp->flux;
+  S.n_age = ssp->n_age; S.n_met = ssp->n_met; S.n_lam = ssp->lam.n;
+  S.lam_start = ssp->lam.start; S.lam_step = ssp->lam.step;
+  for (int i = 0; i < ssp->n_age; ++i) {
+    S.log_age[i] = (double)ssp->log_age_nodes[i];
+    S.age_thr[i] = pow(10.0, S.log_age[i]);
+  }
+  for (int i = 0; i < ssp->n_met; ++i) S.met[i] = (double)ssp->met_nodes[i];
+}
+
+struct PslfIO { const float *const *in; float *const *out; };
+struct BwdIO {
+  const float *const *grad_raw;
+  float *const *d_mass, *const *d_age, *const *d_met, *const *d_vlos, *const *d_vel;
+  double *d_angles;
+};
+
+// Builds the table (host bytes) for `jobs` with per-job workspace regions placed after the table
+// region of `ws`. Per-call I/O (PSF/LSF in/out, backward buffers) is optional.
+static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
+                                        void *ws, const PslfIO *pl, const BwdIO *bw) {
+  std::vector<uint8_t> buf(table_bytes(n_jobs), 0);
+  Table *t = reinterpret_cast<Table *>(buf.data());
+  JobDev *J = reinterpret_cast<JobDev *>(buf.data() + ((sizeof(Table) + 255) & ~size_t(255)));
+  t->h.n_jobs = n_jobs;
+  fill_ssp(t->h.ssp, ssp);
+  uint8_t *region = static_cast<uint8_t *>(ws) + al(table_bytes(n_jobs));
+  int64_t start[NK] = {0};
+  int max_passes = 1;
+  for (int k = 0; k < n_jobs; ++k) {
+    const rubix_job &j = jobs[k];
+    const JobSizes z = sizes_of(j);
+    JobDev &d = J[k];
+    d.x = j.p.x; d.y = j.p.y; d.z = j.p.z; d.vx = j.p.vx; d.vy = j.p.vy; d.vz = j.p.vz;
+    d.mass = j.p.mass; d.age = j.p.age; d.met = j.p.met;
+    d.n = (int32_t)z.n; d.nx = j.grid.nx; d.ny = j.grid.ny; d.n_s = (int32_t)z.n_s;
+    rotation(j.angles_rad, d.R, d.dR2);
+    d.spaxel = j.grid.spaxel_kpc;
+    d.half_nx = j.grid.nx / 2.0; d.half_ny = j.grid.ny / 2.0;
+    d.tel_start = j.tel.start; d.tel_step = j.tel.step; d.z_sys = j.z_sys; d.flux_scale = j.flux_scale;
+    d.lsf_sigma_bins = z.lsf_sigma_bins; d.psf_sigma = j.psf_sigma_spx;
+    d.lsf_r = z.lsf_r; d.psf_r = z.psf_r;
+    gauss_weights(z.lsf_sigma_bins, z.lsf_r, d.lsf_w);
+    gauss_weights(j.psf_sigma_spx, z.psf_r, d.psf_w);
+    d.n_tel = (int32_t)z.n_tel; d.passes = z.passes; d.n_sort_tiles = z.n_sort_tiles; d.n_tiles = z.n_tiles;
+    d.n_chunk_ub = z.n_chunk_ub; d.n_comb_ub = z.n_comb_ub;
+    d.n_psf_tiles = z.n_psf_tiles; d.n_psf_seg_y = z.n_psf_seg_y; d.n_psf_seg_x = z.n_psf_seg_x;
+    d.n_fin_blocks = z.n_fin_blocks;
+    d.key = j.key; d.perm = j.perm; d.seg_off = j.seg_off; d.vlos = j.vlos; d.cube_raw = j.cube_raw;
+    d.cube_elems = z.cube_elems;
+    max_passes = std::max(max_passes, z.passes);
+    // workspace
+    d.kbuf[0] = reinterpret_cast<uint32_t *>(region + z.o_k0);
+    d.kbuf[1] = reinterpret_cast<uint32_t *>(region + z.o_k1);
+    d.vbuf[0] = reinterpret_cast<uint32_t *>(region + z.o_v0);
+    d.vbuf[1] = reinterpret_cast<uint32_t *>(region + z.o_v1);
+    d.hist = reinterpret_cast<uint32_t *>(region + z.o_hist);
+    d.dtot = reinterpret_cast<uint32_t *>(region + z.o_dtot);
+    d.prep = reinterpret_cast<PrepRec *>(region + z.o_prep);
+    d.chunks = reinterpret_cast<ChunkRec *>(region + z.o_chunks);
+    d.combs = reinterpret_cast<CombRec *>(region + z.o_combs);
+    d.counts = reinterpret_cast<int32_t *>(region + z.o_counts);
+    d.partial = reinterpret_cast<float *>(region + z.o_partial);
+    d.tmp_cube = reinterpret_cast<float *>(region + z.o_tmp);
+    d.bintab = reinterpret_cast<float4 *>(region + z.o_bintab);
+    d.dots = reinterpret_cast<double *>(region + z.o_dots);
+    d.ang_part = reinterpret_cast<double *>(region + z.o_ang);
+    region += al(z.region);
+    // PSF/LSF routing: lambda pass, y pass, x pass; the last active pass writes `out`
+    int64_t n_lsf = 0, n_psfy = 0, n_psfx = 0, n_copy = 0;
+    if (pl) {
+      const float *in = pl->in[k];
+      float *out = pl->out[k];
+      const bool L = z.lsf_r > 0, P = z.psf_r > 0;
+      const int n_pass = (L ? 1 : 0) + (P ? 2 : 0);
+      // destinations alternate between out and tmp so that the final pass lands in out
+      float *bufs[2] = {out, d.tmp_cube};
+      int which = (n_pass % 2 == 1) ? 0 : 1;   // first destination
+      const float *cur = in;
+      const bool act[3] = {L, P, P};
+      for (int q = 0; q < 3; ++q) {
+        if (!act[q]) continue;
+        d.pl_src[q] = cur;
+        d.pl_dst[q] = bufs[which];
+        cur = bufs[which];
+        which ^= 1;
+      }
+      if (L) n_lsf = z.n_s * cdiv(z.n_tel, kLsfTL);
+      if (P) {
+        n_psfy = (int64_t)j.grid.nx * z.n_psf_seg_y * z.n_psf_tiles;
+        n_psfx = (int64_t)j.grid.ny * z.n_psf_seg_x * z.n_psf_tiles;
+      }
+      if (n_pass == 0 && in != out) {
+        d.copy_src = in; d.copy_dst = out;
+        n_copy = cdiv(z.cube_elems, 65536);
+      }
+    }
+    if (bw) {
+      d.grad_raw = bw->grad_raw[k];
+      d.d_mass = bw->d_mass[k]; d.d_age = bw->d_age[k]; d.d_met = bw->d_met[k];
+      d.d_vlos = bw->d_vlos[k]; d.d_vel = bw->d_vel ? bw->d_vel[k] : nullptr;
+      d.d_angles = bw->d_angles + 3 * k;
+    }
+    const int64_t cnt[NK] = {
+        /*K_ROT*/ z.n_sort_tiles,
+        /*K_SCAN*/ z.n > 0 ? 256 : 0,
+        /*K_SEG*/ cdiv(z.n_s + 1, 256),
+        /*K_PREP*/ cdiv(z.n, kPrepThreads),
+        /*K_CHUNK*/ 1,
+        /*K_CUBE*/ (int64_t)z.n_tiles * z.n_chunk_ub,
+        /*K_COMB*/ (int64_t)z.n_tiles * z.n_comb_ub,
+        /*K_LSF*/ n_lsf,
+        /*K_PSFY*/ n_psfy,
+        /*K_PSFX*/ n_psfx,
+        /*K_COPY*/ n_copy,
+        /*K_BINTAB*/ cdiv(z.n_tel, 256),
+        /*K_BWD*/ cdiv(z.n, kBwdParticles),
+        /*K_FIN*/ z.n_fin_blocks,
+        /*K_ANG*/ 1,
+    };
+    for (int q = 0; q < NK; ++q) {
+      d.vb_start[q] = start[q];
+      start[q] += cnt[q];
+    }
+  }
+  for (int q = 0; q < NK; ++q) t->h.total[q] = start[q];
+  t->h.max_passes = max_passes;
+  return buf;
+}
+
+static int device_status(hipError_t e, const char *what) {
+  if (e == hipSuccess) return RUBIX_OK;
+  return fail(RUBIX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+using Launcher = hipError_t (*)(const Table *, const TableHeader &, int, hipStream_t);
+
+static int run(const std::vector<uint8_t> &tab, void *ws, hipStream_t s, Launcher fn,
+               const char *what) {
+  hipError_t e = launch_upload(tab.data(), tab.size(), ws, s);
+  if (e != hipSuccess) return device_status(e, "job table upload");
+  const Table *host = reinterpret_cast<const Table *>(tab.data());
+  e = fn(static_cast<const Table *>(ws), host->h, 0, s);
+  return device_status(e, what);
+}
+
+}  // namespace rubix
+
+using namespace rubix;
+
+extern "C" {
+
+const char *rubix_last_error(void) { return g_err.c_str(); }
+
+const char *rubix_version(void) { return "rubix-mi355x 0.1.0 (gfx950)"; }
+
+int rubix_workspace_size(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, size_t *bytes) {
+  g_err.clear();
+  if (!bytes) return fail(RUBIX_EINVAL, "bytes is NULL");
+  int rc = validate_jobs(jobs, n_jobs, CALL_SIZE);
+  if (rc) return rc;
+  if (ssp && (rc = validate_ssp(ssp))) return rc;
+  *bytes = workspace_bytes(jobs, n_jobs);
+  return RUBIX_OK;
+}
+
+int rubix_rotate_bin(const rubix_job *jobs, int n_jobs, void *ws, size_t ws_bytes, void *stream) {
+  g_err.clear();
+  int rc;
+  if ((rc = validate_jobs(jobs, n_jobs, CALL_ROTATE))) return rc;
+  if ((rc = check_ws(jobs, n_jobs, ws, ws_bytes))) return rc;
+  auto tab = build_table(jobs, n_jobs, nullptr, ws, nullptr, nullptr);
+  return run(tab, ws, static_cast<hipStream_t>(stream), launch_rotate_bin, "rubix_rotate_bin");
+}
+
+int rubix_cube(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, void *ws, size_t ws_bytes,
+               void *stream) {
+  g_err.clear();
+  int rc;
+  if ((rc = validate_jobs(jobs, n_jobs, CALL_CUBE))) return rc;
+  if ((rc = validate_ssp(ssp))) return rc;
+  if ((rc = check_ws(jobs, n_jobs, ws, ws_bytes))) return rc;
+  auto tab = build_table(jobs, n_jobs, ssp, ws, nullptr, nullptr);
+  return run(tab, ws, static_cast<hipStream_t>(stream), launch_cube, "rubix_cube");
+}
+
+int rubix_psf_lsf(const rubix_job *jobs, int n_jobs, const float *const *in, float *const *out,
+                  void *ws, size_t ws_bytes, void *stream) {
+  g_err.clear();
+  int rc;
+  if ((rc = validate_jobs(jobs, n_jobs, CALL_PSF))) return rc;
+  if (!in || !out) return fail(RUBIX_EINVAL, "in/out arrays are NULL");
+  for (int k = 0; k < n_jobs; ++k) {
+    if (!in[k] || !out[k]) return fail(RUBIX_EINVAL, "job %d: in/out cube is NULL", k);
+    const int64_t bytes = (int64_t)jobs[k].grid.nx * jobs[k].grid.ny * jobs[k].tel.n * 4;
+    const char *a = reinterpret_cast<const char *>(in[k]);
+    const char *b = reinterpret_cast<const char *>(out[k]);
+    if (a < b + bytes && b < a + bytes) return fail(RUBIX_EINVAL, "job %d: in and out overlap", k);
+  }
+  if ((rc = check_ws(jobs, n_jobs, ws, ws_bytes))) return rc;
+  PslfIO io{in, out};
+  auto tab = build_table(jobs, n_jobs, nullptr, ws, &io, nullptr);
+  return run(tab, ws, static_cast<hipStream_t>(stream), launch_psf_lsf, "rubix_psf_lsf");
+}
+
+int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
+                        const float *const *grad_raw, float *const *d_mass, float *const *d_age,
+                        float *const *d_met, float *const *d_vlos, float *const *d_vel,
+                        double *d_angles, void *ws, size_t ws_bytes, void *stream) {
+  g_err.clear();
+  int rc;
+  if ((rc = validate_jobs(jobs, n_jobs, CALL_BWD))) return rc;
+  if ((rc = validate_ssp(ssp))) return rc;
+  if (!grad_raw || !d_mass || !d_age || !d_met || !d_vlos || !d_angles)
+    return fail(RUBIX_EINVAL, "gradient array argument is NULL");
+  for (int k = 0; k < n_jobs; ++k) {
+    if (!grad_raw[k]) return fail(RUBIX_EINVAL, "job %d: grad_raw is NULL", k);
+    if (jobs[k].p.n > 0 && (!d_mass[k] || !d_age[k] || !d_met[k] || !d_vlos[k]))
+      return fail(RUBIX_EINVAL, "job %d: a gradient output is NULL", k);
+  }
+  if ((rc = check_ws(jobs, n_jobs, ws, ws_bytes))) return rc;
+  BwdIO io{grad_raw, d_mass, d_age, d_met, d_vlos, d_vel, d_angles};
+  auto tab = build_table(jobs, n_jobs, ssp, ws, nullptr, &io);
+  return run(tab, ws, static_cast<hipStream_t>(stream), launch_backward, "rubix_cube_backward");
+}
+
+}  // extern "C"

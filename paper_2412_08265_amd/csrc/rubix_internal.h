@@ -1,0 +1,156 @@
+// Internal layout shared by the HIP translation units of librubix: the device job table that every
+// kernel reads, work-item ("virtual block") bookkeeping and launch helpers.
+//
+// Every kernel walks virtual blocks vb = blockIdx.x, blockIdx.x + gridDim.x, ... < table->total[K]
+// and maps vb to (job, local block) with the per-job prefix jobs[j].vb_start[K]. A launch whose grid
+// equals the total is an ordinary one-pass launch; a smaller grid makes the same kernel persistent.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rubix.h"
+
+namespace rubix {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // keys per sort work item
+constexpr int kPrepThreads = 256;
+constexpr int kCubeTL = 256;        // telescope bins per cube work item (= threads per block)
+constexpr int kCubeChunk = 2048;    // max particles per cube work item
+constexpr int kCubeSubsum = 256;    // particles per inner FP32 partial sum
+constexpr int kLsfTL = 256;         // bins per LSF work item
+constexpr int kPsfLanes = 64;       // bins per PSF work item
+constexpr int kPsfSeg = 128;        // spaxels of a line per PSF work item
+constexpr int kBwdParticles = 16;   // particles per backward work item (4 per wave)
+constexpr int kFinThreads = 256;
+
+enum Kind : int {
+  K_ROT = 0,   // rotate/key and radix-sort tiles (per kSortTile particles)
+  K_SCAN,      // per (job, digit)
+  K_SEG,       // seg_off, per 256 spaxels
+  K_PREP,      // per kPrepThreads sorted particles
+  K_CHUNK,     // one per job
+  K_CUBE,      // per (lambda tile, chunk slot)
+  K_COMB,      // per (lambda tile, combine slot)
+  K_LSF,       // per (spaxel, lambda tile)
+  K_PSFY,      // per (x column, y segment, lambda tile)
+  K_PSFX,      // per (y row, x segment, lambda tile)
+  K_COPY,      // per 64k floats of a cube (identity PSF/LSF)
+  K_BINTAB,    // per 256 telescope bins
+  K_BWD,       // per kBwdParticles sorted particles
+  K_FIN,       // per kFinThreads sorted particles
+  K_ANG,       // one per job
+  NK
+};
+
+// Per-particle record written by the prep kernel, in sorted order (32 bytes).
+struct PrepRec {
+  int32_t row;      // flux offset of corner (ja, jz): (ja*n_met + jz)*n_lam
+  float g;          // beta/(1+beta) / ((1+z_sys) dlam_ssp): Doppler slope of the node index
+  float a[4];       // corner weights (forward: flux_scale m J w_c; backward: w_c)
+  int32_t spaxel;   // key of the particle
+  int32_t pad;
+};
+
+struct ChunkRec {
+  int32_t s, p0, p1, slot;   // spaxel, sorted particle range [p0, p1), partial slot or -1
+};
+
+struct CombRec {
+  int32_t s, first_slot, n_slots, pad;
+};
+
+struct SspDev {
+  const float *flux;
+  int32_t n_age, n_met, n_lam, pad;
+  double lam_start, lam_step;
+  double age_thr[RUBIX_MAX_AGE_NODES];   // 10^(log age node), FP64 cell thresholds in Gyr
+  double log_age[RUBIX_MAX_AGE_NODES];   // log10 age nodes (FP64 copies of the FP32 inputs)
+  double met[RUBIX_MAX_MET_NODES];
+};
+
+struct JobDev {
+  // inputs
+  const float *x, *y, *z, *vx, *vy, *vz, *mass, *age, *met;
+  int32_t n, nx, ny, n_s;
+  double R[9];        // rotation matrix, row major
+  double dR2[9];      // dR[2][:]/dphi_k for k = 0, 1, 2 (row k)
+  double spaxel, half_nx, half_ny;
+  double tel_start, tel_step, z_sys, flux_scale;
+  double lsf_sigma_bins, psf_sigma;
+  float lsf_w[2 * RUBIX_MAX_RADIUS + 1];   // normalised LSF weights, k = -r..r
+  float psf_w[2 * RUBIX_MAX_RADIUS + 1];   // normalised PSF weights
+  int32_t n_tel, passes, n_sort_tiles, n_tiles;     // n_tiles: cube lambda tiles of kCubeTL
+  int32_t n_chunk_ub, n_comb_ub, lsf_r, psf_r;
+  int32_t n_psf_tiles, n_psf_seg_y, n_psf_seg_x, n_fin_blocks;
+  // outputs
+  int32_t *key, *perm, *seg_off;
+  float *vlos, *cube_raw;
+  // PSF/LSF passes: source and destination of the lambda, y and x passes (null = skipped);
+  // copy_src/copy_dst for a job with no pass at all
+  const float *pl_src[3];
+  float *pl_dst[3];
+  const float *copy_src;
+  float *copy_dst;
+  int64_t cube_elems;
+  // backward I/O
+  const float *grad_raw;
+  float *d_mass, *d_age, *d_met, *d_vlos, *d_vel;
+  double *d_angles;     // 3 doubles for this job
+  // workspace (per job)
+  uint32_t *kbuf[2], *vbuf[2];
+  uint32_t *hist;       // [256][n_sort_tiles], digit major
+  uint32_t *dtot;       // [256]
+  PrepRec *prep;        // [n]
+  ChunkRec *chunks;     // [n_chunk_ub]
+  CombRec *combs;       // [n_comb_ub]
+  int32_t *counts;      // [0] chunks, [1] combine entries
+  float *partial;       // [n_comb_slots_ub][n_tel]
+  float *tmp_cube;      // [cube_elems]
+  float4 *bintab;       // [n_tel]: (node index integer part as int bits, frac, lambda, 0)
+  double *dots;         // [n][5]
+  double *ang_part;     // [n_fin_blocks][3]
+  int64_t vb_start[NK];
+};
+
+struct TableHeader {
+  int32_t n_jobs, max_passes;   // max_passes: most radix-sort passes any job of the table needs
+  int64_t total[NK];
+  SspDev ssp;
+};
+
+struct Table {
+  TableHeader h;
+  // JobDev jobs[n_jobs] follows, 16-byte aligned
+};
+
+__host__ __device__ inline const JobDev *table_jobs(const Table *t) {
+  return reinterpret_cast<const JobDev *>(reinterpret_cast<const char *>(t) +
+                                          ((sizeof(Table) + 255) & ~size_t(255)));
+}
+
+__host__ __device__ inline size_t table_bytes(int n_jobs) {
+  return ((sizeof(Table) + 255) & ~size_t(255)) + size_t(n_jobs) * sizeof(JobDev);
+}
+
+// Largest job index j with jobs[j].vb_start[kind] <= vb (vb is wave-uniform).
+__device__ inline int find_job(const Table *t, int kind, int64_t vb) {
+  const JobDev *jobs = table_jobs(t);
+  int lo = 0, hi = t->h.n_jobs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].vb_start[kind] <= vb) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Launchers (one per translation unit); grid = number of blocks (persistent if < total).
+hipError_t launch_upload(const void *host_table, size_t bytes, void *dev_table, hipStream_t s);
+hipError_t launch_rotate_bin(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
+hipError_t launch_cube(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
+hipError_t launch_psf_lsf(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
+hipError_t launch_backward(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
+
+}  // namespace rubix

@@ -1,0 +1,138 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads, exports every entry point the
+header declares, sizes workspaces and rejects invalid arguments before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2412_08265_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2412_08265_amd import build
+        build.build()
+    return _lib.load()
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "rubix.h")) as f:
+        src = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(rubix_\w+)\s*\(", src, re.M)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert {"rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf", "rubix_cube_backward",
+            "rubix_workspace_size", "rubix_last_error"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.rubix_version().decode().startswith("rubix-mi355x")
+
+
+def _job(n=100, nx=8, ny=6, tel_n=300):
+    from paper_2412_08265_amd import ops
+    j = ops.RubixJob()
+    j.p.n = n
+    fake = 0x1000
+    for f in ops.FIELDS:
+        setattr(j.p, f, fake)
+    j.grid = ops.RubixGrid(nx, ny, 0.5)
+    j.tel = ops.RubixLGrid(4000.0, 1.25, tel_n)
+    j.flux_scale = 1.0
+    j.key = j.perm = j.seg_off = j.vlos = j.cube_raw = j.cube = fake
+    return j
+
+
+def _arr(*jobs):
+    from paper_2412_08265_amd import ops
+    return (ops.RubixJob * len(jobs))(*jobs)
+
+
+def _ws_size(lib, jobs, ssp=None):
+    out = ctypes.c_size_t(0)
+    rc = lib.rubix_workspace_size(_arr(*jobs), len(jobs), ssp, ctypes.byref(out))
+    return rc, out.value
+
+
+def test_workspace_size_grows_with_work(lib):
+    rc, a = _ws_size(lib, [_job(1000)])
+    assert rc == 0 and a > 0 and a % 256 == 0
+    rc, b = _ws_size(lib, [_job(100000)])
+    assert rc == 0 and b > a
+    rc, c = _ws_size(lib, [_job(1000), _job(100000)])
+    assert rc == 0 and c > b
+
+
+@pytest.mark.parametrize("mut,code", [
+    (lambda j: setattr(j.p, "n", -1), -1),
+    (lambda j: setattr(j, "grid", type(j.grid)(0, 4, 1.0)), -1),
+    (lambda j: setattr(j, "grid", type(j.grid)(4, 4, 0.0)), -1),
+    (lambda j: setattr(j, "tel", type(j.tel)(4000.0, -1.0, 10)), -1),
+    (lambda j: setattr(j, "tel", type(j.tel)(4000.0, 1.0, 0)), -1),
+    (lambda j: setattr(j, "psf_sigma_spx", -0.5), -1),
+    (lambda j: setattr(j, "lsf_sigma_A", 1000.0), -4),       # radius > RUBIX_MAX_RADIUS
+    (lambda j: setattr(j, "z_sys", -1.0), -1),
+    (lambda j: setattr(j.p, "n", 2 ** 31), -4),
+])
+def test_invalid_jobs_are_rejected(lib, mut, code):
+    j = _job()
+    mut(j)
+    rc, _ = _ws_size(lib, [j])
+    assert rc == code
+    assert lib.rubix_last_error().decode() != ""
+
+
+def test_entry_points_validate_before_launch(lib):
+    from paper_2412_08265_amd import ops
+    j = _job()
+    j.p.x = None
+    assert lib.rubix_rotate_bin(_arr(j), 1, None, 0, None) == -1
+    assert b"position" in lib.rubix_last_error()
+    j = _job()
+    # workspace missing / misaligned / too small
+    assert lib.rubix_rotate_bin(_arr(j), 1, None, 0, None) == -2
+    assert lib.rubix_rotate_bin(_arr(j), 1, 0x1001, 1 << 30, None) == -2
+    assert lib.rubix_rotate_bin(_arr(j), 1, 0x1000, 16, None) == -2
+    assert lib.rubix_rotate_bin(_arr(j), 0, 0x1000, 1 << 30, None) == -1
+    too_many = [_job() for _ in range(65)]
+    assert lib.rubix_rotate_bin(_arr(*too_many), 65, 0x1000, 1 << 40, None) == -1
+
+
+def _ssp_c(la, mz, n_lam=100):
+    from paper_2412_08265_amd import ops
+    la = np.asarray(la, dtype=np.float32)
+    mz = np.asarray(mz, dtype=np.float32)
+    s = ops.RubixSSP(la.size, mz.size, la.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                     mz.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                     ops.RubixLGrid(3600.0, 2.0, n_lam), 0x1000)
+    return s, (la, mz)
+
+
+def test_ssp_validation(lib):
+    good, keep = _ssp_c([-1, 0, 1], [-2, 0])
+    assert _ws_size(lib, [_job()], ctypes.byref(good))[0] == 0
+    for la, mz, n in (([-1, 0, 0], [-2, 0], 100), ([0], [-2, 0], 100), ([-1, 0], [0, -2], 100),
+                      ([-1, float("nan")], [-2, 0], 100), ([-1, 0], [-2, 0], 1)):
+        bad, keep2 = _ssp_c(la, mz, n)
+        assert _ws_size(lib, [_job()], ctypes.byref(bad))[0] == -1, (la, mz, n)
+    big, keep3 = _ssp_c(np.arange(256) * 0.01, np.arange(64) * 0.01, 200000)
+    assert _ws_size(lib, [_job()], ctypes.byref(big))[0] == -4
+
+
+def test_product_path_never_touches_the_oracle():
+    """The HIP package and its binding import nothing from the oracle (and vice versa)."""
+    pkg = os.path.join(ROOT, "paper_2412_08265_amd")
+    for dp, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dp, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle", src, re.M), f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith(".py"):
+            src = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_2412_08265_amd" not in src, f

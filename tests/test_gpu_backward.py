@@ -1,0 +1,223 @@
+"""Parity of the hand-written adjoint (rubix_cube_backward and the RubixCube autograd function)
+with the FP64 oracle's analytic gradient and with FP64 central finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2412_08265_amd import synth
+from tests.helpers import WORKERS, log
+
+pytestmark = pytest.mark.gpu
+
+GRAD_KEYS = ("mass", "age", "met", "vlos")
+
+
+def _gpu_grads(w, G_rows):
+    """GPU forward (for key/perm/seg_off/vlos) then rubix_cube_backward with dL/dC_raw = G_rows."""
+    import torch
+    from paper_2412_08265_amd import ops
+    gal = ops.DeviceGalaxy.from_host(w.particles)
+    ssp = ops.DeviceSSP.from_grid(w.ssp)
+    fw = ops.Forward(gal, ops.Observation.from_workload(w), ssp)
+    fw()
+    G = torch.from_numpy(np.ascontiguousarray(G_rows, dtype=np.float32)).cuda()
+    out = ops.cube_backward(fw, G.reshape(w.ny, w.nx, w.n_tel))
+    torch.cuda.synchronize()
+    return fw, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _compare(gpu, ref, tol, what):
+    for k in GRAD_KEYS:
+        a = np.asarray(gpu[k], dtype=np.float64)
+        b = np.asarray(ref[k], dtype=np.float64)
+        err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+        log(f"{what} d{k}: max-norm rel err {err:.3e}")
+        assert err <= tol, (what, k, err)
+    a, b = np.asarray(gpu["angles"]), np.asarray(ref["angles"])
+    err = np.abs(a[:2] - b[:2]).max() / np.abs(b[:2]).max()
+    log(f"{what} dangles: rel err {err:.3e}; gpu phi3 = {a[2]:.3e}")
+    assert err <= tol and a[2] == 0.0
+    np.testing.assert_allclose(gpu["vel"], np.asarray(ref["vel"], dtype=np.float64),
+                               rtol=0, atol=tol * np.abs(ref["vel"]).max())
+
+
+def _small_workload(n=3000, seed=31):
+    p = synth.make_galaxy(n, seed)
+    ssp = synth.cached_ssp(12, 6, 3600.0, 3.8, 1000)
+    return synth.Workload("grad-small", p, (55.0, 12.0, 20.0), 14, 12, 2.0, 3640.0, 3.1, 1100,
+                          ssp, psf_sigma_spx=1.2, lsf_sigma_A=6.0)
+
+
+def test_backward_kernel_on_seeded_gradient():
+    """dL/dC_raw = a seeded random array, identical on both sides: isolates the adjoint kernels."""
+    w = _small_workload()
+    cfg = O.config_from_workload(w)
+    rng = np.random.default_rng(5)
+    G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
+    _, g = _gpu_grads(w, G)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64))
+    _compare(g, ref, 2e-5, "seeded-G")
+
+
+def _fd_delta_L(cfg, G, s, dplus, dminus):
+    """L(+) - L(-) when one particle of spaxel s changes its spectrum by d+/d- (FP64):
+    <d+ - d-, G[s]> + (|A d+|^2 - |A d-|^2)/2 with A = Px Py L separable, so
+    |A d|^2 = |Px Py e_s|^2 |L d|^2."""
+    wl = O.gaussian_weights(cfg.lsf_sigma_bins())
+    wp = O.gaussian_weights(cfg.psf_sigma_spx)
+    img = np.zeros((cfg.ny, cfg.nx))
+    img[s // cfg.nx, s % cfg.nx] = 1.0
+    img = O.convolve_axis(O.convolve_axis(img, wp, 0), wp, 1)
+    P2 = float(np.sum(img * img))
+    Lp = O.convolve_axis(dplus, wl, 0)
+    Lm = O.convolve_axis(dminus, wl, 0)
+    return float(np.dot(dplus - dminus, G[s])) + 0.5 * P2 * (np.dot(Lp, Lp) - np.dot(Lm, Lm))
+
+
+def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0):
+    p = w.particles
+    key, vlos = fo["key"], fo["vlos"]
+    la, mz = cfg.log_age_nodes, cfg.met_nodes
+    rng = np.random.default_rng(seed)
+    cand = rng.permutation(np.flatnonzero(key < cfg.n_spaxels))
+    maxg = {k: np.abs(gpu[k]).max() for k in GRAD_KEYS}
+    checked = 0
+    worst = {k: 0.0 for k in GRAD_KEYS}
+    for i in cand:
+        if checked >= n_check:
+            break
+        m, a, z, v = float(p.mass[i]), float(p.age[i]), float(p.met[i]), float(vlos[i])
+        # one linear piece on both sides of the step: away from SSP nodes and clamps
+        if np.min(np.abs(la - math.log10(a))) < 1e-4 or np.min(np.abs(mz - z)) < 1e-4:
+            continue
+        if any(abs(gpu[k][i]) < 1e-2 * maxg[k] for k in GRAD_KEYS):
+            continue
+        one = p.subset(np.array([i]))
+
+        def spec(field=None, val=None, vv=v):
+            q = one if field is None else one.replace(**{field: [val]})
+            qq = synth.Particles(*[a_.astype(np.float64) for a_ in q.arrays()])
+            return O.particle_spectra(qq, np.array([0]), np.array([vv]), cfg)[0]
+
+        base = spec()
+        for k, h, mk in (("mass", 1e-6 * m, lambda d: spec("mass", m + d)),
+                         ("age", 1e-6, lambda d: spec("age", a + d)),
+                         ("met", 1e-6, lambda d: spec("met", z + d)),
+                         ("vlos", 1e-4, lambda d: spec(vv=v + d))):
+            dl = _fd_delta_L(cfg, G, int(key[i]), mk(h) - base, mk(-h) - base)
+            fd = dl / (2 * h)
+            rel = abs(gpu[k][i] - fd) / abs(fd)
+            worst[k] = max(worst[k], rel)
+            assert rel <= 1e-4, (k, i, gpu[k][i], fd)
+        checked += 1
+    log(f"FD: {checked} particles, worst relative error per parameter {worst}")
+    assert checked >= min(n_check, 20)
+
+
+def _oracle_target(w, workers):
+    pt, ang = synth.differentiation_target_params(w.particles)
+    cfg_t = O.config_from_workload(w)
+    cfg_t.angles_rad = tuple(math.radians(a) for a in ang)
+    return O.forward(pt, cfg_t, workers=workers)["cube"].astype(np.float32)
+
+
+def test_small_loss_gradient_vs_oracle_and_fd():
+    w = _small_workload(n=4000, seed=8)
+    cfg = O.config_from_workload(w)
+    target = _oracle_target(w, 1)
+    fo = O.forward(w.particles, cfg)
+    G = O.loss_grad_cube(fo["cube"], target, cfg)
+    ref = O.adjoint(w.particles, cfg, G, fo)
+    # GPU: the whole loss path on the device (forward, residual, adjoint PSF/LSF, backward)
+    import torch
+    from paper_2412_08265_amd import ops
+    gal = ops.DeviceGalaxy.from_host(w.particles)
+    ssp = ops.DeviceSSP.from_grid(w.ssp)
+    fw = ops.Forward(gal, ops.Observation.from_workload(w), ssp)
+    buf = fw()
+    resid = buf.cube - torch.from_numpy(target.reshape(w.ny, w.nx, w.n_tel)).cuda()
+    Gd = torch.empty_like(resid)
+    ops.rubix_psf_lsf([fw.job], [resid.contiguous()], [Gd], fw.ws)
+    out = ops.cube_backward(fw, Gd)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    _compare(g, ref, 1e-4, "small-loss")
+    _fd_check(w, cfg, fo, G, g, n_check=40)
+
+
+def test_autograd_function_matches_direct_calls():
+    import torch
+    from paper_2412_08265_amd import ops
+    w = _small_workload(n=2500, seed=4)
+    dev = "cuda"
+    t = {f: torch.from_numpy(getattr(w.particles, f)).to(dev) for f in ops.FIELDS}
+    for f in ("vx", "vy", "vz", "mass", "age", "met"):
+        t[f].requires_grad_(True)
+    angles = torch.tensor([math.radians(a) for a in w.angles_deg], dtype=torch.float64,
+                          requires_grad=True)
+    obs = ops.Observation.from_workload(w)
+    ssp = ops.DeviceSSP.from_grid(w.ssp)
+    cube = ops.RubixCube.apply(*[t[f] for f in ops.FIELDS], angles, obs, ssp)
+    target = torch.zeros_like(cube)
+    loss = 0.5 * ((cube - target) ** 2).sum()
+    loss.backward()
+    # direct path
+    gal = ops.DeviceGalaxy.from_host(w.particles)
+    fw = ops.Forward(gal, obs, ssp)
+    buf = fw()
+    G = torch.empty_like(buf.cube)
+    ops.rubix_psf_lsf([fw.job], [buf.cube.contiguous()], [G], fw.ws)
+    out = ops.cube_backward(fw, G)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(t["mass"].grad.cpu().numpy(), out["mass"].cpu().numpy())
+    np.testing.assert_array_equal(t["age"].grad.cpu().numpy(), out["age"].cpu().numpy())
+    np.testing.assert_array_equal(t["vz"].grad.cpu().numpy(), out["vel"][2].cpu().numpy())
+    np.testing.assert_array_equal(angles.grad.numpy(), out["angles"].cpu().numpy())
+    assert t["x"].grad is None
+
+
+def test_differentiation_workload_full_size():
+    """1e6 particles, 50x50x3000 cube, loss against the oracle's cube of perturbed parameters
+    (masses +10 %, ages +0.5 Gyr, [M/H] +0.1, inclination +5 deg): GPU gradient vs the oracle's
+    analytic gradient (max-norm over 4000 sampled particles, angles) and vs FP64 central finite
+    differences on 64 sampled particles."""
+    import time
+    import torch
+    from paper_2412_08265_amd import ops
+    w = synth.medium_workload()
+    cfg = O.config_from_workload(w)
+    log(f"C5: oracle target ({WORKERS} workers)")
+    target = _oracle_target(w, WORKERS)
+    log("C5: oracle forward")
+    fo = O.forward(w.particles, cfg, workers=WORKERS)
+    G = O.loss_grad_cube(fo["cube"], target, cfg)
+    log("C5: GPU forward + backward")
+    gal = ops.DeviceGalaxy.from_host(w.particles)
+    ssp = ops.DeviceSSP.from_grid(w.ssp)
+    fw = ops.Forward(gal, ops.Observation.from_workload(w), ssp)
+    tgt = torch.from_numpy(target.reshape(w.ny, w.nx, w.n_tel)).cuda()
+    buf = fw()
+    Gd = torch.empty_like(buf.cube)
+    ops.rubix_psf_lsf([fw.job], [(buf.cube - tgt).contiguous()], [Gd], fw.ws)
+    out = ops.cube_backward(fw, Gd)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    rng = np.random.default_rng(1)
+    sub = rng.choice(w.particles.n, 4000, replace=False)
+    log("C5: oracle adjoint on 4000 sampled particles")
+    ref = O.adjoint(w.particles, cfg, G, fo, idx=sub)
+    gs = {k: g[k][sub] for k in GRAD_KEYS}
+    gs["vel"] = g["vel"][:, sub]
+    # angles: the full sum needs every particle; compare the oracle's full gradient
+    log("C5: oracle adjoint (all particles) for the angle gradient")
+    ref_all = O.adjoint(w.particles, cfg, G, fo, chunk=256, workers=WORKERS)
+    gs["angles"] = g["angles"]
+    ref["angles"] = ref_all["angles"]
+    _compare(gs, ref, 1e-4, "C5")
+    for k in GRAD_KEYS:
+        e = np.abs(g[k] - ref_all[k]).max() / np.abs(ref_all[k]).max()
+        log(f"C5 full-vector d{k}: max-norm rel err {e:.3e}")
+        assert e <= 1e-4
+    _fd_check(w, cfg, fo, G, g, n_check=64, seed=2)

@@ -1,0 +1,222 @@
+"""Parity of the HIP forward path (through the C ABI) with the FP64 oracle on the same seeded
+inputs: spaxel keys, permutation and segment offsets bit-exact; vlos bit-exact (FP64 rounded to
+FP32 on both sides); cube voxels within 1e-5 of the cube's maximum."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2412_08265_amd import synth
+from tests.helpers import WORKERS, assert_cube_close, gpu_forward, log, oracle_rows_parallel
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_rotate_bin(w, g, fo=None):
+    cfg = O.config_from_workload(w)
+    fo = fo or O.forward(w.particles, cfg, with_cube=False)
+    np.testing.assert_array_equal(g["key"], fo["key"])
+    np.testing.assert_array_equal(g["perm"], fo["perm"])
+    np.testing.assert_array_equal(g["seg_off"], fo["seg_off"])
+    np.testing.assert_array_equal(g["vlos"], fo["vlos"].astype(np.float32))
+    return fo
+
+
+def _workload(p, nx=12, ny=10, s=0.75, angles=(60.0, 0.0, 0.0), ssp=None, tel=None,
+              psf=0.0, lsf=0.0, name="custom"):
+    ssp = ssp or synth.cached_ssp(8, 5, 3600.0, 7.615230460921844, 500)
+    tel = tel or (ssp.lam_start, ssp.lam_step, ssp.n_lam)
+    return synth.Workload(name, p, angles, nx, ny, s, tel[0], tel[1], tel[2], ssp, psf, lsf)
+
+
+def test_tiny_forward_matches_oracle():
+    w = synth.tiny_workload()
+    log("tiny: 1000 particles, 16x16x500")
+    _, g = gpu_forward(w)
+    cfg = O.config_from_workload(w)
+    fo = O.forward(w.particles, cfg)
+    _check_rotate_bin(w, g, fo)
+    assert_cube_close(g["cube_raw"], fo["cube_raw"], what="tiny cube_raw")
+    assert_cube_close(g["cube"], fo["cube"], what="tiny cube")
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 4095, 4096, 4097, 20011])
+def test_ragged_particle_counts(n):
+    p = synth.make_galaxy(max(n, 1), seed=100 + n).subset(slice(0, n))
+    w = _workload(p, tel=(3650.3, 5.1, 611), psf=1.3, lsf=6.0)
+    log(f"ragged n={n}")
+    _, g = gpu_forward(w)
+    cfg = O.config_from_workload(w)
+    fo = O.forward(p, cfg)
+    _check_rotate_bin(w, g, fo)
+    if n == 0:
+        assert np.all(g["cube_raw"] == 0) and np.all(g["cube"] == 0)
+    else:
+        assert_cube_close(g["cube_raw"], fo["cube_raw"], what=f"n={n} cube_raw")
+        assert_cube_close(g["cube"], fo["cube"], what=f"n={n} cube")
+
+
+def test_edge_particles_and_outside_field():
+    """Particles exactly on spaxel edges and on the field border (power-of-two spaxels so the
+    edges are exact), plus particles far outside."""
+    nx, ny, s = 8, 6, 0.5
+    ex = (np.arange(nx + 1) - nx / 2.0) * s
+    ey = (np.arange(ny + 1) - ny / 2.0) * s
+    xs, ys = np.meshgrid(ex, ey)
+    xs, ys = xs.ravel(), ys.ravel()
+    xs = np.concatenate([xs, np.nextafter(xs.astype(np.float32), np.float32(-np.inf)), [1e3, -1e3]])
+    ys = np.concatenate([ys, np.nextafter(ys.astype(np.float32), np.float32(np.inf)), [0, 0]])
+    n = xs.size
+    rng = np.random.default_rng(0)
+    f = lambda a: np.asarray(a, dtype=np.float32)
+    p = synth.Particles(f(xs), f(ys), f(np.zeros(n)), f(rng.normal(0, 100, n)),
+                        f(rng.normal(0, 100, n)), f(rng.normal(0, 100, n)),
+                        f(10 ** rng.uniform(4, 6, n)), f(rng.uniform(0.1, 13, n)),
+                        f(rng.uniform(-2, 0.3, n)))
+    w = _workload(p, nx=nx, ny=ny, s=s, angles=(0.0, 0.0, 0.0))
+    _, g = gpu_forward(w)
+    fo = _check_rotate_bin(w, g)
+    assert (fo["key"] == nx * ny).sum() >= nx + ny
+    assert_cube_close(g["cube_raw"], O.forward(p, O.config_from_workload(w))["cube_raw"],
+                      what="edge cube_raw")
+
+
+def test_three_pass_sort_large_grid():
+    """300 x 300 spaxels: keys need 17 bits, i.e. three 8-bit radix passes."""
+    p = synth.make_galaxy(200_000, seed=77)
+    ssp = synth.cached_ssp(4, 3, 5000.0, 10.0, 40)
+    w = _workload(p, nx=300, ny=300, s=0.1, ssp=ssp)
+    log("300x300 grid, 2e5 particles")
+    _, g = gpu_forward(w)
+    _check_rotate_bin(w, g)
+
+
+def test_medium_full_size_matches_oracle():
+    """The 1e6-particle workload (50x50x3000, SSP 100x12x3000, PSF 1.5 spx, LSF 2.5 A) in full."""
+    w = synth.medium_workload()
+    log("medium: GPU forward")
+    _, g = gpu_forward(w)
+    cfg = O.config_from_workload(w)
+    log(f"medium: oracle forward on {WORKERS} workers")
+    fo = O.forward(w.particles, cfg, workers=WORKERS)
+    log("medium: compare")
+    _check_rotate_bin(w, g, fo)
+    assert_cube_close(g["cube_raw"], fo["cube_raw"], what="medium cube_raw")
+    assert_cube_close(g["cube"], fo["cube"], what="medium cube")
+
+
+def test_large_full_size_sampled_spaxels():
+    """The 1e7-particle workload (150x150x4563): keys/perm/seg_off in full, bit-exact; cube rows
+    of sampled spaxels (the two heaviest, two split into exactly 2 work chunks, 40 random) from
+    the oracle one spaxel at a time."""
+    w = synth.large_workload()
+    log("large: GPU forward")
+    _, g = gpu_forward(w)
+    cfg = O.config_from_workload(w)
+    log("large: oracle rotate/bin")
+    fo = O.forward(w.particles, cfg, with_cube=False)
+    _check_rotate_bin(w, g, fo)
+    cnt = np.diff(fo["seg_off"])
+    order = np.argsort(-cnt, kind="stable")
+    two = np.flatnonzero((cnt > 2048) & (cnt <= 4096))[:2]
+    rng = np.random.default_rng(3)
+    rand = rng.choice(np.flatnonzero(cnt > 0), 40, replace=False)
+    spx = list(dict.fromkeys([int(s) for s in np.r_[order[:2], two, rand]]))
+    log(f"large: oracle rows for {len(spx)} spaxels (max count {cnt[spx].max()})")
+    ref = oracle_rows_parallel(w.particles, cfg, fo, spx)
+    got = g["cube_raw"][spx]
+    err = np.abs(got - ref).max(axis=1) / np.abs(ref).max()
+    log(f"large: worst sampled row error {err.max():.3e} (global scale = sampled max)")
+    assert err.max() <= 1e-5
+    # properties at full size: empty spaxels are zero, cube is non-negative (templates > 0)
+    assert np.all(g["cube_raw"][cnt == 0] == 0)
+    assert g["cube_raw"].min() >= 0
+
+
+def test_deterministic_and_linear_in_mass():
+    w = synth.medium_workload(n=200_000)
+    _, g1 = gpu_forward(w)
+    _, g2 = gpu_forward(w)
+    np.testing.assert_array_equal(g1["cube_raw"], g2["cube_raw"])
+    np.testing.assert_array_equal(g1["cube"], g2["cube"])
+    p2 = w.particles.replace(mass=w.particles.mass.astype(np.float64) * 2.0)
+    w2 = synth.Workload(w.name, p2, w.angles_deg, w.nx, w.ny, w.spaxel_kpc, w.tel_start,
+                        w.tel_step, w.n_tel, w.ssp, w.psf_sigma_spx, w.lsf_sigma_A)
+    _, g3 = gpu_forward(w2)
+    np.testing.assert_array_equal(g3["cube_raw"], 2 * g1["cube_raw"])
+
+
+def test_psf_lsf_on_seeded_random_cube():
+    """rubix_psf_lsf alone on a seeded random cube vs the oracle's convolution."""
+    import torch
+    from paper_2412_08265_amd import ops
+    rng = np.random.default_rng(11)
+    for (ny, nx, nl, psf, lsf, step) in [(37, 45, 700, 2.0, 2.7, 1.25), (5, 300, 130, 0.7, 0.0, 1.0),
+                                         (150, 9, 257, 0.0, 30.0, 1.25), (3, 4, 50, 0.0, 0.0, 1.0)]:
+        c = rng.normal(size=(ny, nx, nl)).astype(np.float32)
+        obs = ops.Observation((0, 0, 0), nx, ny, 1.0, 5000.0, step, nl, psf, lsf)
+        buf = ops.JobBuffers.allocate(0, obs)
+        gal = ops.DeviceGalaxy({f: torch.empty(0, dtype=torch.float32, device="cuda")
+                                for f in ops.FIELDS})
+        job = ops.make_job(gal, obs, buf)
+        ws = ops.workspace(ops.rubix_workspace_size([job]))
+        cin = torch.from_numpy(c).cuda()
+        cout = torch.empty_like(cin)
+        ops.rubix_psf_lsf([job], [cin], [cout], ws)
+        torch.cuda.synchronize()
+        ssp = synth.cached_ssp(3, 3, 5000.0, step, 10)
+        cfg = O.OracleConfig((0, 0, 0), nx, ny, 1.0, 5000.0, step, nl, ssp.log_age_nodes,
+                             ssp.met_nodes, ssp.lam_start, ssp.lam_step, ssp.flux, psf, lsf)
+        ref = O.psf_lsf(c.reshape(ny * nx, nl).astype(np.float64), cfg)
+        assert_cube_close(cout.cpu().numpy().reshape(ny * nx, nl), ref, tol=2e-6,
+                          what=f"psf/lsf {ny}x{nx}x{nl} psf={psf} lsf={lsf}")
+
+
+def test_batch_equals_single_calls():
+    """Jobs batched into one call give bitwise the results of separate calls."""
+    import torch
+    from paper_2412_08265_amd import ops
+    ws_list = [synth.medium_workload(n=30_000 + 7000 * k, seed=50 + k) for k in range(3)]
+    ws_list[1] = synth.Workload("b", ws_list[1].particles, (30.0, 10.0, 5.0), 21, 17, 1.7,
+                                3700.0, 2.5, 1111, ws_list[1].ssp, 0.0, 4.0)
+    ssp = ops.DeviceSSP.from_grid(ws_list[0].ssp)
+    singles = [gpu_forward(w)[1] for w in ws_list]
+    gals = [ops.DeviceGalaxy.from_host(w.particles) for w in ws_list]
+    obss = [ops.Observation.from_workload(w) for w in ws_list]
+    bufs = [ops.JobBuffers.allocate(g.n, o) for g, o in zip(gals, obss)]
+    jobs = [ops.make_job(g, o, b) for g, o, b in zip(gals, obss, bufs)]
+    ws = ops.workspace(ops.rubix_workspace_size(jobs, ssp))
+    ops.rubix_rotate_bin(jobs, ws)
+    ops.rubix_cube(jobs, ssp, ws)
+    ops.rubix_psf_lsf(jobs, [b.cube_raw for b in bufs], [b.cube for b in bufs], ws)
+    torch.cuda.synchronize()
+    for s, b in zip(singles, bufs):
+        np.testing.assert_array_equal(s["perm"], b.perm.cpu().numpy())
+        np.testing.assert_array_equal(s["cube_raw"].ravel(), b.cube_raw.cpu().numpy().ravel())
+        np.testing.assert_array_equal(s["cube"].ravel(), b.cube.cpu().numpy().ravel())
+
+
+def test_shifted_line_and_rest_frame_invariants():
+    """Single particles: at rest the cube is m * template (identical grids); a narrow line moves
+    to lam (1 + v/c); total flux is conserved within the bound the oracle pins."""
+    import torch
+    ssp = synth.make_line_ssp(5000.0, 0.5, 4000, 6000.0, 0.6)
+    f = lambda a: np.asarray(a, dtype=np.float32)
+    for v in (0.0, 250.0, -420.0):
+        p = synth.Particles(f([0.1]), f([0.1]), f([0]), f([0]), f([0]), f([v]), f([3.0]),
+                            f([2.0]), f([-0.5]))
+        w = _workload(p, nx=2, ny=2, s=1.0, angles=(0.0, 0.0, 0.0), ssp=ssp)
+        _, g = gpu_forward(w)
+        spec = g["cube_raw"][g["key"][0]]
+        lam = 5000.0 + 0.5 * np.arange(4000)
+        expect = 6000.0 * (1 + v / O.C_KMS)
+        assert abs(lam[np.argmax(spec)] - expect) <= 0.25 + 1e-6
+        if v == 0.0:
+            np.testing.assert_allclose(spec, 3.0 * ssp.flux[0, 0].astype(np.float64),
+                                       rtol=2e-6, atol=1e-6 * ssp.flux.max() * 3)
+        else:
+            S = ssp.flux[0, 0].astype(np.float64)
+            beta = v / O.C_KMS
+            bound = 2 * abs(beta) * S.max() / S.sum() + 4 * beta * beta
+            assert abs(spec.sum() - 3.0 * S.sum()) / (3.0 * S.sum()) <= bound + 1e-6
