@@ -37,7 +37,7 @@ C_KMS = 299792.458  # km/s
 __all__ = [
     "C_KMS", "rotation_matrix", "rotation_matrix_derivs", "rotate_positions", "los_velocity",
     "spaxel_keys", "sort_by_key", "ssp_cell", "ssp_weights", "interp_templates",
-    "doppler_index", "resample_linear", "particle_spectra", "cube_raw", "gaussian_weights",
+    "doppler_index", "node_decision", "resample_linear", "particle_spectra", "cube_raw", "gaussian_weights",
     "convolve_axis", "psf_lsf", "forward", "loss", "loss_grad_cube", "adjoint",
     "OracleConfig", "config_from_workload",
 ]
@@ -229,14 +229,46 @@ def doppler_index(lam_tel: np.ndarray, vlos: np.ndarray, z_sys: float, ssp_start
     return (lam_rest - ssp_start) / ssp_step
 
 
-def resample_linear(S: np.ndarray, q: np.ndarray) -> np.ndarray:
+def node_decision(lam_tel: np.ndarray, vlos: np.ndarray, z_sys: float, ssp_start: float,
+                  ssp_step: float, n_nodes: int):
+    """Integer SSP node index k_ij = floor(q_ij) and the in-range mask, decided in FP32 the way
+    the GPU kernels decide them, so that both sides put every bin in the same node interval.
+
+    The fraction inside the interval stays FP64 (q - k); only the integer decision is shared.
+    The split form: q = Qi_j + t with Q_j = (lam_j/(1+z) - lam0)/dlam (FP64), Qi_j = floor(Q_j),
+    t = fl32(fl32(Q_j - Qi_j) - fl32(lam_j) * g) rounded once (a fused multiply-add), where
+    g = fl32(beta/(1+beta) / ((1+z) dlam)) and beta = fl32(v_los)/c. In range iff k >= 0 and
+    (k < n-1, or k = n-1 with t's fraction exactly 0)."""
+    lam = np.asarray(lam_tel, dtype=np.float64)
+    Q = (lam / (1.0 + z_sys) - ssp_start) / ssp_step
+    Qi = np.floor(Q)
+    Qf = (Q - Qi).astype(np.float32).astype(np.float64)
+    lam32 = lam.astype(np.float32).astype(np.float64)
+    beta = np.asarray(vlos, dtype=np.float32).astype(np.float64) / C_KMS
+    g32 = (beta / (1.0 + beta) / ((1.0 + z_sys) * ssp_step)).astype(np.float32).astype(np.float64)
+    # the product of two FP32 values is exact in FP64 and so is the difference here: rounding it
+    # once to FP32 reproduces a fused multiply-add
+    t = (Qf[None, :] - lam32[None, :] * g32[:, None]).astype(np.float32)
+    fl = np.floor(t)
+    frac = t - fl
+    k = Qi[None, :].astype(np.int64) + fl.astype(np.int64)
+    valid = (k >= 0) & ((k < n_nodes - 1) | ((k == n_nodes - 1) & (frac == 0)))
+    return k, valid
+
+
+def resample_linear(S: np.ndarray, q: np.ndarray, k: Optional[np.ndarray] = None,
+                    valid: Optional[np.ndarray] = None) -> np.ndarray:
     """Piecewise-linear interpolation of row i of S at fractional node positions q[i, :];
-    zero where q < 0 or q > n-1. The last node maps to (k = n-2, tau = 1)."""
+    zero where q < 0 or q > n-1. The last node maps to (k = n-2, tau = 1).
+
+    k / valid: optional integer interval and range decision (see node_decision); by default
+    k = floor(q) and valid = 0 <= q <= n-1 in FP64."""
     n = S.shape[1]
-    valid = (q >= 0.0) & (q <= n - 1)
-    qc = np.where(valid, q, 0.0)
-    k = np.minimum(np.floor(qc).astype(np.int64), n - 2)
-    tau = qc - k
+    if k is None:
+        valid = (q >= 0.0) & (q <= n - 1)
+        k = np.floor(np.where(valid, q, 0.0)).astype(np.int64)
+    k = np.where(valid, np.minimum(k, n - 2), 0)
+    tau = np.where(valid, q - k, 0.0)
     s0 = np.take_along_axis(S, k, axis=1)
     s1 = np.take_along_axis(S, k + 1, axis=1)
     return np.where(valid, (1.0 - tau) * s0 + tau * s1, 0.0)
@@ -252,8 +284,10 @@ def particle_spectra(p, idx: np.ndarray, vlos: np.ndarray, cfg: OracleConfig) ->
     ja, jz, ta, tz, w, _, _ = ssp_weights(age, met, cfg.log_age_nodes, cfg.met_nodes)
     S = interp_templates(cfg.ssp_flux, ja, jz, w)
     q = doppler_index(cfg.tel_lambda(), v, cfg.z_sys, cfg.ssp_lam_start, cfg.ssp_lam_step)
+    k, valid = node_decision(cfg.tel_lambda(), v, cfg.z_sys, cfg.ssp_lam_start,
+                             cfg.ssp_lam_step, S.shape[1])
     J = 1.0 / ((1.0 + cfg.z_sys) * (1.0 + v / C_KMS))
-    return (cfg.flux_scale * mass * J)[:, None] * resample_linear(S, q)
+    return (cfg.flux_scale * mass * J)[:, None] * resample_linear(S, q, k, valid)
 
 
 # --------------------------------------------------------------------------------------------------
@@ -435,10 +469,9 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
         beta = v / C_KMS
         ja, jz, ta, tz, w, ina, inz = ssp_weights(age, met, la_nodes, mz_nodes)
         q = doppler_index(lam, v, cfg.z_sys, cfg.ssp_lam_start, cfg.ssp_lam_step)
-        valid = (q >= 0.0) & (q <= nl - 1)
-        qc = np.where(valid, q, 0.0)
-        k = np.minimum(np.floor(qc).astype(np.int64), nl - 2)
-        tau = qc - k
+        k, valid = node_decision(lam, v, cfg.z_sys, cfg.ssp_lam_start, cfg.ssp_lam_step, nl)
+        k = np.where(valid, np.minimum(k, nl - 2), 0)
+        tau = np.where(valid, q - k, 0.0)
         g = G[key[ii]]                                   # [m, n_tel]
         corners = [(ja, jz), (ja, jz + 1), (ja + 1, jz), (ja + 1, jz + 1)]
         X = np.zeros((ii.shape[0], 4))

@@ -1,15 +1,15 @@
 // Adjoint of the cube (gradients through the pipeline: arXiv:2412.08265, Abstract and Sec. 1).
 //
-// Given G = dL/dC_raw, each in-field particle i of spaxel s needs five dot products over the
-// telescope bins j of its spaxel's gradient row:
-//   X_c = sum_j G[s,j] Tlin_c(q_ij)                  (c = the 4 SSP corners)
-//   Y   = sum_j G[s,j] lam_j sum_c w_c dT_c(q_ij)    (dT_c = right-cell slope per node)
-// from which the per-particle gradients follow in closed form (k_bwd_final).
+// Given G = dL/dC_raw, each in-field particle i of spaxel s needs four dot products over the
+// telescope bins j of its spaxel's gradient row (Slin = bilinear SSP spectrum, linear in lambda):
+//   s_m = sum_j G[s,j] Slin_i(q_ij)                        (mass, and the Jacobian term of v_los)
+//   s_a = sum_j G[s,j] dSlin_i/dt_a(q_ij)                  (age direction of the bilinear cell)
+//   s_z = sum_j G[s,j] dSlin_i/dt_z(q_ij)                  (metallicity direction)
+//   Y   = sum_j G[s,j] lam_j dSlin_i/dq(q_ij)              (right-cell slope per node)
+// from which the per-particle gradients follow in closed form (k_bwd_final). The directional
+// derivatives are formed per bin from differences of the FP32 template values at each node
+// (exact or nearly so) before they meet G, so no sum is a difference of nearly equal sums.
 //
-// Layout: one wave per particle; its 64 lanes stride over the bins, accumulate FP32 partials
-// (at most n_tel/64 terms each) and reduce across the wave in FP64. Consecutive particles of a
-// work item mostly share a spaxel, so the G row stays in L1/L2. The rest is a per-particle
-// streaming pass and an FP64 tree over particles for the angle gradient, both in fixed order.
 #include "rubix_internal.h"
 
 namespace rubix {
@@ -57,7 +57,9 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
       if (p >= n_in) break;
       const PrepRec r = J.prep[p];
       const float *__restrict__ G = J.grad_raw + (int64_t)r.spaxel * J.n_tel;
-      float x0 = 0.f, x1 = 0.f, x2 = 0.f, x3 = 0.f, y = 0.f;
+      const float w0 = r.a[0], w1 = r.a[1], w2 = r.a[2], w3 = r.a[3];
+      const float ta = w2 + w3, tz = w1 + w3;   // bilinear fractions recovered from the weights
+      float sm = 0.f, sa = 0.f, sz = 0.f, y = 0.f;
       for (int jb = lane; jb < J.n_tel; jb += 64) {
         const float4 bt = J.bintab[jb];
         const float tq = fmaf(-bt.z, r.g, bt.y);
@@ -69,22 +71,29 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
           const int kk = min(k, nl - 2);
           const float tt = (k > kk) ? 1.f : tau;
           const float *b = flux + r.row + kk;
+          const float p0 = b[0], q0 = b[1], p1 = b[o1], q1 = b[o1 + 1];
+          const float p2 = b[o2], q2 = b[o2 + 1], p3 = b[o3], q3 = b[o3 + 1];
+          const float d0 = q0 - p0, d1 = q1 - p1, d2 = q2 - p2, d3 = q3 - p3;
+          const float S = w0 * fmaf(tt, d0, p0) + w1 * fmaf(tt, d1, p1) +
+                          w2 * fmaf(tt, d2, p2) + w3 * fmaf(tt, d3, p3);
+          const float dS = w0 * d0 + w1 * d1 + w2 * d2 + w3 * d3;
+          // age direction: (1-tz)(Tlin_2 - Tlin_0) + tz (Tlin_3 - Tlin_1)
+          const float ea = p2 - p0, fa = q2 - q0, eb = p3 - p1, fb = q3 - q1;
+          const float Aa = (1.f - tz) * fmaf(tt, fa - ea, ea) + tz * fmaf(tt, fb - eb, eb);
+          // metallicity direction: (1-ta)(Tlin_1 - Tlin_0) + ta (Tlin_3 - Tlin_2)
+          const float ez = p1 - p0, fz = q1 - q0, ez2 = p3 - p2, fz2 = q3 - q2;
+          const float Az = (1.f - ta) * fmaf(tt, fz - ez, ez) + ta * fmaf(tt, fz2 - ez2, ez2);
           const float g = G[jb];
-          const float d0 = b[1] - b[0], d1 = b[o1 + 1] - b[o1];
-          const float d2 = b[o2 + 1] - b[o2], d3 = b[o3 + 1] - b[o3];
-          x0 = fmaf(g, fmaf(tt, d0, b[0]), x0);
-          x1 = fmaf(g, fmaf(tt, d1, b[o1]), x1);
-          x2 = fmaf(g, fmaf(tt, d2, b[o2]), x2);
-          x3 = fmaf(g, fmaf(tt, d3, b[o3]), x3);
-          const float sp = r.a[0] * d0 + r.a[1] * d1 + r.a[2] * d2 + r.a[3] * d3;
-          y = fmaf(g * bt.z, sp, y);
+          sm = fmaf(g, S, sm);
+          sa = fmaf(g, Aa, sa);
+          sz = fmaf(g, Az, sz);
+          y = fmaf(g * bt.z, dS, y);
         }
       }
-      const double X0 = wave_sum(x0), X1 = wave_sum(x1), X2 = wave_sum(x2), X3 = wave_sum(x3);
-      const double Y = wave_sum(y);
+      const double Sm = wave_sum(sm), Sa = wave_sum(sa), Sz = wave_sum(sz), Y = wave_sum(y);
       if (lane == 0) {
-        double *d = J.dots + p * 5;
-        d[0] = X0; d[1] = X1; d[2] = X2; d[3] = X3; d[4] = Y;
+        double *d = J.dots + p * 4;
+        d[0] = Sm; d[1] = Sa; d[2] = Sz; d[3] = Y;
       }
     }
   }
@@ -123,35 +132,19 @@ __global__ __launch_bounds__(kFinThreads) void k_bwd_final(const Table *__restri
         const bool in_z = (met >= S.met[0]) && (met <= S.met[nz - 1]);
         const int ja = cell_of_b(S.age_thr, na, age);
         const int jz = cell_of_b(S.met, nz, met);
-        double ta, tz;
-        if (!(age > S.age_thr[0])) ta = 0.0;
-        else if (age >= S.age_thr[na - 1]) ta = 1.0;
-        else ta = fmin(1.0, fmax(0.0, (log10(age) - S.log_age[ja]) /
-                                          (S.log_age[ja + 1] - S.log_age[ja])));
-        if (!(met > S.met[0])) tz = 0.0;
-        else if (met >= S.met[nz - 1]) tz = 1.0;
-        else tz = fmin(1.0, fmax(0.0, (met - S.met[jz]) / (S.met[jz + 1] - S.met[jz])));
-        const double *X = J.dots + i * 5;
-        const double x0 = X[0], x1 = X[1], x2 = X[2], x3 = X[3], Y = X[4];
-        const double w0 = (1 - ta) * (1 - tz), w1 = (1 - ta) * tz, w2 = ta * (1 - tz), w3 = ta * tz;
-        const double wx = w0 * x0 + w1 * x1 + w2 * x2 + w3 * x3;
+        const double *X = J.dots + i * 4;
+        const double sm = X[0], sa = X[1], sz = X[2], Y = X[3];
         const double beta = v / kCkmsB;
         const double opz = 1.0 + J.z_sys;
         const double jac = 1.0 / (opz * (1.0 + beta));
         const double fs = J.flux_scale;
         const double A = fs * m * jac;
-        gm = (float)(fs * jac * wx);
-        if (in_a) {
-          const double dwa = -(1 - tz) * x0 - tz * x1 + (1 - tz) * x2 + tz * x3;
-          ga = (float)(A * dwa / (S.log_age[ja + 1] - S.log_age[ja]) / (age * 2.302585092994046));
-        }
-        if (in_z) {
-          const double dwz = -(1 - ta) * x0 + (1 - ta) * x1 - ta * x2 + ta * x3;
-          gz = (float)(A * dwz / (S.met[jz + 1] - S.met[jz]));
-        }
+        gm = (float)(fs * jac * sm);
+        if (in_a) ga = (float)(A * sa / (S.log_age[ja + 1] - S.log_age[ja]) / (age * 2.302585092994046));
+        if (in_z) gz = (float)(A * sz / (S.met[jz + 1] - S.met[jz]));
         const double dJ = -jac / (1.0 + beta);
         const double dq = -1.0 / (opz * (1.0 + beta) * (1.0 + beta) * S.lam_step);
-        const double dbeta = fs * m * (dJ * wx + jac * dq * Y);
+        const double dbeta = fs * m * (dJ * sm + jac * dq * Y);
         const double dv = dbeta / kCkmsB;
         gv = (float)dv;
         const double vx = J.vx[j], vy = J.vy[j], vz = J.vz[j];

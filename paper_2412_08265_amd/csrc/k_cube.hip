@@ -4,14 +4,20 @@
 // Data flow (all on the caller's stream):
 //   k_prep    one thread per sorted in-field particle: gathers (mass, age, [M/H], v_los) through
 //             perm, finds the SSP cell, and writes a 32-byte record {flux row, Doppler slope g,
-//             4 corner weights} in spaxel order.
+//             4 corner weights, spaxel, node-offset bounds} in spaxel order.
 //   k_chunks  one block per job: splits every spaxel's particle range into chunks of at most
 //             kCubeChunk particles (load balance for dense central spaxels); chunks of a spaxel
 //             with several chunks get partial-sum slots.
-//   k_cube    one block per (lambda tile of kCubeTL bins, chunk): lanes own telescope bins and
-//             loop over the chunk's particles, accumulating in registers (no atomics). Blocks are
-//             ordered lambda-tile major, so the blocks resident on one XCD at a time share one
-//             tile's slice of the template grid in that XCD's L2.
+//   k_cube    one block per (lambda tile of at most kCubeMaxTL bins, chunk), particles taken in
+//             batches of kCubeBatch:
+//               phase 1  lanes span SSP nodes: each staged particle's bilinear spectrum
+//                        S_i[n] = sum_c a_ic T_c[n] over the tile's node window goes to LDS
+//                        (four coalesced row loads per node, the template slice sits in L2);
+//               phase 2  lanes span telescope bins: the Doppler-shifted node index and one
+//                        ds_read2 of (S_i[k], S_i[k+1]) give the resampled value, accumulated in
+//                        registers (no atomics).
+//             Blocks are ordered lambda-tile major, so the blocks resident on one XCD at a time
+//             share one tile's slice of the template grid in that XCD's L2.
 //   k_combine sums a multi-chunk spaxel's partial spectra in chunk order (deterministic).
 //
 // Resampling index: for bin centre lam_j the node index of the rest-frame wavelength is
@@ -19,7 +25,8 @@
 //   Q_j = (lam_j/(1+z) - lam0)/dlam,  g = beta/(1+beta) / ((1+z) dlam).
 // Q_j is formed in FP64 per lane and split into an integer and an FP32 fraction; only the small
 // Doppler term lam_j*g is FP32, so q carries an absolute error of ~1e-6 nodes instead of the
-// ~1e-3 that an FP32 lam/(1+beta) would give at 9000 A.
+// ~1e-3 that an FP32 lam/(1+beta) would give at 9000 A. The integer part k = floor(q) is the
+// same FP32 decision in every kernel (forward and adjoint).
 #include "rubix_internal.h"
 
 namespace rubix {
@@ -74,7 +81,21 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__
     r.a[2] = (float)(scale * ta * (1.0 - tz));
     r.a[3] = (float)(scale * ta * tz);
     r.spaxel = J.key[j];
-    r.pad = 0;
+    // floor(q) - floor(Q_j) = floor(fl32(Qf_j - lam_j g)) with Qf_j in [0, 1] and lam_j over the
+    // band: bounded by the band ends, with one node of margin each side for FP32 rounding and one
+    // more below, so that the interval (k-1, k) used at the last SSP node is inside the window
+    const double glo = (double)r.g;
+    const double l0 = (double)(float)J.tel_start;
+    const double l1 = (double)(float)(J.tel_start + (J.n_tel - 1) * J.tel_step);
+    const double e0 = -l0 * glo, e1 = -l1 * glo;
+    const double mn = fmin(e0, e1), mx = fmax(e0, e1);
+    if (isfinite(mn) && isfinite(mx) && mn > -30000.0 && mx < 30000.0) {
+      const int dlo = (int)floor(mn) - 2;
+      const int dhi = (int)floor(mx) + 2;
+      r.lohi = (int32_t)((uint32_t)(dlo & 0xffff) | ((uint32_t)dhi << 16));
+    } else {
+      r.lohi = kLohiBad;
+    }
     J.prep[i] = r;
   }
 }
@@ -126,12 +147,46 @@ __global__ __launch_bounds__(1024) void k_chunks(const Table *__restrict__ T) {
   }
 }
 
-__global__ __launch_bounds__(kCubeTL) void k_cube(const Table *__restrict__ T) {
+// One particle's resampled contribution to bin jb with both taps gathered from the template grid
+// (particles without a bounded node window, and jobs whose telescope grid is much coarser than
+// the SSP grid).
+__device__ __forceinline__ float direct_contrib(const PrepRec &r, const float *__restrict__ flux,
+                                               int nl, int o1, int o2, int o3, int qi, float qf,
+                                               float lamf, bool act) {
+  const float tq = fmaf(-lamf, r.g, qf);
+  const float fl = floorf(tq);
+  const float tau = tq - fl;
+  const int k = qi + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
+  const bool ok = act && (k >= 0) && ((k < nl - 1) || (k == nl - 1 && tau == 0.f));
+  if (!ok) return 0.f;
+  const int kk = min(k, nl - 2);
+  const float tt = (k > kk) ? 1.f : tau;
+  const float *b = flux + r.row + kk;
+  float v = r.a[0] * fmaf(tt, b[1] - b[0], b[0]);
+  v = fmaf(r.a[1], fmaf(tt, b[o1 + 1] - b[o1], b[o1]), v);
+  v = fmaf(r.a[2], fmaf(tt, b[o2 + 1] - b[o2], b[o2]), v);
+  v = fmaf(r.a[3], fmaf(tt, b[o3 + 1] - b[o3], b[o3]), v);
+  return v;
+}
+
+__device__ __forceinline__ void split_index(const JobDev &J, const SspDev &S, int jb, int &qi,
+                                            float &qf, float &lamf) {
+  const double lam = J.tel_start + (double)jb * J.tel_step;
+  const double Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
+  const double Qfl = floor(Q);
+  qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
+  qf = (float)(Q - Qfl);
+  lamf = (float)lam;
+}
+
+__global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__ T) {
+  __shared__ float sbuf[kCubeBatch * kCubeSlot];
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
   const float *__restrict__ flux = S.flux;
   const int nl = S.n_lam;
   const int o1 = nl, o2 = S.n_met * nl, o3 = o2 + nl;
+  const int tid = threadIdx.x;
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_CUBE]; vb += gridDim.x) {
     const int jj = find_job(T, K_CUBE, vb);
     const JobDev &J = jobs[jj];
@@ -140,37 +195,89 @@ __global__ __launch_bounds__(kCubeTL) void k_cube(const Table *__restrict__ T) {
     const int c = (int)(local - (int64_t)tile * J.n_chunk_ub);
     if (c >= J.counts[0]) continue;
     const ChunkRec ch = J.chunks[c];
-    const int jb = tile * kCubeTL + threadIdx.x;
-    const bool act = jb < J.n_tel;
-    const double lam = J.tel_start + (double)jb * J.tel_step;
-    const double Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
-    const double Qfl = floor(Q);
-    const int qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
-    const float qf = (float)(Q - Qfl);
-    const float lamf = (float)lam;
+    const int TL = J.cube_tl;
+    const int j0 = tile * TL;
+    const int jl = min(j0 + TL, J.n_tel) - 1;
+    const int jb = j0 + tid;
+    const bool act = (tid < TL) && (jb < J.n_tel);
+    const bool direct_job = J.cube_direct != 0;
+    int qi, qi0, qil;
+    float qf, lamf, qf_u, lam_u;
+    split_index(J, S, jb, qi, qf, lamf);
+    split_index(J, S, j0, qi0, qf_u, lam_u);     // tile-uniform node index range
+    split_index(J, S, jl, qil, qf_u, lam_u);
+    const int span = qil - qi0;
+    const int lrel = qi - qi0;
     float acc = 0.f, tot = 0.f;
+    int since = 0;
     const PrepRec *__restrict__ prep = J.prep;
-    for (int p = ch.p0; p < ch.p1; ++p) {
-      const PrepRec r = prep[p];
-      const float tq = fmaf(-lamf, r.g, qf);
-      const float fl = floorf(tq);
-      const float tau = tq - fl;
-      const int k = qi + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
-      const bool ok = act && (k >= 0) && ((k < nl - 1) || (k == nl - 1 && tau == 0.f));
-      if (ok) {
-        const int kk = min(k, nl - 2);
-        const float tt = (k > kk) ? 1.f : tau;
-        const float *b = flux + r.row + kk;
-        const float v0 = fmaf(tt, b[1] - b[0], b[0]);
-        const float v1 = fmaf(tt, b[o1 + 1] - b[o1], b[o1]);
-        const float v2 = fmaf(tt, b[o2 + 1] - b[o2], b[o2]);
-        const float v3 = fmaf(tt, b[o3 + 1] - b[o3], b[o3]);
-        acc = fmaf(r.a[0], v0, acc);
-        acc = fmaf(r.a[1], v1, acc);
-        acc = fmaf(r.a[2], v2, acc);
-        acc = fmaf(r.a[3], v3, acc);
+    for (int pb = ch.p0; pb < ch.p1; pb += kCubeBatch) {
+      const int nb = min(kCubeBatch, ch.p1 - pb);
+      // phase 1: node windows of the batch's spectra into LDS
+#pragma unroll
+      for (int b = 0; b < kCubeBatch; ++b) {
+        if (b < nb) {
+          const PrepRec r = prep[pb + b];
+          const int dlo = (int)(int16_t)(r.lohi & 0xffff), dhi = r.lohi >> 16;
+          const int W = span + dhi - dlo + 2;
+          if (!direct_job && r.lohi != kLohiBad && W <= kCubeSlot) {
+            const int n0 = qi0 + dlo;
+            const bool inside = (n0 >= 0) && (n0 + W <= nl);
+            const float *__restrict__ rp = flux + r.row;
+            for (int m = tid; m < W; m += kCubeThreads) {
+              int node = n0 + m;
+              if (!inside) node = min(max(node, 0), nl - 1);
+              float v = r.a[0] * rp[node];
+              v = fmaf(r.a[1], rp[o1 + node], v);
+              v = fmaf(r.a[2], rp[o2 + node], v);
+              v = fmaf(r.a[3], rp[o3 + node], v);
+              sbuf[b * kCubeSlot + m] = v;
+            }
+          }
+        }
       }
-      if (((p - ch.p0) & (kCubeSubsum - 1)) == kCubeSubsum - 1) { tot += acc; acc = 0.f; }
+      __syncthreads();
+      // phase 2: Doppler-shifted linear resampling from the staged spectra
+#pragma unroll
+      for (int b = 0; b < kCubeBatch; ++b) {
+        if (b < nb) {
+          const PrepRec r = prep[pb + b];
+          const int dlo = (int)(int16_t)(r.lohi & 0xffff), dhi = r.lohi >> 16;
+          const int W = span + dhi - dlo + 2;
+          if (!direct_job && r.lohi != kLohiBad && W <= kCubeSlot) {
+            const int n0 = qi0 + dlo;
+            const bool inside = (n0 >= 0) && (n0 + W <= nl);
+            const float tq = fmaf(-lamf, r.g, qf);
+            const float fl = floorf(tq);
+            const float tau = tq - fl;
+            const int fi = (int)fminf(fmaxf(fl, -30000.f), 30000.f);
+            if (inside) {
+              // every node of the window exists: no range test; the clamp only guards lanes
+              // past the end of the band, whose results are discarded
+              const int idx = min(max(lrel + fi - dlo, 0), kCubeSlot - 2);
+              const float s0 = sbuf[b * kCubeSlot + idx];
+              const float s1 = sbuf[b * kCubeSlot + idx + 1];
+              acc += fmaf(tau, s1 - s0, s0);
+            } else {
+              const int k = qi + fi;
+              const bool ok = act && (k >= 0) && ((k < nl - 1) || (k == nl - 1 && tau == 0.f));
+              if (ok) {
+                const int kk = min(k, nl - 2);
+                const float tt = (k > kk) ? 1.f : tau;
+                const int idx = min(max(kk - n0, 0), kCubeSlot - 2);
+                const float s0 = sbuf[b * kCubeSlot + idx];
+                const float s1 = sbuf[b * kCubeSlot + idx + 1];
+                acc += fmaf(tt, s1 - s0, s0);
+              }
+            }
+          } else {
+            acc += direct_contrib(r, flux, nl, o1, o2, o3, qi, qf, lamf, act);
+          }
+        }
+      }
+      since += nb;
+      if (since >= kCubeSubsum) { tot += acc; acc = 0.f; since = 0; }
+      __syncthreads();
     }
     tot += acc;
     if (act) {
@@ -180,7 +287,7 @@ __global__ __launch_bounds__(kCubeTL) void k_cube(const Table *__restrict__ T) {
   }
 }
 
-__global__ __launch_bounds__(kCubeTL) void k_combine(const Table *__restrict__ T) {
+__global__ __launch_bounds__(kCubeThreads) void k_combine(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_COMB]; vb += gridDim.x) {
     const int jj = find_job(T, K_COMB, vb);
@@ -190,7 +297,8 @@ __global__ __launch_bounds__(kCubeTL) void k_combine(const Table *__restrict__ T
     const int e = (int)(local - (int64_t)tile * J.n_comb_ub);
     if (e >= J.counts[1]) continue;
     const CombRec cr = J.combs[e];
-    const int jb = tile * kCubeTL + threadIdx.x;
+    if ((int)threadIdx.x >= J.cube_tl) continue;
+    const int jb = tile * J.cube_tl + threadIdx.x;
     if (jb >= J.n_tel) continue;
     float sum = 0.f;
     for (int q = 0; q < cr.n_slots; ++q) sum += J.partial[(int64_t)(cr.first_slot + q) * J.n_tel + jb];
@@ -213,9 +321,9 @@ hipError_t launch_cube(const Table *dt, const TableHeader &h, int cap, hipStream
   if ((g = grid_for(h.total[K_CHUNK], cap)))
     hipLaunchKernelGGL(k_chunks, dim3(g), dim3(1024), 0, s, dt);
   if ((g = grid_for(h.total[K_CUBE], cap)))
-    hipLaunchKernelGGL(k_cube, dim3(g), dim3(kCubeTL), 0, s, dt);
+    hipLaunchKernelGGL(k_cube, dim3(g), dim3(kCubeThreads), 0, s, dt);
   if ((g = grid_for(h.total[K_COMB], cap)))
-    hipLaunchKernelGGL(k_combine, dim3(g), dim3(kCubeTL), 0, s, dt);
+    hipLaunchKernelGGL(k_combine, dim3(g), dim3(kCubeThreads), 0, s, dt);
   return hipGetLastError();
 }
 

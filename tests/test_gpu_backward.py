@@ -94,11 +94,14 @@ def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0):
             continue
         if any(abs(gpu[k][i]) < 1e-2 * maxg[k] for k in GRAD_KEYS):
             continue
-        one = p.subset(np.array([i]))
+        one = {f: np.asarray(getattr(p, f)[i:i + 1], dtype=np.float64) for f in p.FIELDS}
 
         def spec(field=None, val=None, vv=v):
-            q = one if field is None else one.replace(**{field: [val]})
-            qq = synth.Particles(*[a_.astype(np.float64) for a_ in q.arrays()])
+            # FP64 particle (no rounding of the perturbed value back to FP32)
+            d = dict(one)
+            if field is not None:
+                d[field] = np.array([val], dtype=np.float64)
+            qq = synth.Particles(**d)
             return O.particle_spectra(qq, np.array([0]), np.array([vv]), cfg)[0]
 
         base = spec()
