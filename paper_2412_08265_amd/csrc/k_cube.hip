@@ -4,18 +4,20 @@
 // Data flow (all on the caller's stream):
 //   k_prep    one thread per sorted in-field particle: gathers (mass, age, [M/H], v_los) through
 //             perm, finds the SSP cell, and writes a 32-byte record {flux row, Doppler slope g,
-//             4 corner weights, spaxel, node-offset bounds} in spaxel order.
+//             4 corner weights, spaxel, window flag} in spaxel order.
 //   k_chunks  one block per job: splits every spaxel's particle range into chunks of at most
 //             kCubeChunk particles (load balance for dense central spaxels); chunks of a spaxel
 //             with several chunks get partial-sum slots.
-//   k_cube    one block per (lambda tile of at most kCubeMaxTL bins, chunk), particles taken in
-//             batches of kCubeBatch:
-//               phase 1  lanes span SSP nodes: each staged particle's bilinear spectrum
-//                        S_i[n] = sum_c a_ic T_c[n] over the tile's node window goes to LDS
-//                        (four coalesced row loads per node, the template slice sits in L2);
-//               phase 2  lanes span telescope bins: the Doppler-shifted node index and one
-//                        ds_read2 of (S_i[k], S_i[k+1]) give the resampled value, accumulated in
-//                        registers (no atomics).
+//   k_cube    one block per (lambda tile of kCubeTL bins, chunk); each wave owns 62 consecutive
+//             telescope bins and walks the chunk's particles, kCubeGroup at a time:
+//               stage    lane l computes the particle's bilinear spectrum at SSP node n0 + l,
+//                        S = sum_c a_c T_c[n0 + l] (four coalesced row loads from the template
+//                        slice in L2), into the wave's own 64-float LDS slot; n0 is lane 0's
+//                        shifted node index, so the slot covers both taps of all 62 bins;
+//               resample each lane reads (S[k - n0], S[k - n0 + 1]) with one ds_read2 and
+//                        accumulates the linear interpolant in registers (no atomics).
+//             Slots are private to a wave, so no block barrier is needed; particle records
+//             come through the scalar cache and a group's 16 row loads are in flight together.
 //             Blocks are ordered lambda-tile major, so the blocks resident on one XCD at a time
 //             share one tile's slice of the template grid in that XCD's L2.
 //   k_combine sums a multi-chunk spaxel's partial spectra in chunk order (deterministic).
@@ -81,21 +83,11 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__
     r.a[2] = (float)(scale * ta * (1.0 - tz));
     r.a[3] = (float)(scale * ta * tz);
     r.spaxel = J.key[j];
-    // floor(q) - floor(Q_j) = floor(fl32(Qf_j - lam_j g)) with Qf_j in [0, 1] and lam_j over the
-    // band: bounded by the band ends, with one node of margin each side for FP32 rounding and one
-    // more below, so that the interval (k-1, k) used at the last SSP node is inside the window
-    const double glo = (double)r.g;
-    const double l0 = (double)(float)J.tel_start;
-    const double l1 = (double)(float)(J.tel_start + (J.n_tel - 1) * J.tel_step);
-    const double e0 = -l0 * glo, e1 = -l1 * glo;
-    const double mn = fmin(e0, e1), mx = fmax(e0, e1);
-    if (isfinite(mn) && isfinite(mx) && mn > -30000.0 && mx < 30000.0) {
-      const int dlo = (int)floor(mn) - 2;
-      const int dhi = (int)floor(mx) + 2;
-      r.lohi = (int32_t)((uint32_t)(dlo & 0xffff) | ((uint32_t)dhi << 16));
-    } else {
-      r.lohi = kLohiBad;
-    }
+    // q advances by bin_slope/(1+beta) nodes per telescope bin; when 61 steps stay below 61.9
+    // nodes, the node indices of 62 consecutive bins span at most 63 nodes (0.1 node of margin
+    // is far above the FP32 error of q)
+    const double beff = J.bin_slope / (1.0 + beta);
+    r.fits = (isfinite((double)r.g) && beff > 0.0 && 61.0 * beff <= 61.9) ? 1 : 0;
     J.prep[i] = r;
   }
 }
@@ -147,10 +139,47 @@ __global__ __launch_bounds__(1024) void k_chunks(const Table *__restrict__ T) {
   }
 }
 
-// One particle's resampled contribution to bin jb with both taps gathered from the template grid
-// (particles without a bounded node window, and jobs whose telescope grid is much coarser than
-// the SSP grid).
-__device__ __forceinline__ float direct_contrib(const PrepRec &r, const float *__restrict__ flux,
+typedef __attribute__((address_space(1))) const float GFloat;     // global memory
+
+// The template grid is read through a buffer resource: one uniform descriptor, a per-lane byte
+// offset (VGPR) and a per-particle byte offset (SGPR), so a row load needs no vector address
+// arithmetic; offsets past the end of the grid read 0 instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t flux_rsrc(const SspDev &S) {
+  const uint32_t bytes = (uint32_t)S.n_age * (uint32_t)S.n_met * (uint32_t)S.n_lam * 4u;
+  return __builtin_amdgcn_make_buffer_rsrc((void *)S.flux, (short)0, (int)bytes, 0x00020000);
+}
+
+// floor(t) as an integer in one instruction (floor-and-convert); t is finite and far inside the
+// int range here.
+__device__ __forceinline__ int floor_i32(float t) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(t));
+  return r;
+}
+
+__device__ __forceinline__ float ldf(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+typedef __attribute__((address_space(4))) const int CInt;         // read-only: scalar loads
+
+// A particle record through the scalar cache (the records are read-only in this kernel).
+__device__ __forceinline__ PrepRec load_rec(const PrepRec *p) {
+  CInt *q = (CInt *)p;
+  PrepRec r;
+  r.row = q[0];
+  r.g = __int_as_float(q[1]);
+  r.a[0] = __int_as_float(q[2]);
+  r.a[1] = __int_as_float(q[3]);
+  r.a[2] = __int_as_float(q[4]);
+  r.a[3] = __int_as_float(q[5]);
+  r.spaxel = q[6];
+  r.fits = q[7];
+  return r;
+}
+
+// One particle's resampled contribution to the lane's bin with both taps gathered from the
+// template grid (particles whose node span does not fit a wave window, coarse telescope grids).
+__device__ __forceinline__ float direct_contrib(const PrepRec &r, __amdgpu_buffer_rsrc_t rs,
                                                int nl, int o1, int o2, int o3, int qi, float qf,
                                                float lamf, bool act) {
   const float tq = fmaf(-lamf, r.g, qf);
@@ -161,12 +190,45 @@ __device__ __forceinline__ float direct_contrib(const PrepRec &r, const float *_
   if (!ok) return 0.f;
   const int kk = min(k, nl - 2);
   const float tt = (k > kk) ? 1.f : tau;
-  const float *b = flux + r.row + kk;
-  float v = r.a[0] * fmaf(tt, b[1] - b[0], b[0]);
-  v = fmaf(r.a[1], fmaf(tt, b[o1 + 1] - b[o1], b[o1]), v);
-  v = fmaf(r.a[2], fmaf(tt, b[o2 + 1] - b[o2], b[o2]), v);
-  v = fmaf(r.a[3], fmaf(tt, b[o3 + 1] - b[o3], b[o3]), v);
+  const uint32_t e = (uint32_t)(r.row + kk) * 4u;
+  const uint32_t b1 = (uint32_t)o1 * 4u, b2 = (uint32_t)o2 * 4u, b3 = (uint32_t)o3 * 4u;
+  const float p0 = ldf(rs, e, 0), q0 = ldf(rs, e + 4u, 0);
+  const float p1 = ldf(rs, e + b1, 0), q1 = ldf(rs, e + b1 + 4u, 0);
+  const float p2 = ldf(rs, e + b2, 0), q2 = ldf(rs, e + b2 + 4u, 0);
+  const float p3 = ldf(rs, e + b3, 0), q3 = ldf(rs, e + b3 + 4u, 0);
+  float v = r.a[0] * fmaf(tt, q0 - p0, p0);
+  v = fmaf(r.a[1], fmaf(tt, q1 - p1, p1), v);
+  v = fmaf(r.a[2], fmaf(tt, q2 - p2, p2), v);
+  v = fmaf(r.a[3], fmaf(tt, q3 - p3, p3), v);
   return v;
+}
+
+// One particle through the wave's LDS slot, with range checks for windows that reach past the
+// SSP wavelength grid. All 64 lanes must be active (n0 is lane 0's node index).
+__device__ __forceinline__ float slot_contrib(const PrepRec &r, __amdgpu_buffer_rsrc_t rs,
+                                             int nl, const uint32_t lb[4], int qi, float qf,
+                                             float lamf, bool act, float *slot, int lane) {
+  const float t = fmaf(-lamf, r.g, qf);
+  const float fl = floorf(t);
+  const float tau = t - fl;
+  const int k = qi + (int)fl;
+  const int n0 = __builtin_amdgcn_readfirstlane(k);
+  const bool inside = (n0 >= 0) && (n0 + 63 <= nl - 1);
+  // nodes outside the grid stage values that only out-of-range lanes read (masked below)
+  const uint32_t so = (uint32_t)(r.row + n0) * 4u;
+  float S = r.a[0] * ldf(rs, lb[0], so);
+  S = fmaf(r.a[1], ldf(rs, lb[1], so), S);
+  S = fmaf(r.a[2], ldf(rs, lb[2], so), S);
+  S = fmaf(r.a[3], ldf(rs, lb[3], so), S);
+  slot[lane] = S;
+  __builtin_amdgcn_wave_barrier();
+  const int idx = min(max(k - n0, 0), 62);
+  const float s0 = slot[idx], s1 = slot[idx + 1];
+  __builtin_amdgcn_wave_barrier();
+  if (inside) return fmaf(tau, s1 - s0, s0);
+  const bool ok = act && (k >= 0) && ((k < nl - 1) || (k == nl - 1 && tau == 0.f));
+  if (!ok) return 0.f;
+  return (k == nl - 1) ? s0 : fmaf(tau, s1 - s0, s0);
 }
 
 __device__ __forceinline__ void split_index(const JobDev &J, const SspDev &S, int jb, int &qi,
@@ -180,104 +242,114 @@ __device__ __forceinline__ void split_index(const JobDev &J, const SspDev &S, in
 }
 
 __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__ T) {
-  __shared__ float sbuf[kCubeBatch * kCubeSlot];
+  __shared__ float slots[kCubeThreads / 64][kCubeGroup][64];
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
-  const float *__restrict__ flux = S.flux;
+  const __amdgpu_buffer_rsrc_t rs = flux_rsrc(S);
   const int nl = S.n_lam;
   const int o1 = nl, o2 = S.n_met * nl, o3 = o2 + nl;
-  const int tid = threadIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float *wslot = &slots[w][0][0];
+  // byte offsets of this lane's node in the four corner rows relative to corner (ja, jz)
+  const uint32_t lb[4] = {(uint32_t)lane * 4u, (uint32_t)(lane + o1) * 4u,
+                          (uint32_t)(lane + o2) * 4u, (uint32_t)(lane + o3) * 4u};
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_CUBE]; vb += gridDim.x) {
     const int jj = find_job(T, K_CUBE, vb);
     const JobDev &J = jobs[jj];
     const int64_t local = vb - J.vb_start[K_CUBE];
     const int tile = (int)(local / J.n_chunk_ub);
     const int c = (int)(local - (int64_t)tile * J.n_chunk_ub);
-    if (c >= J.counts[0]) continue;
-    const ChunkRec ch = J.chunks[c];
-    const int TL = J.cube_tl;
-    const int j0 = tile * TL;
-    const int jl = min(j0 + TL, J.n_tel) - 1;
-    const int jb = j0 + tid;
-    const bool act = (tid < TL) && (jb < J.n_tel);
+    if (c >= ((CInt *)J.counts)[0]) continue;
+    const int jw = tile * kCubeTL + w * kCubeWaveBins;     // first bin of this wave
+    if (jw >= J.n_tel) continue;                           // wave-uniform: nothing to do
+    CInt *chp = (CInt *)(J.chunks + c);
+    const ChunkRec ch{chp[0], chp[1], chp[2], chp[3]};
+    const int jb = jw + lane;
+    const bool act = (lane < kCubeWaveBins) && (jb < J.n_tel);
+    // lanes 62, 63 only stage nodes; they and lanes past the band take the constants of the
+    // wave's last bin, so every lane's node index stays within the 64-node window
+    int qi;
+    float qf, lamf;
+    split_index(J, S, min(jw + min(lane, kCubeWaveBins - 1), J.n_tel - 1), qi, qf, lamf);
+    const int qi0 = __builtin_amdgcn_readfirstlane(qi);
+    const uint32_t abase = (uint32_t)(qi - qi0) * 4u;   // + LDS byte address of the slots
     const bool direct_job = J.cube_direct != 0;
-    int qi, qi0, qil;
-    float qf, lamf, qf_u, lam_u;
-    split_index(J, S, jb, qi, qf, lamf);
-    split_index(J, S, j0, qi0, qf_u, lam_u);     // tile-uniform node index range
-    split_index(J, S, jl, qil, qf_u, lam_u);
-    const int span = qil - qi0;
-    const int lrel = qi - qi0;
+    const PrepRec *prep = J.prep;
     float acc = 0.f, tot = 0.f;
     int since = 0;
-    const PrepRec *__restrict__ prep = J.prep;
-    for (int pb = ch.p0; pb < ch.p1; pb += kCubeBatch) {
-      const int nb = min(kCubeBatch, ch.p1 - pb);
-      // phase 1: node windows of the batch's spectra into LDS
+    int p = ch.p0;
+    // full groups: straight-line code, all row loads of the group in flight together
+    for (; p + kCubeGroup <= ch.p1; p += kCubeGroup) {
+      PrepRec r[kCubeGroup];
 #pragma unroll
-      for (int b = 0; b < kCubeBatch; ++b) {
-        if (b < nb) {
-          const PrepRec r = prep[pb + b];
-          const int dlo = (int)(int16_t)(r.lohi & 0xffff), dhi = r.lohi >> 16;
-          const int W = span + dhi - dlo + 2;
-          if (!direct_job && r.lohi != kLohiBad && W <= kCubeSlot) {
-            const int n0 = qi0 + dlo;
-            const bool inside = (n0 >= 0) && (n0 + W <= nl);
-            const float *__restrict__ rp = flux + r.row;
-            for (int m = tid; m < W; m += kCubeThreads) {
-              int node = n0 + m;
-              if (!inside) node = min(max(node, 0), nl - 1);
-              float v = r.a[0] * rp[node];
-              v = fmaf(r.a[1], rp[o1 + node], v);
-              v = fmaf(r.a[2], rp[o2 + node], v);
-              v = fmaf(r.a[3], rp[o3 + node], v);
-              sbuf[b * kCubeSlot + m] = v;
-            }
+      for (int u = 0; u < kCubeGroup; ++u) r[u] = load_rec(prep + p + u);
+      bool fast = !direct_job;
+#pragma unroll
+      for (int u = 0; u < kCubeGroup; ++u) fast = fast && (r[u].fits != 0);
+      bool done = false;
+      if (fast) {
+        float tau[kCubeGroup];
+        int fi[kCubeGroup], fi0[kCubeGroup], n0[kCubeGroup];
+        bool inside = true;
+#pragma unroll
+        for (int u = 0; u < kCubeGroup; ++u) {
+          const float t = fmaf(-lamf, r[u].g, qf);
+          tau[u] = __builtin_amdgcn_fractf(t);
+          fi[u] = floor_i32(t);
+          fi0[u] = __builtin_amdgcn_readfirstlane(fi[u]);
+          n0[u] = qi0 + fi0[u];                           // window base: lane 0's node
+          inside = inside && (n0[u] >= 0) && (n0[u] + 63 <= nl - 1);
+        }
+        if (inside) {
+          float v[kCubeGroup][4];
+#pragma unroll
+          for (int u = 0; u < kCubeGroup; ++u) {
+            const uint32_t so = (uint32_t)(r[u].row + n0[u]) * 4u;   // per-particle, scalar
+            v[u][0] = ldf(rs, lb[0], so);
+            v[u][1] = ldf(rs, lb[1], so);
+            v[u][2] = ldf(rs, lb[2], so);
+            v[u][3] = ldf(rs, lb[3], so);
           }
+#pragma unroll
+          for (int u = 0; u < kCubeGroup; ++u) {
+            float Sv = r[u].a[0] * v[u][0];
+            Sv = fmaf(r[u].a[1], v[u][1], Sv);
+            Sv = fmaf(r[u].a[2], v[u][2], Sv);
+            Sv = fmaf(r[u].a[3], v[u][3], Sv);
+            wslot[u * 64 + lane] = Sv;
+          }
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int u = 0; u < kCubeGroup; ++u) {
+            // k - n0 = (qi - qi0) + (fi - fi0), in [0, 62] for every lane
+            const float *sp = (const float *)((const char *)wslot + abase +
+                                              (uint32_t)(fi[u] - fi0[u]) * 4u) + u * 64;
+            const float s0 = sp[0], s1 = sp[1];
+            acc += fmaf(tau[u], s1 - s0, s0);
+          }
+          __builtin_amdgcn_wave_barrier();
+          done = true;
         }
       }
-      __syncthreads();
-      // phase 2: Doppler-shifted linear resampling from the staged spectra
+      if (!done) {
 #pragma unroll
-      for (int b = 0; b < kCubeBatch; ++b) {
-        if (b < nb) {
-          const PrepRec r = prep[pb + b];
-          const int dlo = (int)(int16_t)(r.lohi & 0xffff), dhi = r.lohi >> 16;
-          const int W = span + dhi - dlo + 2;
-          if (!direct_job && r.lohi != kLohiBad && W <= kCubeSlot) {
-            const int n0 = qi0 + dlo;
-            const bool inside = (n0 >= 0) && (n0 + W <= nl);
-            const float tq = fmaf(-lamf, r.g, qf);
-            const float fl = floorf(tq);
-            const float tau = tq - fl;
-            const int fi = (int)fminf(fmaxf(fl, -30000.f), 30000.f);
-            if (inside) {
-              // every node of the window exists: no range test; the clamp only guards lanes
-              // past the end of the band, whose results are discarded
-              const int idx = min(max(lrel + fi - dlo, 0), kCubeSlot - 2);
-              const float s0 = sbuf[b * kCubeSlot + idx];
-              const float s1 = sbuf[b * kCubeSlot + idx + 1];
-              acc += fmaf(tau, s1 - s0, s0);
-            } else {
-              const int k = qi + fi;
-              const bool ok = act && (k >= 0) && ((k < nl - 1) || (k == nl - 1 && tau == 0.f));
-              if (ok) {
-                const int kk = min(k, nl - 2);
-                const float tt = (k > kk) ? 1.f : tau;
-                const int idx = min(max(kk - n0, 0), kCubeSlot - 2);
-                const float s0 = sbuf[b * kCubeSlot + idx];
-                const float s1 = sbuf[b * kCubeSlot + idx + 1];
-                acc += fmaf(tt, s1 - s0, s0);
-              }
-            }
-          } else {
-            acc += direct_contrib(r, flux, nl, o1, o2, o3, qi, qf, lamf, act);
-          }
+        for (int u = 0; u < kCubeGroup; ++u) {
+          if (!direct_job && r[u].fits)
+            acc += slot_contrib(r[u], rs, nl, lb, qi, qf, lamf, act, wslot, lane);
+          else
+            acc += direct_contrib(r[u], rs, nl, o1, o2, o3, qi, qf, lamf, act);
         }
       }
-      since += nb;
+      since += kCubeGroup;
       if (since >= kCubeSubsum) { tot += acc; acc = 0.f; since = 0; }
-      __syncthreads();
+    }
+    // the last < kCubeGroup particles one at a time
+    for (; p < ch.p1; ++p) {
+      const PrepRec r = load_rec(prep + p);
+      if (!direct_job && r.fits)
+        acc += slot_contrib(r, rs, nl, lb, qi, qf, lamf, act, wslot, lane);
+      else
+        acc += direct_contrib(r, rs, nl, o1, o2, o3, qi, qf, lamf, act);
     }
     tot += acc;
     if (act) {
@@ -297,8 +369,8 @@ __global__ __launch_bounds__(kCubeThreads) void k_combine(const Table *__restric
     const int e = (int)(local - (int64_t)tile * J.n_comb_ub);
     if (e >= J.counts[1]) continue;
     const CombRec cr = J.combs[e];
-    if ((int)threadIdx.x >= J.cube_tl) continue;
-    const int jb = tile * J.cube_tl + threadIdx.x;
+    if ((int)threadIdx.x >= kCubeTL) continue;
+    const int jb = tile * kCubeTL + threadIdx.x;
     if (jb >= J.n_tel) continue;
     float sum = 0.f;
     for (int q = 0; q < cr.n_slots; ++q) sum += J.partial[(int64_t)(cr.first_slot + q) * J.n_tel + jb];

@@ -68,7 +68,7 @@ enum Call { CALL_ROTATE, CALL_CUBE, CALL_PSF, CALL_BWD, CALL_SIZE, CALL_PACK };
 
 struct JobSizes {
   int64_t n, n_s, n_tel, cube_elems;
-  int passes, n_sort_tiles, n_tiles, cube_tl, n_chunk_ub, n_comb_ub, n_slot_ub;
+  int passes, n_sort_tiles, n_tiles, n_chunk_ub, n_comb_ub, n_slot_ub;
   int lsf_r, psf_r, n_psf_tiles, n_psf_seg_y, n_psf_seg_x, n_fin_blocks;
   double lsf_sigma_bins;
   // byte offsets inside the job's workspace region
@@ -91,8 +91,7 @@ static JobSizes sizes_of(const rubix_job &j) {
   while ((int64_t(1) << bits) <= z.n_s) ++bits;      // keys are 0..n_s
   z.passes = std::max(1, (bits + 7) / 8);
   z.n_sort_tiles = (int)cdiv(z.n, kSortTile);
-  z.n_tiles = (int)cdiv(z.n_tel, kCubeMaxTL);
-  z.cube_tl = (int)cdiv(z.n_tel, z.n_tiles);
+  z.n_tiles = (int)cdiv(z.n_tel, kCubeTL);
   z.n_chunk_ub = (int)(z.n_s + cdiv(z.n, kCubeChunk));
   z.n_comb_ub = z.n > kCubeChunk ? (int)(z.n / (kCubeChunk + 1) + 1) : 0;
   z.n_slot_ub = (int)(2 * cdiv(z.n, kCubeChunk) + 2);
@@ -297,10 +296,10 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
     gauss_weights(z.lsf_sigma_bins, z.lsf_r, d.lsf_w);
     gauss_weights(j.psf_sigma_spx, z.psf_r, d.psf_w);
     d.n_tel = (int32_t)z.n_tel; d.passes = z.passes; d.n_sort_tiles = z.n_sort_tiles; d.n_tiles = z.n_tiles;
-    d.cube_tl = z.cube_tl;
-    // a telescope grid much coarser than the SSP grid would need node windows far wider than a
-    // tile; such jobs gather their two taps per corner directly from the template grid
-    d.cube_direct = (ssp && j.tel.step / ((1.0 + j.z_sys) * ssp->lam.step) > 1.5) ? 1 : 0;
+    d.bin_slope = ssp ? j.tel.step / ((1.0 + j.z_sys) * ssp->lam.step) : 1.0;
+    // a telescope grid coarser than the SSP grid needs node windows wider than a wave; such jobs
+    // gather their two taps per corner directly from the template grid
+    d.cube_direct = d.bin_slope > 1.0 ? 1 : 0;
     d.n_chunk_ub = z.n_chunk_ub; d.n_comb_ub = z.n_comb_ub;
     d.n_psf_tiles = z.n_psf_tiles; d.n_psf_seg_y = z.n_psf_seg_y; d.n_psf_seg_x = z.n_psf_seg_x;
     d.n_fin_blocks = z.n_fin_blocks;

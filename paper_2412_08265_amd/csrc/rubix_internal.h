@@ -17,13 +17,12 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per sort work item
 constexpr int kPrepThreads = 256;
-constexpr int kCubeThreads = 256;   // threads per cube work item
-constexpr int kCubeMaxTL = 250;     // max telescope bins per cube tile (node window fits 256 lanes)
-constexpr int kCubeBatch = 8;       // particles staged in LDS per phase
-constexpr int kCubeSlot = 512;      // LDS floats per staged particle spectrum window
+constexpr int kCubeThreads = 256;   // threads per cube work item (4 waves)
+constexpr int kCubeWaveBins = 62;   // telescope bins per wave; its 64 lanes stage a 64-node window
+constexpr int kCubeTL = 4 * kCubeWaveBins;  // telescope bins per cube tile
+constexpr int kCubeGroup = 4;       // particles staged per wave at once (their loads overlap)
 constexpr int kCubeChunk = 2048;    // max particles per cube work item
 constexpr int kCubeSubsum = 256;    // particles per inner FP32 partial sum
-constexpr int32_t kLohiBad = INT32_MIN;  // PrepRec.lohi of a particle without a finite window
 constexpr int kLsfTL = 256;         // bins per LSF work item
 constexpr int kPsfLanes = 64;       // bins per PSF work item
 constexpr int kPsfSeg = 128;        // spaxels of a line per PSF work item
@@ -55,8 +54,8 @@ struct PrepRec {
   float g;          // beta/(1+beta) / ((1+z_sys) dlam_ssp): Doppler slope of the node index
   float a[4];       // corner weights (forward: flux_scale m J w_c; backward: w_c)
   int32_t spaxel;   // key of the particle
-  int32_t lohi;     // bounds [dlo, dhi] of floor(q) - floor(Q_j) over the telescope band (int16
-                    // each, dlo low half), or kLohiBad
+  int32_t fits;     // 1: the node indices of 62 consecutive bins span at most 63 nodes, so a
+                    // 64-node window staged by one wave covers both taps of every bin
 };
 
 struct ChunkRec {
@@ -87,8 +86,9 @@ struct JobDev {
   double lsf_sigma_bins, psf_sigma;
   float lsf_w[2 * RUBIX_MAX_RADIUS + 1];   // normalised LSF weights, k = -r..r
   float psf_w[2 * RUBIX_MAX_RADIUS + 1];   // normalised PSF weights
-  int32_t n_tel, passes, n_sort_tiles, n_tiles;     // n_tiles: cube lambda tiles of cube_tl bins
-  int32_t cube_tl, cube_direct;                      // tile width; 1 = gather taps from global
+  int32_t n_tel, passes, n_sort_tiles, n_tiles;     // n_tiles: cube lambda tiles of kCubeTL bins
+  int32_t cube_direct, pad_;                         // 1 = gather taps from global (coarse grids)
+  double bin_slope;                                  // d(node index)/d(bin) at rest
   int32_t n_chunk_ub, n_comb_ub, lsf_r, psf_r;
   int32_t n_psf_tiles, n_psf_seg_y, n_psf_seg_x, n_fin_blocks;
   // outputs
