@@ -141,9 +141,11 @@ __global__ __launch_bounds__(1024) void k_chunks(const Table *__restrict__ T) {
 
 typedef __attribute__((address_space(1))) const float GFloat;     // global memory
 
-// The template grid is read through a buffer resource: one uniform descriptor, a per-lane byte
-// offset (VGPR) and a per-particle byte offset (SGPR), so a row load needs no vector address
-// arithmetic; offsets past the end of the grid read 0 instead of faulting.
+// The template grid is read through a buffer resource: one uniform descriptor and a 32-bit byte
+// offset per lane; offsets past the end of the grid read 0 instead of faulting. The whole offset
+// goes in the lane offset (the scalar offset stays 0): a window that starts before node 0 of the
+// first row has a negative per-particle part, which must wrap modulo 2^32 together with the lane
+// part, and only the lane offset does.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t flux_rsrc(const SspDev &S) {
   const uint32_t bytes = (uint32_t)S.n_age * (uint32_t)S.n_met * (uint32_t)S.n_lam * 4u;
   return __builtin_amdgcn_make_buffer_rsrc((void *)S.flux, (short)0, (int)bytes, 0x00020000);
@@ -158,7 +160,7 @@ __device__ __forceinline__ int floor_i32(float t) {
 }
 
 __device__ __forceinline__ float ldf(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + soff, 0, 0));
 }
 typedef __attribute__((address_space(4))) const int CInt;         // read-only: scalar loads
 
