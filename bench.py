@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--n", type=int, default=10_000_000, help="particles (default: full 1e7)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after timing, copy 1 GiB device to device once (a known-size kernel "
+                         "for calibrating profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the lambda-sharded "
@@ -175,6 +178,13 @@ def main():
                        "psf_lsf_GBs": psf_gbs, "psf_lsf_frac": psf_gbs / PEAK_HBM_GBS},
     }
     err(f"step {ms_step:.3f} ms, stages {st}")
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = {"read": a.numel() * 4, "write": b.numel() * 4}
     if not args.no_cpu_baseline:
         err("cpu baseline (oracle on a sample)")
         out["cpu_baseline"] = cpu_baseline(w, n_in, args.cpu_sample)

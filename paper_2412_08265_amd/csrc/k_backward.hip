@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
         if (ok) {
           const int kk = min(k, nl - 2);
           const float tt = (k > kk) ? 1.f : tau;
-          const float *b = flux + r.row + kk;
+          const float *b = flux + prep_row(r.row) + kk;
           const float p0 = b[0], q0 = b[1], p1 = b[o1], q1 = b[o1 + 1];
           const float p2 = b[o2], q2 = b[o2 + 1], p3 = b[o3], q3 = b[o3 + 1];
           const float d0 = q0 - p0, d1 = q1 - p1, d2 = q2 - p2, d3 = q3 - p3;

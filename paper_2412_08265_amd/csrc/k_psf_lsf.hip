@@ -1,53 +1,89 @@
 // Step 7 of the pipeline (arXiv:2412.08265, Sec. 3, with the Gaussian PSF/LSF of Sec. 4): a
 // separable, zero-padded Gaussian convolution of the cube along lambda (LSF), y and x (PSF).
 //
-// Each pass is an HBM-bound 1-D stencil. A work item stages its input tile plus a halo of r
-// values in LDS with lane-contiguous (coalesced) loads and writes each output once:
-//   k_lsf    (spaxel, 256-bin tile): a contiguous run of one spectrum;
-//   k_psf<A> (line, 128-spaxel segment, 64-bin tile): 64 lanes span lambda, so every load of a
-//            neighbouring spaxel is a contiguous 256-byte row segment.
-// The normalised FP32 weights come with the job table (computed on the host in FP64).
+// Each pass is an HBM-bound 1-D stencil. A work item stages its input tile plus a halo of r values
+// in LDS with lane-contiguous (coalesced) loads and writes each output once; every lane computes
+// four outputs from one run of LDS values (register blocking), so an LDS value feeds four filter
+// taps instead of one:
+//   k_lsf    (spaxel, 1024-bin run): thread t owns bins 4t..4t+3 and reads the staged run with
+//            aligned 16-byte LDS loads;
+//   k_psf<A> (line, 64-spaxel segment, 64-bin tile): 64 lanes span lambda (every load of a
+//            neighbouring spaxel is a contiguous 256-byte row segment); wave w owns 16 output
+//            positions of the segment, four at a time.
+// The normalised FP32 weights come with the job table (computed on the host in FP64), padded with
+// kWPad zeros on both sides so a blocked filter needs no branch at the ends of its window.
 #include "rubix_internal.h"
 
 namespace rubix {
 
-__global__ __launch_bounds__(kLsfTL) void k_lsf(const Table *__restrict__ T) {
-  __shared__ float buf[kLsfTL + 2 * RUBIX_MAX_RADIUS];
+__global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T) {
+  __shared__ __attribute__((aligned(16))) float buf[kLsfOut + 2 * RUBIX_MAX_RADIUS + 8];
   const JobDev *jobs = table_jobs(T);
+  const int tid = threadIdx.x;
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_LSF]; vb += gridDim.x) {
     const int jj = find_job(T, K_LSF, vb);
     const JobDev &J = jobs[jj];
-    const int nt = (J.n_tel + kLsfTL - 1) / kLsfTL;
+    const int nt = (J.n_tel + kLsfOut - 1) / kLsfOut;
     const int64_t local = vb - J.vb_start[K_LSF];
     const int64_t s = local / nt;
     const int t = (int)(local - s * nt);
     const int r = J.lsf_r;
     const float *__restrict__ src = J.pl_src[0] + s * J.n_tel;
     float *__restrict__ dst = J.pl_dst[0] + s * J.n_tel;
-    const int j0 = t * kLsfTL;
-    for (int q = threadIdx.x; q < kLsfTL + 2 * r; q += kLsfTL) {
+    const int j0 = t * kLsfOut;
+    const int nload = kLsfOut + 2 * r + 4;       // + 4: the last float4 of a lane's window
+    for (int q = tid; q < nload; q += 256) {
       const int jj2 = j0 - r + q;
       buf[q] = (jj2 >= 0 && jj2 < J.n_tel) ? src[jj2] : 0.f;
     }
     __syncthreads();
-    const int jb = j0 + threadIdx.x;
-    if (jb < J.n_tel) {
-      float acc = 0.f;
-      for (int k = 0; k <= 2 * r; ++k) acc = fmaf(J.lsf_w[k], buf[threadIdx.x + k], acc);
-      dst[jb] = acc;
+    // out[4t + i] = sum_{k=0..2r} w_k buf[4t + i + k] = sum_o wp[o - i] buf[4t + o], o = 0..2r+3,
+    // wp[m] = weight of offset m (zero outside 0..2r)
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+    const float *wp = J.lsf_w + kWPad;            // wp[m], m in [-kWPad, 2r + kWPad]
+    const int nq = (2 * r + 4 + 3) / 4;
+    for (int m = 0; m < nq; ++m) {
+      const float4 x = *reinterpret_cast<const float4 *>(&buf[4 * tid + 4 * m]);
+      const int o = 4 * m;
+      acc0 = fmaf(wp[o], x.x, acc0);
+      acc1 = fmaf(wp[o - 1], x.x, acc1);
+      acc2 = fmaf(wp[o - 2], x.x, acc2);
+      acc3 = fmaf(wp[o - 3], x.x, acc3);
+      acc0 = fmaf(wp[o + 1], x.y, acc0);
+      acc1 = fmaf(wp[o], x.y, acc1);
+      acc2 = fmaf(wp[o - 1], x.y, acc2);
+      acc3 = fmaf(wp[o - 2], x.y, acc3);
+      acc0 = fmaf(wp[o + 2], x.z, acc0);
+      acc1 = fmaf(wp[o + 1], x.z, acc1);
+      acc2 = fmaf(wp[o], x.z, acc2);
+      acc3 = fmaf(wp[o - 1], x.z, acc3);
+      acc0 = fmaf(wp[o + 3], x.w, acc0);
+      acc1 = fmaf(wp[o + 2], x.w, acc1);
+      acc2 = fmaf(wp[o + 1], x.w, acc2);
+      acc3 = fmaf(wp[o], x.w, acc3);
+    }
+    const int jb = j0 + 4 * tid;
+    if (jb + 3 < J.n_tel && (((uintptr_t)(dst + jb)) & 15) == 0) {
+      *reinterpret_cast<float4 *>(dst + jb) = make_float4(acc0, acc1, acc2, acc3);
+    } else {
+      if (jb < J.n_tel) dst[jb] = acc0;
+      if (jb + 1 < J.n_tel) dst[jb + 1] = acc1;
+      if (jb + 2 < J.n_tel) dst[jb + 2] = acc2;
+      if (jb + 3 < J.n_tel) dst[jb + 3] = acc3;
     }
     __syncthreads();
   }
 }
 
 // AXIS 0: PSF along y (a line is one x column); AXIS 1: PSF along x (a line is one y row).
+// Dynamic LDS: (kPsfSeg + 2 * max_psf_r) rows of kPsfLanes floats.
 template <int AXIS>
 __global__ __launch_bounds__(256) void k_psf(const Table *__restrict__ T) {
-  __shared__ float buf[(kPsfSeg + 2 * RUBIX_MAX_RADIUS) * kPsfLanes];
+  extern __shared__ float buf[];
   const JobDev *jobs = table_jobs(T);
   const int kind = AXIS == 0 ? K_PSFY : K_PSFX;
   const int lane = threadIdx.x & 63;
-  const int grp = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6;
   for (int64_t vb = blockIdx.x; vb < T->h.total[kind]; vb += gridDim.x) {
     const int jj = find_job(T, kind, vb);
     const JobDev &J = jobs[jj];
@@ -66,21 +102,38 @@ __global__ __launch_bounds__(256) void k_psf(const Table *__restrict__ T) {
     const bool act = jb < J.n_tel;
     const float *__restrict__ src = J.pl_src[1 + AXIS];
     float *__restrict__ dst = J.pl_dst[1 + AXIS];
-    // spaxel index of position q on this line
     auto spx = [&](int q) -> int64_t {
       return AXIS == 0 ? (int64_t)q * J.nx + line : (int64_t)line * J.nx + q;
     };
-    for (int q = q0 - r + grp; q < q1 + r; q += 4) {
+    // rows q0 - r .. q0 + kPsfSeg + r + 3 (the last rows only feed masked blocked outputs)
+    const int nrow = kPsfSeg + 2 * r + 4;
+    for (int t = w; t < nrow; t += 4) {
+      const int q = q0 - r + t;
       float v = 0.f;
       if (act && q >= 0 && q < L) v = src[spx(q) * J.n_tel + jb];
-      buf[(q - (q0 - r)) * kPsfLanes + lane] = v;
+      buf[t * kPsfLanes + lane] = v;
     }
     __syncthreads();
-    for (int q = q0 + grp; q < q1; q += 4) {
-      float acc = 0.f;
-      const float *b = buf + (q - q0) * kPsfLanes + lane;
-      for (int k = 0; k <= 2 * r; ++k) acc = fmaf(J.psf_w[k], b[k * kPsfLanes], acc);
-      if (act) dst[spx(q) * J.n_tel + jb] = acc;
+    const float *wp = J.psf_w + kWPad;
+    for (int b = 0; b < 4; ++b) {
+      const int qr = 16 * w + 4 * b;                  // first of 4 output rows (segment-relative)
+      if (q0 + qr >= q1) break;                       // wave-uniform
+      float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+      const float *col = buf + qr * kPsfLanes + lane;
+      for (int o = 0; o < 2 * r + 4; ++o) {
+        const float v = col[o * kPsfLanes];
+        acc0 = fmaf(wp[o], v, acc0);
+        acc1 = fmaf(wp[o - 1], v, acc1);
+        acc2 = fmaf(wp[o - 2], v, acc2);
+        acc3 = fmaf(wp[o - 3], v, acc3);
+      }
+      if (act) {
+        const int q = q0 + qr;
+        dst[spx(q) * J.n_tel + jb] = acc0;
+        if (q + 1 < q1) dst[spx(q + 1) * J.n_tel + jb] = acc1;
+        if (q + 2 < q1) dst[spx(q + 2) * J.n_tel + jb] = acc2;
+        if (q + 3 < q1) dst[spx(q + 3) * J.n_tel + jb] = acc3;
+      }
     }
     __syncthreads();
   }
@@ -110,9 +163,12 @@ static inline int grid_for(int64_t total, int cap) {
 
 hipError_t launch_psf_lsf(const Table *dt, const TableHeader &h, int cap, hipStream_t s) {
   int g;
-  if ((g = grid_for(h.total[K_LSF], cap))) hipLaunchKernelGGL(k_lsf, dim3(g), dim3(kLsfTL), 0, s, dt);
-  if ((g = grid_for(h.total[K_PSFY], cap))) hipLaunchKernelGGL(k_psf<0>, dim3(g), dim3(256), 0, s, dt);
-  if ((g = grid_for(h.total[K_PSFX], cap))) hipLaunchKernelGGL(k_psf<1>, dim3(g), dim3(256), 0, s, dt);
+  const size_t psf_lds = sizeof(float) * kPsfLanes * (kPsfSeg + 2 * h.max_psf_r + 4);
+  if ((g = grid_for(h.total[K_LSF], cap))) hipLaunchKernelGGL(k_lsf, dim3(g), dim3(256), 0, s, dt);
+  if ((g = grid_for(h.total[K_PSFY], cap)))
+    hipLaunchKernelGGL(k_psf<0>, dim3(g), dim3(256), psf_lds, s, dt);
+  if ((g = grid_for(h.total[K_PSFX], cap)))
+    hipLaunchKernelGGL(k_psf<1>, dim3(g), dim3(256), psf_lds, s, dt);
   if ((g = grid_for(h.total[K_COPY], cap))) hipLaunchKernelGGL(k_copy, dim3(g), dim3(256), 0, s, dt);
   return hipGetLastError();
 }

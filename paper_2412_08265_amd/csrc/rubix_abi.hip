@@ -241,11 +241,13 @@ static void rotation(const double ang[3], double R[9], double dR2[9]) {
   dR2[6] = 0.0;  dR2[7] = 0.0;      dR2[8] = 0.0;
 }
 
+// Normalised sampled Gaussian of radius r at w[kWPad + k + r], k = -r..r; zeros elsewhere.
 static void gauss_weights(double sigma, int r, float *w) {
-  if (r == 0) { w[0] = 1.f; return; }
+  for (int i = 0; i < kWArray; ++i) w[i] = 0.f;
+  if (r == 0) { w[kWPad] = 1.f; return; }
   double tmp[2 * RUBIX_MAX_RADIUS + 1], sum = 0.0;
   for (int k = -r; k <= r; ++k) { tmp[k + r] = exp(-0.5 * (k / sigma) * (k / sigma)); sum += tmp[k + r]; }
-  for (int k = 0; k <= 2 * r; ++k) w[k] = (float)(tmp[k] / sum);
+  for (int k = 0; k <= 2 * r; ++k) w[kWPad + k] = (float)(tmp[k] / sum);
 }
 
 static void fill_ssp(SspDev &S, const rubix_ssp *ssp) {
@@ -342,7 +344,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
         cur = bufs[which];
         which ^= 1;
       }
-      if (L) n_lsf = z.n_s * cdiv(z.n_tel, kLsfTL);
+      if (L) n_lsf = z.n_s * cdiv(z.n_tel, kLsfOut);
       if (P) {
         n_psfy = (int64_t)j.grid.nx * z.n_psf_seg_y * z.n_psf_tiles;
         n_psfx = (int64_t)j.grid.ny * z.n_psf_seg_x * z.n_psf_tiles;
@@ -382,6 +384,10 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
   }
   for (int q = 0; q < NK; ++q) t->h.total[q] = start[q];
   t->h.max_passes = max_passes;
+  for (int k = 0; k < n_jobs; ++k) {
+    t->h.max_psf_r = std::max(t->h.max_psf_r, J[k].psf_r);
+    t->h.max_lsf_r = std::max(t->h.max_lsf_r, J[k].lsf_r);
+  }
   return buf;
 }
 

@@ -23,9 +23,11 @@ constexpr int kCubeTL = 4 * kCubeWaveBins;  // telescope bins per cube tile
 constexpr int kCubeGroup = 4;       // particles staged per wave at once (their loads overlap)
 constexpr int kCubeChunk = 2048;    // max particles per cube work item
 constexpr int kCubeSubsum = 256;    // particles per inner FP32 partial sum
-constexpr int kLsfTL = 256;         // bins per LSF work item
+constexpr int kWPad = 4;            // zero weights before a padded filter
+constexpr int kWArray = 2 * RUBIX_MAX_RADIUS + 1 + 16;   // padded filter array (zeros after)
+constexpr int kLsfOut = 1024;       // bins per LSF work item (4 consecutive per thread)
 constexpr int kPsfLanes = 64;       // bins per PSF work item
-constexpr int kPsfSeg = 128;        // spaxels of a line per PSF work item
+constexpr int kPsfSeg = 64;         // spaxels of a line per PSF work item (16 per wave)
 constexpr int kBwdParticles = 16;   // particles per backward work item (4 per wave)
 constexpr int kFinThreads = 256;
 
@@ -50,13 +52,17 @@ enum Kind : int {
 
 // Per-particle record written by the prep kernel, in sorted order (32 bytes).
 struct PrepRec {
-  int32_t row;      // flux offset of corner (ja, jz): (ja*n_met + jz)*n_lam
+  int32_t row;      // flux offset of corner (ja, jz): (ja*n_met + jz)*n_lam, stored as ~offset
+                    // (negative) when the particle's node span does not fit a wave window (see
+                    // prep_row): the 62 node indices of a wave's bins then span more than 63 nodes
   float g;          // beta/(1+beta) / ((1+z_sys) dlam_ssp): Doppler slope of the node index
   float a[4];       // corner weights (forward: flux_scale m J w_c; backward: w_c)
   int32_t spaxel;   // key of the particle
-  int32_t fits;     // 1: the node indices of 62 consecutive bins span at most 63 nodes, so a
-                    // 64-node window staged by one wave covers both taps of every bin
+  int32_t pad;
 };
+
+// Flux offset of a record's corner (ja, jz) whatever its window flag.
+__host__ __device__ inline int32_t prep_row(int32_t row) { return row < 0 ? ~row : row; }
 
 struct ChunkRec {
   int32_t s, p0, p1, slot;   // spaxel, sorted particle range [p0, p1), partial slot or -1
@@ -84,8 +90,10 @@ struct JobDev {
   double spaxel, half_nx, half_ny;
   double tel_start, tel_step, z_sys, flux_scale;
   double lsf_sigma_bins, psf_sigma;
-  float lsf_w[2 * RUBIX_MAX_RADIUS + 1];   // normalised LSF weights, k = -r..r
-  float psf_w[2 * RUBIX_MAX_RADIUS + 1];   // normalised PSF weights
+  // normalised weights of offsets -r..r at [kWPad + k + r], zero-padded by kWPad on both sides
+  // so register-blocked filters can read weights of out-of-range offsets without a branch
+  float lsf_w[kWArray];
+  float psf_w[kWArray];
   int32_t n_tel, passes, n_sort_tiles, n_tiles;     // n_tiles: cube lambda tiles of kCubeTL bins
   int32_t cube_direct, pad_;                         // 1 = gather taps from global (coarse grids)
   double bin_slope;                                  // d(node index)/d(bin) at rest
@@ -123,6 +131,7 @@ struct JobDev {
 
 struct TableHeader {
   int32_t n_jobs, max_passes;   // max_passes: most radix-sort passes any job of the table needs
+  int32_t max_psf_r, max_lsf_r; // largest PSF / LSF radius of the table (sizes LDS)
   int64_t total[NK];
   SspDev ssp;
 };
