@@ -149,6 +149,19 @@ typedef __attribute__((address_space(1))) const float GFloat;     // global memo
 // offset: a window that starts before node 0 of the first row has a negative per-particle part,
 // which must wrap modulo 2^32 together with the lane part (only the lane offset does), and on
 // the 1e7-particle workload the scalar-offset form measured 40.8 ms against 30.5 ms.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t flux_rsrc(const SspDev &S) {
+  const uint32_t bytes = (uint32_t)S.n_age * (uint32_t)S.n_met * (uint32_t)S.n_lam * 4u;
+  return __builtin_amdgcn_make_buffer_rsrc((void *)S.flux, (short)0, (int)bytes, 0x00020000);
+}
+
+// floor(t) as an integer in one instruction (floor-and-convert); t is finite and far inside the
+// int range here.
+__device__ __forceinline__ int floor_i32(float t) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(t));
+  return r;
+}
+
 __device__ __forceinline__ float ldf(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + off, 0, 0));
 }
