@@ -90,6 +90,68 @@ def cpu_baseline(w, n_in_full: int, sample_particles: int):
                        "for the full step")}
 
 
+def serve_main(args):
+    """Serving report: a Poisson stream of requests (N log-uniform 1e4..5e6, square grids of 20..100
+    spaxels over 30 kpc, contiguous windows of 1500..4563 bins of the resident 100 x 12 x 4563 SSP
+    grid, inclination uniform in 0..90 deg) through the batched graph executor and through
+    one-at-a-time plain launches, at arrival rates doubling until the graph path saturates."""
+    import numpy as np
+    import torch
+    from paper_2412_08265_amd import ops, synth
+    from paper_2412_08265_amd.serve import (GraphExecutor, PlainExecutor, Request, Scheduler,
+                                            replay_trace)
+    grid = synth.serving_ssp()
+    dssp = ops.DeviceSSP.from_grid(grid)
+    n_req = args.serve_requests
+    reqs, n_tot = [], 0
+    for i in range(n_req):
+        w = synth.serving_request(i, grid)
+        reqs.append(Request.from_particles(w.particles, ops.Observation.from_workload(w), rid=i))
+        n_tot += w.particles.n
+        if (i + 1) % 32 == 0:
+            err(f"generated {i + 1}/{n_req} requests ({n_tot:.3g} particles)")
+    budget = int(args.serve_budget_gb * 2 ** 30)
+    graph_ex = GraphExecutor(dssp, max_jobs=args.serve_slots, lanes=2, grid_blocks=2048)
+    plain_ex = PlainExecutor(dssp)
+    fps = [graph_ex.footprint(r) for r in reqs]
+    # warm both paths (module load, graph upload) on the first requests
+    for ex, slots in ((graph_ex, args.serve_slots), (plain_ex, 1)):
+        sch = Scheduler(ex, budget, max_slots=slots)
+        for r in reqs[:4]:
+            sch.submit(r)
+        sch.drain()
+    torch.cuda.synchronize()
+    rows = []
+    rate = args.serve_rate0
+    while True:
+        arr = synth.poisson_arrivals(n_req, rate, seed=4)
+        row = {"rate_hz": rate}
+        for name, ex, slots in (("graph", graph_ex, args.serve_slots), ("plain", plain_ex, 1)):
+            sch = Scheduler(ex, budget, max_slots=slots)
+            rep = replay_trace(sch, reqs, arr)
+            rep.pop("futures")
+            row[name] = {k: rep[k] for k in ("p50_ms", "p99_ms", "mean_ms", "cubes_per_s",
+                                             "span_s", "batches", "mean_batch", "errors")}
+            row[name]["peak_budget_gb"] = rep["peak_budget_bytes"] / 2 ** 30
+            del sch, rep
+            torch.cuda.synchronize()
+            err(f"rate {rate:g}/s {name}: p50 {row[name]['p50_ms']:.1f} ms, p99 "
+                f"{row[name]['p99_ms']:.1f} ms, {row[name]['cubes_per_s']:.1f} cubes/s, mean "
+                f"batch {row[name]['mean_batch']:.2f}")
+        rows.append(row)
+        if row["graph"]["cubes_per_s"] < 0.6 * rate or rate >= args.serve_rate_max:
+            break
+        rate *= 2
+    out = {"metric": "serving latency p50/p99 (ms) and cubes/s (1 GPU)",
+           "requests": n_req, "particles_total": n_tot,
+           "mean_footprint_mb": float(np.mean(fps)) / 2 ** 20,
+           "max_footprint_mb": float(np.max(fps)) / 2 ** 20,
+           "budget_gb": args.serve_budget_gb, "max_slots": args.serve_slots, "lanes": 2,
+           "grid_blocks": 2048, "data": "synthetic (seeded request stream, seeds 4000+i)",
+           "sweep": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,15 +159,29 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000, help="particles (default: full 1e7)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-backward", action="store_true",
+                    help="skip timing the gradient pass (reported beside the forward step)")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 1 GiB device to device once (a known-size kernel "
                          "for calibrating profiler byte counters)")
+    ap.add_argument("--serve", action="store_true",
+                    help="print the serving report (request stream, batched graph path vs "
+                         "one-at-a-time plain launches) instead of the forward-step line")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-rate0", type=float, default=16.0)
+    ap.add_argument("--serve-rate-max", type=float, default=4096.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the lambda-sharded "
               "design is documented, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        serve_main(args)
+        return
 
     import torch
     from paper_2412_08265_amd import ops, synth
@@ -178,6 +254,28 @@ def main():
                        "psf_lsf_GBs": psf_gbs, "psf_lsf_frac": psf_gbs / PEAK_HBM_GBS},
     }
     err(f"step {ms_step:.3f} ms, stages {st}")
+    if not args.no_backward:
+        # gradient pass beside the forward: adjoint PSF/LSF of a seeded dL/dcube, then the
+        # per-particle adjoint (mass, age, [M/H], v_los, velocities, angles)
+        gen = torch.Generator(device=dev).manual_seed(7)
+        gcube = torch.randn(fw.buf.cube.shape, generator=gen, device=dev)
+        graw = torch.empty_like(gcube)
+
+        def backward():
+            ops.rubix_psf_lsf([fw.job], [gcube], [graw], fw.ws)
+            return ops.cube_backward(fw, graw)
+
+        backward()
+        torch.cuda.synchronize()
+        b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        nb = 3
+        b0.record()
+        for _ in range(nb):
+            backward()
+        b1.record()
+        torch.cuda.synchronize()
+        out["stages_ms"]["backward"] = b0.elapsed_time(b1) / nb
+        err(f"backward {out['stages_ms']['backward']:.3f} ms")
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)

@@ -157,6 +157,38 @@ int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
                         float *const *d_vel, double *d_angles, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* ---- Batched forward pass for replayed launches (serving) -----------------------------------
+ * The calls above upload their job table through kernel arguments. For a serving loop that
+ * replays one captured launch sequence (a HIP graph) for every batch, the table instead lives in
+ * a caller-owned device buffer that the caller refreshes before each replay:
+ *   1. rubix_forward_pack writes the table for a batch into a host buffer (ideally pinned);
+ *   2. the caller copies it to its device table buffer (e.g. hipMemcpyAsync on the stream);
+ *   3. rubix_forward_packed launches rotate/bin -> cube -> PSF/LSF (cube_raw -> cube) for every
+ *      job of that table. Its launch arguments depend only on (dev_table, grid_blocks,
+ *      max_psf_radius, max_sort_passes), never on the table's contents, so the launches can be
+ *      captured once and replayed: each kernel runs grid_blocks blocks that walk the work items
+ *      the table describes (persistent blocks).
+ * The jobs' workspace regions are laid out inside `ws` (size: rubix_workspace_size minus
+ * rubix_table_bytes), which must stay valid until the launches complete. */
+
+/* Bytes of a packed table for n_jobs jobs (0 if n_jobs is out of range). */
+size_t rubix_table_bytes(int n_jobs);
+
+/* Validates the jobs (they need positions, velocities, properties and every output, including
+ * cube) and writes their table into host_table (>= rubix_table_bytes(n_jobs) bytes). Fails with
+ * RUBIX_ERANGE if a job needs a larger PSF radius or more sort passes than the replayed launch
+ * will provide. */
+int rubix_forward_pack(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, void *ws,
+                       size_t ws_bytes, void *host_table, size_t host_table_bytes,
+                       int max_psf_radius, int max_sort_passes);
+
+/* Enqueues the forward pass of the packed table at dev_table (DEVICE, 256-byte aligned) on
+ * `stream`: grid_blocks blocks per kernel (>= 1), LDS sized for max_psf_radius (0..64),
+ * max_sort_passes (1..4) radix passes (jobs needing fewer skip the rest). Results are those of
+ * rubix_rotate_bin + rubix_cube + rubix_psf_lsf(cube_raw -> cube), bit for bit. */
+int rubix_forward_packed(const void *dev_table, int grid_blocks, int max_psf_radius,
+                         int max_sort_passes, void *stream);
+
 /* Message for the last non-zero status returned on this thread ("" if none). */
 const char *rubix_last_error(void);
 

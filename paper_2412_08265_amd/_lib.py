@@ -50,7 +50,8 @@ class RubixJob(ctypes.Structure):
 
 
 EXPORTS = ("rubix_workspace_size", "rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf",
-           "rubix_cube_backward", "rubix_last_error", "rubix_version")
+           "rubix_cube_backward", "rubix_last_error", "rubix_version", "rubix_table_bytes",
+           "rubix_forward_pack", "rubix_forward_packed")
 
 _lib = None
 
@@ -81,8 +82,13 @@ def load() -> ctypes.CDLL:
                                         POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                         POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                         c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.rubix_table_bytes.argtypes = [c_int]
+    lib.rubix_table_bytes.restype = c_size_t
+    lib.rubix_forward_pack.argtypes = [POINTER(RubixJob), c_int, POINTER(RubixSSP), c_void_p,
+                                       c_size_t, c_void_p, c_size_t, c_int, c_int]
+    lib.rubix_forward_packed.argtypes = [c_void_p, c_int, c_int, c_int, c_void_p]
     for f in ("rubix_workspace_size", "rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf",
-              "rubix_cube_backward"):
+              "rubix_cube_backward", "rubix_forward_pack", "rubix_forward_packed"):
         getattr(lib, f).restype = c_int
     lib.rubix_last_error.restype = ctypes.c_char_p
     lib.rubix_version.restype = ctypes.c_char_p

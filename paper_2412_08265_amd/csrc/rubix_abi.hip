@@ -223,6 +223,14 @@ static int check_ws(const rubix_job *jobs, int n_jobs, void *ws, size_t ws_bytes
   return RUBIX_OK;
 }
 
+static int check_ws_regions(const rubix_job *jobs, int n_jobs, void *ws, size_t ws_bytes) {
+  const size_t need = workspace_bytes(jobs, n_jobs) - al(table_bytes(n_jobs));
+  if (!ws) return fail(RUBIX_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(RUBIX_EWORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < need) return fail(RUBIX_EWORKSPACE, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+  return RUBIX_OK;
+}
+
 // ---------------------------------------------------------------------------------------------
 // table construction
 // ---------------------------------------------------------------------------------------------
@@ -273,13 +281,15 @@ struct BwdIO {
 // Builds the table (host bytes) for `jobs` with per-job workspace regions placed after the table
 // region of `ws`. Per-call I/O (PSF/LSF in/out, backward buffers) is optional.
 static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
-                                        void *ws, const PslfIO *pl, const BwdIO *bw) {
+                                        void *ws, const PslfIO *pl, const BwdIO *bw,
+                                        bool table_in_ws = true) {
   std::vector<uint8_t> buf(table_bytes(n_jobs), 0);
   Table *t = reinterpret_cast<Table *>(buf.data());
   JobDev *J = reinterpret_cast<JobDev *>(buf.data() + ((sizeof(Table) + 255) & ~size_t(255)));
   t->h.n_jobs = n_jobs;
   fill_ssp(t->h.ssp, ssp);
-  uint8_t *region = static_cast<uint8_t *>(ws) + al(table_bytes(n_jobs));
+  // per-job regions follow the table when the table is uploaded to the workspace head
+  uint8_t *region = static_cast<uint8_t *>(ws) + (table_in_ws ? al(table_bytes(n_jobs)) : 0);
   int64_t start[NK] = {0};
   int max_passes = 1;
   for (int k = 0; k < n_jobs; ++k) {
@@ -485,6 +495,63 @@ int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
   BwdIO io{grad_raw, d_mass, d_age, d_met, d_vlos, d_vel, d_angles};
   auto tab = build_table(jobs, n_jobs, ssp, ws, nullptr, &io);
   return run(tab, ws, static_cast<hipStream_t>(stream), launch_backward, "rubix_cube_backward");
+}
+
+size_t rubix_table_bytes(int n_jobs) {
+  if (n_jobs < 1 || n_jobs > RUBIX_MAX_JOBS) return 0;
+  return al(table_bytes(n_jobs));
+}
+
+int rubix_forward_pack(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, void *ws,
+                       size_t ws_bytes, void *host_table, size_t host_table_bytes,
+                       int max_psf_radius, int max_sort_passes) {
+  g_err.clear();
+  int rc;
+  if ((rc = validate_jobs(jobs, n_jobs, CALL_PACK))) return rc;
+  if ((rc = validate_ssp(ssp))) return rc;
+  if ((rc = check_ws_regions(jobs, n_jobs, ws, ws_bytes))) return rc;
+  if (!host_table) return fail(RUBIX_EINVAL, "host_table is NULL");
+  if (host_table_bytes < al(table_bytes(n_jobs)))
+    return fail(RUBIX_EINVAL, "host_table of %zu bytes < %zu needed", host_table_bytes,
+                al(table_bytes(n_jobs)));
+  std::vector<const float *> in(n_jobs);
+  std::vector<float *> out(n_jobs);
+  for (int k = 0; k < n_jobs; ++k) { in[k] = jobs[k].cube_raw; out[k] = jobs[k].cube; }
+  PslfIO io{in.data(), out.data()};
+  auto tab = build_table(jobs, n_jobs, ssp, ws, &io, nullptr, /*table_in_ws=*/false);
+  const Table *t = reinterpret_cast<const Table *>(tab.data());
+  if (t->h.max_psf_r > max_psf_radius || t->h.max_lsf_r > RUBIX_MAX_RADIUS)
+    return fail(RUBIX_ERANGE, "a job's PSF radius %d exceeds the packed launch's %d",
+                t->h.max_psf_r, max_psf_radius);
+  if (t->h.max_passes > max_sort_passes)
+    return fail(RUBIX_ERANGE, "a job needs %d sort passes, the packed launch runs %d",
+                t->h.max_passes, max_sort_passes);
+  memcpy(host_table, tab.data(), tab.size());
+  return RUBIX_OK;
+}
+
+int rubix_forward_packed(const void *dev_table, int grid_blocks, int max_psf_radius,
+                         int max_sort_passes, void *stream) {
+  g_err.clear();
+  if (!dev_table) return fail(RUBIX_EINVAL, "dev_table is NULL");
+  if (grid_blocks < 1) return fail(RUBIX_EINVAL, "grid_blocks=%d < 1", grid_blocks);
+  if (max_psf_radius < 0 || max_psf_radius > RUBIX_MAX_RADIUS)
+    return fail(RUBIX_EINVAL, "max_psf_radius=%d outside [0, %d]", max_psf_radius, RUBIX_MAX_RADIUS);
+  if (max_sort_passes < 1 || max_sort_passes > 4)
+    return fail(RUBIX_EINVAL, "max_sort_passes=%d outside [1, 4]", max_sort_passes);
+  // launch shapes that do not depend on the table: every kind gets grid_blocks blocks and walks
+  // the totals it reads from the device table
+  TableHeader h;
+  memset(&h, 0, sizeof h);
+  for (int q = 0; q < NK; ++q) h.total[q] = grid_blocks;
+  h.max_passes = max_sort_passes;
+  h.max_psf_r = max_psf_radius;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Table *dt = static_cast<const Table *>(dev_table);
+  hipError_t e = launch_rotate_bin(dt, h, grid_blocks, s);
+  if (e == hipSuccess) e = launch_cube(dt, h, grid_blocks, s);
+  if (e == hipSuccess) e = launch_psf_lsf(dt, h, grid_blocks, s);
+  return device_status(e, "rubix_forward_packed");
 }
 
 }  // extern "C"

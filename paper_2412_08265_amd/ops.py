@@ -200,6 +200,26 @@ def rubix_cube_backward(jobs, ssp: DeviceSSP, grad_raw, d_mass, d_age, d_met, d_
                                   _stream(stream)))
 
 
+def rubix_table_bytes(n_jobs: int) -> int:
+    return int(_lib.load().rubix_table_bytes(int(n_jobs)))
+
+
+def rubix_forward_pack(jobs, ssp: DeviceSSP, ws: torch.Tensor, host_table: torch.Tensor,
+                       max_psf_radius: int, max_sort_passes: int) -> None:
+    """Write the packed table of a forward batch into host_table (a uint8 CPU tensor)."""
+    lib = _lib.load()
+    check(lib.rubix_forward_pack(_jobs_array(jobs), len(jobs), byref(ssp.c), ws.data_ptr(),
+                                 ws.numel(), host_table.data_ptr(), host_table.numel(),
+                                 int(max_psf_radius), int(max_sort_passes)))
+
+
+def rubix_forward_packed(dev_table: torch.Tensor, grid_blocks: int, max_psf_radius: int,
+                         max_sort_passes: int, stream=None) -> None:
+    lib = _lib.load()
+    check(lib.rubix_forward_packed(dev_table.data_ptr(), int(grid_blocks), int(max_psf_radius),
+                                   int(max_sort_passes), _stream(stream)))
+
+
 # --------------------------------------------------------------------------------------------------
 # one galaxy through the pipeline
 # --------------------------------------------------------------------------------------------------

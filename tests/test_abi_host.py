@@ -22,13 +22,14 @@ def lib():
 def _declared():
     with open(os.path.join(ROOT, "include", "rubix.h")) as f:
         src = f.read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(rubix_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*)\s*(rubix_\w+)\s*\(", src, re.M)))
 
 
 def test_exports_every_declared_symbol(lib):
     names = _declared()
     assert {"rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf", "rubix_cube_backward",
-            "rubix_workspace_size", "rubix_last_error"} <= set(names)
+            "rubix_workspace_size", "rubix_last_error", "rubix_table_bytes",
+            "rubix_forward_pack", "rubix_forward_packed"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
     assert lib.rubix_version().decode().startswith("rubix-mi355x")
@@ -122,6 +123,36 @@ def test_ssp_validation(lib):
         assert _ws_size(lib, [_job()], ctypes.byref(bad))[0] == -1, (la, mz, n)
     big, keep3 = _ssp_c(np.arange(256) * 0.01, np.arange(64) * 0.01, 200000)
     assert _ws_size(lib, [_job()], ctypes.byref(big))[0] == -4
+
+
+def test_packed_table_sizes_and_validation(lib):
+    """The packed forward path checks its arguments on the host: table sizes, workspace regions,
+    the replayed launch's PSF radius and sort passes, the launch shape."""
+    from paper_2412_08265_amd import _lib
+    t1, t64 = lib.rubix_table_bytes(1), lib.rubix_table_bytes(64)
+    assert t1 > 0 and t1 % 256 == 0 and t64 > t1
+    assert lib.rubix_table_bytes(0) == 0 and lib.rubix_table_bytes(65) == 0
+    ssp, keep = _ssp_c([-1, 0, 1], [-2, 0])
+    j = _job(n=1000)
+    j.psf_sigma_spx = 2.0                      # radius 8
+    rc, full = _ws_size(lib, [j])
+    regions = full - t1
+    host = (ctypes.c_uint8 * t1)()
+    pack = lambda ws, nb, tb, r, p: lib.rubix_forward_pack(_arr(j), 1, ctypes.byref(ssp), ws, nb,
+                                                          host, tb, r, p)
+    assert pack(0x1000, regions, t1, 8, 1) == _lib.RUBIX_OK
+    assert pack(0x1000, regions - 1, t1, 8, 1) == _lib.RUBIX_EWORKSPACE
+    assert pack(0x1000, regions, t1 - 1, 8, 1) == _lib.RUBIX_EINVAL
+    assert pack(0x1000, regions, t1, 7, 1) == _lib.RUBIX_ERANGE      # PSF radius 8 > 7
+    big = _job(n=1000, nx=300, ny=300)          # 90001 keys: 3 radix passes
+    rc, fb = _ws_size(lib, [big])
+    assert lib.rubix_forward_pack(_arr(big), 1, ctypes.byref(ssp), 0x1000, fb, host, t1, 8,
+                                  2) == _lib.RUBIX_ERANGE
+    j.cube = None
+    assert pack(0x1000, regions, t1, 8, 1) == _lib.RUBIX_EINVAL       # needs the cube output
+    for args in ((None, 64, 8, 2), (0x1000, 0, 8, 2), (0x1000, 64, 65, 2), (0x1000, 64, 8, 0),
+                 (0x1000, 64, 8, 5)):
+        assert lib.rubix_forward_packed(*args, None) == _lib.RUBIX_EINVAL, args
 
 
 def test_product_path_never_touches_the_oracle():
