@@ -166,8 +166,10 @@ int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
  *   3. rubix_forward_packed launches rotate/bin -> cube -> PSF/LSF (cube_raw -> cube) for every
  *      job of that table. Its launch arguments depend only on (dev_table, grid_blocks,
  *      max_psf_radius, max_sort_passes), never on the table's contents, so the launches can be
- *      captured once and replayed: each kernel runs grid_blocks blocks that walk the work items
- *      the table describes (persistent blocks).
+ *      captured once and replayed: each kernel runs grid_blocks blocks that claim the work items
+ *      the table describes one at a time (persistent blocks). The claims consume counters held
+ *      in the device table, so the table must be copied afresh from the host buffer before every
+ *      launch (replaying without the copy skips the work).
  * The jobs' workspace regions are laid out inside `ws` (size: rubix_workspace_size minus
  * rubix_table_bytes), which must stay valid until the launches complete. */
 

@@ -53,7 +53,8 @@ __device__ __forceinline__ double clamp01(double t) { return fmin(1.0, fmax(0.0,
 __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__ T, int mode) {
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_PREP]; vb += gridDim.x) {
+  const Items items(T, K_PREP, C_PREP);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int jj = find_job(T, K_PREP, vb);
     const JobDev &J = jobs[jj];
     const int64_t i = (vb - J.vb_start[K_PREP]) * kPrepThreads + threadIdx.x;
@@ -258,7 +259,8 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
   // byte offsets of this lane's node in the four corner rows relative to corner (ja, jz)
   const uint32_t lb[4] = {(uint32_t)lane * 4u, (uint32_t)(lane + o1) * 4u,
                           (uint32_t)(lane + o2) * 4u, (uint32_t)(lane + o3) * 4u};
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_CUBE]; vb += gridDim.x) {
+  const Items items(T, K_CUBE, C_CUBE);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int jj = find_job(T, K_CUBE, vb);
     const JobDev &J = jobs[jj];
     const int64_t local = vb - J.vb_start[K_CUBE];
@@ -368,7 +370,8 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
 
 __global__ __launch_bounds__(kCubeThreads) void k_combine(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_COMB]; vb += gridDim.x) {
+  const Items items(T, K_COMB, C_COMB);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int jj = find_job(T, K_COMB, vb);
     const JobDev &J = jobs[jj];
     const int64_t local = vb - J.vb_start[K_COMB];

@@ -20,7 +20,8 @@ __global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T) {
   __shared__ __attribute__((aligned(16))) float buf[kLsfOut + 2 * RUBIX_MAX_RADIUS + 8];
   const JobDev *jobs = table_jobs(T);
   const int tid = threadIdx.x;
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_LSF]; vb += gridDim.x) {
+  const Items items(T, K_LSF, C_LSF);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int jj = find_job(T, K_LSF, vb);
     const JobDev &J = jobs[jj];
     const int nt = (J.n_tel + kLsfOut - 1) / kLsfOut;
@@ -84,7 +85,8 @@ __global__ __launch_bounds__(256) void k_psf(const Table *__restrict__ T) {
   const int kind = AXIS == 0 ? K_PSFY : K_PSFX;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  for (int64_t vb = blockIdx.x; vb < T->h.total[kind]; vb += gridDim.x) {
+  const Items items(T, kind, AXIS == 0 ? C_PSFY : C_PSFX);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int jj = find_job(T, kind, vb);
     const JobDev &J = jobs[jj];
     const int nseg = AXIS == 0 ? J.n_psf_seg_y : J.n_psf_seg_x;
@@ -142,7 +144,8 @@ __global__ __launch_bounds__(256) void k_psf(const Table *__restrict__ T) {
 // Identity operator (no PSF and no LSF) into a separate output buffer.
 __global__ __launch_bounds__(256) void k_copy(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_COPY]; vb += gridDim.x) {
+  const Items items(T, K_COPY, C_COPY);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int jj = find_job(T, K_COPY, vb);
     const JobDev &J = jobs[jj];
     const int64_t base = (vb - J.vb_start[K_COPY]) * 65536;

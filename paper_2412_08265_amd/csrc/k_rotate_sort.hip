@@ -36,7 +36,8 @@ __device__ __forceinline__ void rotate_one(const JobDev &J, int i) {
 
 __global__ __launch_bounds__(kSortThreads) void k_rotate(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_ROT]; vb += gridDim.x) {
+  const Items items(T, K_ROT, C_ROT);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int j = find_job(T, K_ROT, vb);
     const JobDev &J = jobs[j];
     const int64_t base = (vb - J.vb_start[K_ROT]) * kSortTile;
@@ -59,7 +60,8 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const Table *__restrict__
   __shared__ uint32_t h[256];
   const JobDev *jobs = table_jobs(T);
   const int shift = 8 * pass;
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_ROT]; vb += gridDim.x) {
+  const Items items(T, K_ROT, C_HIST + pass);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int j = find_job(T, K_ROT, vb);
     const JobDev &J = jobs[j];
     if (pass >= J.passes) continue;          // uniform: this job needs fewer passes
@@ -102,7 +104,8 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
 __global__ __launch_bounds__(256) void k_scan(const Table *__restrict__ T, int pass) {
   __shared__ uint32_t lds[256];
   const JobDev *jobs = table_jobs(T);
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_SCAN]; vb += gridDim.x) {
+  const Items items(T, K_SCAN, C_SCAN + pass);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int j = find_job(T, K_SCAN, vb);
     const JobDev &J = jobs[j];
     if (pass >= J.passes) continue;
@@ -139,7 +142,8 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restric
   const int w = t >> 6;
   const int lane = t & 63;
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_ROT]; vb += gridDim.x) {
+  const Items items(T, K_ROT, C_SCAT + pass);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int j = find_job(T, K_ROT, vb);
     const JobDev &J = jobs[j];
     if (pass >= J.passes) continue;
@@ -212,7 +216,8 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restric
 // seg_off[s] = number of sorted keys < s (lower bound), s = 0..n_s.
 __global__ __launch_bounds__(256) void k_segoff(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_SEG]; vb += gridDim.x) {
+  const Items items(T, K_SEG, C_SEG);
+  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
     const int j = find_job(T, K_SEG, vb);
     const JobDev &J = jobs[j];
     const int64_t s = (vb - J.vb_start[K_SEG]) * 256 + threadIdx.x;
