@@ -50,11 +50,11 @@ __device__ __forceinline__ int cell_of(const double *thr, int n, double x) {
 __device__ __forceinline__ double clamp01(double t) { return fmin(1.0, fmax(0.0, t)); }
 
 // mode 0: forward weights flux_scale*m*J*w_c; mode 1: plain bilinear weights w_c.
-__global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__ T, int mode) {
+__global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__ T, unsigned long long *__restrict__ claim, int mode) {
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
-  const Items items(T, K_PREP, C_PREP);
-  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
+  const Items items(T, K_PREP, claim, C_PREP);
+  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
     const int jj = find_job(T, K_PREP, vb);
     const JobDev &J = jobs[jj];
     const int64_t i = (vb - J.vb_start[K_PREP]) * kPrepThreads + threadIdx.x;
@@ -247,7 +247,7 @@ __device__ __forceinline__ void split_index(const JobDev &J, const SspDev &S, in
   lamf = (float)lam;
 }
 
-__global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__ T) {
+__global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__ T, unsigned long long *__restrict__ claim) {
   __shared__ float slots[kCubeThreads / 64][kCubeGroup][64];
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
@@ -259,8 +259,8 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
   // byte offsets of this lane's node in the four corner rows relative to corner (ja, jz)
   const uint32_t lb[4] = {(uint32_t)lane * 4u, (uint32_t)(lane + o1) * 4u,
                           (uint32_t)(lane + o2) * 4u, (uint32_t)(lane + o3) * 4u};
-  const Items items(T, K_CUBE, C_CUBE);
-  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
+  const Items items(T, K_CUBE, claim, C_CUBE);
+  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
     const int jj = find_job(T, K_CUBE, vb);
     const JobDev &J = jobs[jj];
     const int64_t local = vb - J.vb_start[K_CUBE];
@@ -368,10 +368,10 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
   }
 }
 
-__global__ __launch_bounds__(kCubeThreads) void k_combine(const Table *__restrict__ T) {
+__global__ __launch_bounds__(kCubeThreads) void k_combine(const Table *__restrict__ T, unsigned long long *__restrict__ claim) {
   const JobDev *jobs = table_jobs(T);
-  const Items items(T, K_COMB, C_COMB);
-  for (int64_t vb = items.first(T); vb < items.total; vb = items.next(T, vb)) {
+  const Items items(T, K_COMB, claim, C_COMB);
+  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
     const int jj = find_job(T, K_COMB, vb);
     const JobDev &J = jobs[jj];
     const int64_t local = vb - J.vb_start[K_COMB];
@@ -397,23 +397,25 @@ static inline int grid_for(int64_t total, int cap) {
 }
 
 hipError_t launch_cube(const Table *dt, const TableHeader &h, int cap, hipStream_t s) {
+  unsigned long long *cl = table_claims(dt);
   int g;
   if ((g = grid_for(h.total[K_PREP], cap)))
-    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, 0);
+    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, cl, 0);
   if ((g = grid_for(h.total[K_CHUNK], cap)))
     hipLaunchKernelGGL(k_chunks, dim3(g), dim3(1024), 0, s, dt);
   if ((g = grid_for(h.total[K_CUBE], cap)))
-    hipLaunchKernelGGL(k_cube, dim3(g), dim3(kCubeThreads), 0, s, dt);
+    hipLaunchKernelGGL(k_cube, dim3(g), dim3(kCubeThreads), 0, s, dt, cl);
   if ((g = grid_for(h.total[K_COMB], cap)))
-    hipLaunchKernelGGL(k_combine, dim3(g), dim3(kCubeThreads), 0, s, dt);
+    hipLaunchKernelGGL(k_combine, dim3(g), dim3(kCubeThreads), 0, s, dt, cl);
   return hipGetLastError();
 }
 
 // Backward needs the same per-particle records with plain bilinear weights.
 hipError_t launch_prep_backward(const Table *dt, const TableHeader &h, int cap, hipStream_t s) {
+  unsigned long long *cl = table_claims(dt);
   int g;
   if ((g = grid_for(h.total[K_PREP], cap)))
-    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, 1);
+    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, cl, 1);
   return hipGetLastError();
 }
 

@@ -161,15 +161,15 @@ __host__ __device__ inline size_t table_bytes(int n_jobs) {
 }
 
 // The work items of one launch. A grid with at least one block per item gives block b item b. A
-// smaller (persistent) grid hands items out in increasing order from the launch's counter in
-// the table, one at a time per block, so blocks that draw heavy items take fewer of them. Every
-// thread of the block must call first()/next() (they contain block barriers); the item is
-// block-uniform.
-__device__ __forceinline__ int64_t claim_item(const Table *t, int slot) {
+// smaller (persistent) grid hands items out in increasing order from the launch's counter, one at
+// a time per block, so blocks that draw heavy items take fewer of them. Every thread of the block
+// must call first()/next() (they contain block barriers); the item is block-uniform.
+// The counters sit in the table header but reach the kernels as a separate argument: the table
+// itself is never written during a launch, so the compiler may read it through the scalar cache.
+__device__ __forceinline__ int64_t claim_item(unsigned long long *ctr) {
   __shared__ int64_t s_item;
   __syncthreads();                            // the last item's readers are done with s_item
-  if (threadIdx.x == 0)
-    s_item = (int64_t)atomicAdd(const_cast<unsigned long long *>(&t->h.claim[slot]), 1ull);
+  if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(ctr, 1ull);
   __syncthreads();
   const int64_t v = s_item;
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -180,16 +180,18 @@ __device__ __forceinline__ int64_t claim_item(const Table *t, int slot) {
 struct Items {
   int64_t total;
   bool dyn;
-  int slot;
-  __device__ Items(const Table *t, int kind, int claim_slot)
-      : total(t->h.total[kind]), dyn((int64_t)gridDim.x < t->h.total[kind]), slot(claim_slot) {}
-  __device__ int64_t first(const Table *t) const {
-    return dyn ? claim_item(t, slot) : (int64_t)blockIdx.x;
-  }
-  __device__ int64_t next(const Table *t, int64_t vb) const {
-    return dyn ? claim_item(t, slot) : vb + gridDim.x;
-  }
+  unsigned long long *ctr;
+  __device__ Items(const Table *t, int kind, unsigned long long *claim, int slot)
+      : total(t->h.total[kind]), dyn((int64_t)gridDim.x < t->h.total[kind]), ctr(claim + slot) {}
+  __device__ int64_t first() const { return dyn ? claim_item(ctr) : (int64_t)blockIdx.x; }
+  __device__ int64_t next(int64_t vb) const { return dyn ? claim_item(ctr) : vb + gridDim.x; }
 };
+
+// Device address of a table's claim counters.
+inline unsigned long long *table_claims(const Table *dt) {
+  return reinterpret_cast<unsigned long long *>(reinterpret_cast<uintptr_t>(dt) +
+                                                offsetof(TableHeader, claim));
+}
 
 // Largest job index j with jobs[j].vb_start[kind] <= vb (vb is wave-uniform).
 __device__ inline int find_job(const Table *t, int kind, int64_t vb) {
