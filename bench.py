@@ -111,11 +111,16 @@ def serve_main(args):
         if (i + 1) % 32 == 0:
             err(f"generated {i + 1}/{n_req} requests ({n_tot:.3g} particles)")
     budget = int(args.serve_budget_gb * 2 ** 30)
-    graph_ex = GraphExecutor(dssp, max_jobs=args.serve_slots, lanes=2, grid_blocks=2048)
-    plain_ex = PlainExecutor(dssp)
-    fps = [graph_ex.footprint(r) for r in reqs]
-    # warm both paths (module load, graph upload) on the first requests
-    for ex, slots in ((graph_ex, args.serve_slots), (plain_ex, 1)):
+    execs = {"graph": (GraphExecutor(dssp, max_jobs=args.serve_slots, lanes=2, mode="native"),
+                       args.serve_slots),
+             "persistent": (GraphExecutor(dssp, max_jobs=args.serve_slots, lanes=2,
+                                          mode="persistent", grid_blocks=2048), args.serve_slots),
+             "plain": (PlainExecutor(dssp), 1)}
+    execs = {k: v for k, v in execs.items() if k in args.serve_modes.split(",")}
+    fps = [execs["plain"][0].footprint(r) for r in reqs] if "plain" in execs else \
+        [next(iter(execs.values()))[0].footprint(r) for r in reqs]
+    # warm every path (module load, graph upload) on the first requests
+    for ex, slots in execs.values():
         sch = Scheduler(ex, budget, max_slots=slots)
         for r in reqs[:4]:
             sch.submit(r)
@@ -126,7 +131,7 @@ def serve_main(args):
     while True:
         arr = synth.poisson_arrivals(n_req, rate, seed=4)
         row = {"rate_hz": rate}
-        for name, ex, slots in (("graph", graph_ex, args.serve_slots), ("plain", plain_ex, 1)):
+        for name, (ex, slots) in execs.items():
             sch = Scheduler(ex, budget, max_slots=slots)
             rep = replay_trace(sch, reqs, arr)
             rep.pop("futures")
@@ -139,7 +144,8 @@ def serve_main(args):
                 f"{row[name]['p99_ms']:.1f} ms, {row[name]['cubes_per_s']:.1f} cubes/s, mean "
                 f"batch {row[name]['mean_batch']:.2f}")
         rows.append(row)
-        if row["graph"]["cubes_per_s"] < 0.6 * rate or rate >= args.serve_rate_max:
+        first = next(iter(execs))
+        if row[first]["cubes_per_s"] < 0.6 * rate or rate >= args.serve_rate_max:
             break
         rate *= 2
     out = {"metric": "serving latency p50/p99 (ms) and cubes/s (1 GPU)",
@@ -147,7 +153,10 @@ def serve_main(args):
            "mean_footprint_mb": float(np.mean(fps)) / 2 ** 20,
            "max_footprint_mb": float(np.max(fps)) / 2 ** 20,
            "budget_gb": args.serve_budget_gb, "max_slots": args.serve_slots, "lanes": 2,
-           "grid_blocks": 2048, "data": "synthetic (seeded request stream, seeds 4000+i)",
+           "modes": {"graph": "native forward graph per lane, exact grids per batch",
+                     "persistent": "torch-captured rubix_forward_packed, 2048-block grids",
+                     "plain": "one request at a time, plain entry points"},
+           "data": "synthetic (seeded request stream, seeds 4000+i)",
            "sweep": rows}
     print(json.dumps(out), flush=True)
 
@@ -173,6 +182,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-rate0", type=float, default=16.0)
     ap.add_argument("--serve-rate-max", type=float, default=4096.0)
+    ap.add_argument("--serve-modes", default="graph,persistent,plain",
+                    help="executors to compare (the first one decides when the sweep stops)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the lambda-sharded "

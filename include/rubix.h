@@ -191,6 +191,36 @@ int rubix_forward_pack(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, 
 int rubix_forward_packed(const void *dev_table, int grid_blocks, int max_psf_radius,
                          int max_sort_passes, void *stream);
 
+/* ---- Forward graph (serving) ------------------------------------------------------------------
+ * A forward graph holds the whole forward launch sequence (rotate/bin, cube, PSF/LSF with
+ * cube_raw -> cube) of packed tables at one device address, captured once as a HIP graph and
+ * instantiated. Each launch copies a packed table (rubix_forward_pack) to that address, sets
+ * every kernel's grid to the table's work-item count, and launches the graph: the kernels run
+ * exactly as in the plain entry points (one block per work item), so results are bitwise those of
+ * rubix_rotate_bin + rubix_cube + rubix_psf_lsf, at the host cost of one graph launch.
+ * Unlike the rest of this library a graph is state: it owns a HIP graph and its instantiation
+ * (host and driver resources; no device memory is allocated) until rubix_graph_destroy. */
+typedef struct rubix_graph_s *rubix_graph;
+
+/* Captures and instantiates the forward sequence for tables of up to max_jobs jobs at dev_table
+ * (DEVICE, >= rubix_table_bytes(max_jobs) bytes, 256-byte aligned, valid for the graph's life),
+ * with LDS for PSF radii up to max_psf_radius (0..64) and max_sort_passes (1..4) radix passes.
+ * Capture runs on a private stream and launches nothing. *out = NULL on failure. */
+int rubix_graph_create(const void *dev_table, int max_jobs, int max_psf_radius,
+                       int max_sort_passes, rubix_graph *out);
+
+/* Enqueues on `stream`: the copy of host_table (written by rubix_forward_pack with the same radius
+ * and pass limits; pinned host memory makes the copy asynchronous; it must stay unchanged until
+ * the copy has run) to the graph's dev_table, then the graph with grids from that table. The
+ * jobs' buffers and the workspace named in the table must stay valid until the graph completes.
+ * The graph's previous launch must have completed before the next call (its grids are updated
+ * in place). */
+int rubix_graph_launch(rubix_graph g, const void *host_table, size_t host_table_bytes,
+                       void *stream);
+
+/* Releases the graph (NULL is ignored). Its launches must have completed. */
+int rubix_graph_destroy(rubix_graph g);
+
 /* Message for the last non-zero status returned on this thread ("" if none). */
 const char *rubix_last_error(void);
 

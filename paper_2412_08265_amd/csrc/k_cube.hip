@@ -50,11 +50,10 @@ __device__ __forceinline__ int cell_of(const double *thr, int n, double x) {
 __device__ __forceinline__ double clamp01(double t) { return fmin(1.0, fmax(0.0, t)); }
 
 // mode 0: forward weights flux_scale*m*J*w_c; mode 1: plain bilinear weights w_c.
-__global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__ T, unsigned long long *__restrict__ claim, int mode) {
+__global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__ T, int mode) {
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
-  const Items items(T, K_PREP, claim, C_PREP);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_PREP]; vb += gridDim.x) {
     const int jj = find_job(T, K_PREP, vb);
     const JobDev &J = jobs[jj];
     const int64_t i = (vb - J.vb_start[K_PREP]) * kPrepThreads + threadIdx.x;
@@ -247,7 +246,7 @@ __device__ __forceinline__ void split_index(const JobDev &J, const SspDev &S, in
   lamf = (float)lam;
 }
 
-__global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__ T, unsigned long long *__restrict__ claim) {
+__global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__ T) {
   __shared__ float slots[kCubeThreads / 64][kCubeGroup][64];
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
@@ -259,8 +258,7 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
   // byte offsets of this lane's node in the four corner rows relative to corner (ja, jz)
   const uint32_t lb[4] = {(uint32_t)lane * 4u, (uint32_t)(lane + o1) * 4u,
                           (uint32_t)(lane + o2) * 4u, (uint32_t)(lane + o3) * 4u};
-  const Items items(T, K_CUBE, claim, C_CUBE);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_CUBE]; vb += gridDim.x) {
     const int jj = find_job(T, K_CUBE, vb);
     const JobDev &J = jobs[jj];
     const int64_t local = vb - J.vb_start[K_CUBE];
@@ -368,10 +366,9 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
   }
 }
 
-__global__ __launch_bounds__(kCubeThreads) void k_combine(const Table *__restrict__ T, unsigned long long *__restrict__ claim) {
+__global__ __launch_bounds__(kCubeThreads) void k_combine(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
-  const Items items(T, K_COMB, claim, C_COMB);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_COMB]; vb += gridDim.x) {
     const int jj = find_job(T, K_COMB, vb);
     const JobDev &J = jobs[jj];
     const int64_t local = vb - J.vb_start[K_COMB];
@@ -397,26 +394,32 @@ static inline int grid_for(int64_t total, int cap) {
 }
 
 hipError_t launch_cube(const Table *dt, const TableHeader &h, int cap, hipStream_t s) {
-  unsigned long long *cl = table_claims(dt);
   int g;
   if ((g = grid_for(h.total[K_PREP], cap)))
-    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, cl, 0);
+    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, 0);
   if ((g = grid_for(h.total[K_CHUNK], cap)))
     hipLaunchKernelGGL(k_chunks, dim3(g), dim3(1024), 0, s, dt);
   if ((g = grid_for(h.total[K_CUBE], cap)))
-    hipLaunchKernelGGL(k_cube, dim3(g), dim3(kCubeThreads), 0, s, dt, cl);
+    hipLaunchKernelGGL(k_cube, dim3(g), dim3(kCubeThreads), 0, s, dt);
   if ((g = grid_for(h.total[K_COMB], cap)))
-    hipLaunchKernelGGL(k_combine, dim3(g), dim3(kCubeThreads), 0, s, dt, cl);
+    hipLaunchKernelGGL(k_combine, dim3(g), dim3(kCubeThreads), 0, s, dt);
   return hipGetLastError();
 }
 
 // Backward needs the same per-particle records with plain bilinear weights.
 hipError_t launch_prep_backward(const Table *dt, const TableHeader &h, int cap, hipStream_t s) {
-  unsigned long long *cl = table_claims(dt);
   int g;
   if ((g = grid_for(h.total[K_PREP], cap)))
-    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, cl, 1);
+    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, 1);
   return hipGetLastError();
+}
+
+int cube_kernel_kind(const void *f) {
+  if (f == (const void *)k_prep) return K_PREP;
+  if (f == (const void *)k_chunks) return K_CHUNK;
+  if (f == (const void *)k_cube) return K_CUBE;
+  if (f == (const void *)k_combine) return K_COMB;
+  return -1;
 }
 
 }  // namespace rubix

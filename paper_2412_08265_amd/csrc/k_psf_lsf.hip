@@ -16,12 +16,11 @@
 
 namespace rubix {
 
-__global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T, unsigned long long *__restrict__ claim) {
+__global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T) {
   __shared__ __attribute__((aligned(16))) float buf[kLsfOut + 2 * RUBIX_MAX_RADIUS + 8];
   const JobDev *jobs = table_jobs(T);
   const int tid = threadIdx.x;
-  const Items items(T, K_LSF, claim, C_LSF);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_LSF]; vb += gridDim.x) {
     const int jj = find_job(T, K_LSF, vb);
     const JobDev &J = jobs[jj];
     const int nt = (J.n_tel + kLsfOut - 1) / kLsfOut;
@@ -79,14 +78,13 @@ __global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T, unsign
 // AXIS 0: PSF along y (a line is one x column); AXIS 1: PSF along x (a line is one y row).
 // Dynamic LDS: (kPsfSeg + 2 * max_psf_r) rows of kPsfLanes floats.
 template <int AXIS>
-__global__ __launch_bounds__(256) void k_psf(const Table *__restrict__ T, unsigned long long *__restrict__ claim) {
+__global__ __launch_bounds__(256) void k_psf(const Table *__restrict__ T) {
   extern __shared__ float buf[];
   const JobDev *jobs = table_jobs(T);
   const int kind = AXIS == 0 ? K_PSFY : K_PSFX;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const Items items(T, kind, claim, AXIS == 0 ? C_PSFY : C_PSFX);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[kind]; vb += gridDim.x) {
     const int jj = find_job(T, kind, vb);
     const JobDev &J = jobs[jj];
     const int nseg = AXIS == 0 ? J.n_psf_seg_y : J.n_psf_seg_x;
@@ -142,10 +140,9 @@ __global__ __launch_bounds__(256) void k_psf(const Table *__restrict__ T, unsign
 }
 
 // Identity operator (no PSF and no LSF) into a separate output buffer.
-__global__ __launch_bounds__(256) void k_copy(const Table *__restrict__ T, unsigned long long *__restrict__ claim) {
+__global__ __launch_bounds__(256) void k_copy(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
-  const Items items(T, K_COPY, claim, C_COPY);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_COPY]; vb += gridDim.x) {
     const int jj = find_job(T, K_COPY, vb);
     const JobDev &J = jobs[jj];
     const int64_t base = (vb - J.vb_start[K_COPY]) * 65536;
@@ -165,16 +162,23 @@ static inline int grid_for(int64_t total, int cap) {
 }
 
 hipError_t launch_psf_lsf(const Table *dt, const TableHeader &h, int cap, hipStream_t s) {
-  unsigned long long *cl = table_claims(dt);
   int g;
   const size_t psf_lds = sizeof(float) * kPsfLanes * (kPsfSeg + 2 * h.max_psf_r + 4);
-  if ((g = grid_for(h.total[K_LSF], cap))) hipLaunchKernelGGL(k_lsf, dim3(g), dim3(256), 0, s, dt, cl);
+  if ((g = grid_for(h.total[K_LSF], cap))) hipLaunchKernelGGL(k_lsf, dim3(g), dim3(256), 0, s, dt);
   if ((g = grid_for(h.total[K_PSFY], cap)))
-    hipLaunchKernelGGL(k_psf<0>, dim3(g), dim3(256), psf_lds, s, dt, cl);
+    hipLaunchKernelGGL(k_psf<0>, dim3(g), dim3(256), psf_lds, s, dt);
   if ((g = grid_for(h.total[K_PSFX], cap)))
-    hipLaunchKernelGGL(k_psf<1>, dim3(g), dim3(256), psf_lds, s, dt, cl);
-  if ((g = grid_for(h.total[K_COPY], cap))) hipLaunchKernelGGL(k_copy, dim3(g), dim3(256), 0, s, dt, cl);
+    hipLaunchKernelGGL(k_psf<1>, dim3(g), dim3(256), psf_lds, s, dt);
+  if ((g = grid_for(h.total[K_COPY], cap))) hipLaunchKernelGGL(k_copy, dim3(g), dim3(256), 0, s, dt);
   return hipGetLastError();
+}
+
+int psf_lsf_kernel_kind(const void *f) {
+  if (f == (const void *)k_lsf) return K_LSF;
+  if (f == (const void *)k_psf<0>) return K_PSFY;
+  if (f == (const void *)k_psf<1>) return K_PSFX;
+  if (f == (const void *)k_copy) return K_COPY;
+  return -1;
 }
 
 }  // namespace rubix

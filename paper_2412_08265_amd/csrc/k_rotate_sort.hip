@@ -34,10 +34,9 @@ __device__ __forceinline__ void rotate_one(const JobDev &J, int i) {
   J.vlos[i] = (float)vl;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_rotate(const Table *__restrict__ T, unsigned long long *__restrict__ claim) {
+__global__ __launch_bounds__(kSortThreads) void k_rotate(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
-  const Items items(T, K_ROT, claim, C_ROT);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_ROT]; vb += gridDim.x) {
     const int j = find_job(T, K_ROT, vb);
     const JobDev &J = jobs[j];
     const int64_t base = (vb - J.vb_start[K_ROT]) * kSortTile;
@@ -56,12 +55,11 @@ __device__ __forceinline__ const uint32_t *sort_src_keys(const JobDev &J, int pa
   return pass == 0 ? reinterpret_cast<const uint32_t *>(J.key) : J.kbuf[(pass - 1) & 1];
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_hist(const Table *__restrict__ T, unsigned long long *__restrict__ claim, int pass) {
+__global__ __launch_bounds__(kSortThreads) void k_hist(const Table *__restrict__ T, int pass) {
   __shared__ uint32_t h[256];
   const JobDev *jobs = table_jobs(T);
   const int shift = 8 * pass;
-  const Items items(T, K_ROT, claim, C_HIST + pass);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_ROT]; vb += gridDim.x) {
     const int j = find_job(T, K_ROT, vb);
     const JobDev &J = jobs[j];
     if (pass >= J.passes) continue;          // uniform: this job needs fewer passes
@@ -101,11 +99,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
 }
 
 // Exclusive scan of hist[d][0..n_sort_tiles) in place, one work item per (job, digit d).
-__global__ __launch_bounds__(256) void k_scan(const Table *__restrict__ T, unsigned long long *__restrict__ claim, int pass) {
+__global__ __launch_bounds__(256) void k_scan(const Table *__restrict__ T, int pass) {
   __shared__ uint32_t lds[256];
   const JobDev *jobs = table_jobs(T);
-  const Items items(T, K_SCAN, claim, C_SCAN + pass);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_SCAN]; vb += gridDim.x) {
     const int j = find_job(T, K_SCAN, vb);
     const JobDev &J = jobs[j];
     if (pass >= J.passes) continue;
@@ -131,7 +128,7 @@ __global__ __launch_bounds__(256) void k_scan(const Table *__restrict__ T, unsig
 }
 
 // Stable scatter of one tile: 4 waves x 16 rounds x 64 lanes.
-__global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restrict__ T, unsigned long long *__restrict__ claim,
+__global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restrict__ T,
                                                           int pass) {
   __shared__ uint32_t wcnt[4][256];
   __shared__ uint32_t gbase[256];
@@ -142,8 +139,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restric
   const int w = t >> 6;
   const int lane = t & 63;
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  const Items items(T, K_ROT, claim, C_SCAT + pass);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_ROT]; vb += gridDim.x) {
     const int j = find_job(T, K_ROT, vb);
     const JobDev &J = jobs[j];
     if (pass >= J.passes) continue;
@@ -214,10 +210,9 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restric
 }
 
 // seg_off[s] = number of sorted keys < s (lower bound), s = 0..n_s.
-__global__ __launch_bounds__(256) void k_segoff(const Table *__restrict__ T, unsigned long long *__restrict__ claim) {
+__global__ __launch_bounds__(256) void k_segoff(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
-  const Items items(T, K_SEG, claim, C_SEG);
-  for (int64_t vb = items.first(); vb < items.total; vb = items.next(vb)) {
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_SEG]; vb += gridDim.x) {
     const int j = find_job(T, K_SEG, vb);
     const JobDev &J = jobs[j];
     const int64_t s = (vb - J.vb_start[K_SEG]) * 256 + threadIdx.x;
@@ -243,19 +238,26 @@ static inline int grid_for(int64_t total, int cap) {
 }
 
 hipError_t launch_rotate_bin(const Table *dt, const TableHeader &h, int cap, hipStream_t s) {
-  unsigned long long *cl = table_claims(dt);
   const int max_passes = h.max_passes;
   int g = grid_for(h.total[K_ROT], cap);
-  if (g) hipLaunchKernelGGL(k_rotate, dim3(g), dim3(kSortThreads), 0, s, dt, cl);
+  if (g) hipLaunchKernelGGL(k_rotate, dim3(g), dim3(kSortThreads), 0, s, dt);
   for (int p = 0; p < max_passes; ++p) {
-    if (g) hipLaunchKernelGGL(k_hist, dim3(g), dim3(kSortThreads), 0, s, dt, cl, p);
+    if (g) hipLaunchKernelGGL(k_hist, dim3(g), dim3(kSortThreads), 0, s, dt, p);
     int gs = grid_for(h.total[K_SCAN], cap);
-    if (gs) hipLaunchKernelGGL(k_scan, dim3(gs), dim3(256), 0, s, dt, cl, p);
-    if (g) hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kSortThreads), 0, s, dt, cl, p);
+    if (gs) hipLaunchKernelGGL(k_scan, dim3(gs), dim3(256), 0, s, dt, p);
+    if (g) hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kSortThreads), 0, s, dt, p);
   }
   int gseg = grid_for(h.total[K_SEG], cap);
-  if (gseg) hipLaunchKernelGGL(k_segoff, dim3(gseg), dim3(256), 0, s, dt, cl);
+  if (gseg) hipLaunchKernelGGL(k_segoff, dim3(gseg), dim3(256), 0, s, dt);
   return hipGetLastError();
+}
+
+int rotate_bin_kernel_kind(const void *f) {
+  if (f == (const void *)k_rotate || f == (const void *)k_hist || f == (const void *)k_scatter)
+    return K_ROT;
+  if (f == (const void *)k_scan) return K_SCAN;
+  if (f == (const void *)k_segoff) return K_SEG;
+  return -1;
 }
 
 }  // namespace rubix

@@ -554,4 +554,135 @@ int rubix_forward_packed(const void *dev_table, int grid_blocks, int max_psf_rad
   return device_status(e, "rubix_forward_packed");
 }
 
+struct rubix_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipGraphNode_t> nodes;      // kernel nodes, in no particular order
+  std::vector<hipKernelNodeParams> params;
+  std::vector<int> kinds;                 // work-item kind that sets each node's grid
+  const void *dev_table = nullptr;
+  int max_jobs = 0, max_psf_r = 0, max_passes = 0;
+};
+
+static void graph_free(rubix_graph g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+int rubix_graph_create(const void *dev_table, int max_jobs, int max_psf_radius,
+                       int max_sort_passes, rubix_graph *out) {
+  g_err.clear();
+  if (!out) return fail(RUBIX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!dev_table) return fail(RUBIX_EINVAL, "dev_table is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_table) & 255)
+    return fail(RUBIX_EINVAL, "dev_table not 256-byte aligned");
+  if (max_jobs < 1 || max_jobs > RUBIX_MAX_JOBS)
+    return fail(RUBIX_EINVAL, "max_jobs=%d outside [1, %d]", max_jobs, RUBIX_MAX_JOBS);
+  if (max_psf_radius < 0 || max_psf_radius > RUBIX_MAX_RADIUS)
+    return fail(RUBIX_EINVAL, "max_psf_radius=%d outside [0, %d]", max_psf_radius, RUBIX_MAX_RADIUS);
+  if (max_sort_passes < 1 || max_sort_passes > 4)
+    return fail(RUBIX_EINVAL, "max_sort_passes=%d outside [1, 4]", max_sort_passes);
+  rubix_graph g = new rubix_graph_s;
+  g->dev_table = dev_table;
+  g->max_jobs = max_jobs;
+  g->max_psf_r = max_psf_radius;
+  g->max_passes = max_sort_passes;
+  // capture every forward kernel once with a one-block grid on a private stream
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) { graph_free(g); return device_status(e, "capture stream"); }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    TableHeader h;
+    memset(&h, 0, sizeof h);
+    for (int q = 0; q < NK; ++q) h.total[q] = 1;
+    h.max_passes = max_sort_passes;
+    h.max_psf_r = max_psf_radius;
+    const Table *dt = static_cast<const Table *>(dev_table);
+    hipError_t el = launch_rotate_bin(dt, h, 0, cs);
+    if (el == hipSuccess) el = launch_cube(dt, h, 0, cs);
+    if (el == hipSuccess) el = launch_psf_lsf(dt, h, 0, cs);
+    e = hipStreamEndCapture(cs, &g->graph);
+    if (el != hipSuccess) e = el;
+  }
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) { graph_free(g); return device_status(e, "forward graph capture"); }
+  size_t n = 0;
+  e = hipGraphGetNodes(g->graph, nullptr, &n);
+  std::vector<hipGraphNode_t> all(n);
+  if (e == hipSuccess && n) e = hipGraphGetNodes(g->graph, all.data(), &n);
+  if (e != hipSuccess) { graph_free(g); return device_status(e, "graph nodes"); }
+  for (hipGraphNode_t nd : all) {
+    hipGraphNodeType ty;
+    if ((e = hipGraphNodeGetType(nd, &ty)) != hipSuccess) break;
+    if (ty != hipGraphNodeTypeKernel) {
+      graph_free(g);
+      return fail(RUBIX_EDEVICE, "forward graph holds a node of type %d (kernels only)", (int)ty);
+    }
+    hipKernelNodeParams kp;
+    memset(&kp, 0, sizeof kp);
+    if ((e = hipGraphKernelNodeGetParams(nd, &kp)) != hipSuccess) break;
+    int kind = rotate_bin_kernel_kind(kp.func);
+    if (kind < 0) kind = cube_kernel_kind(kp.func);
+    if (kind < 0) kind = psf_lsf_kernel_kind(kp.func);
+    if (kind < 0) {
+      graph_free(g);
+      return fail(RUBIX_EDEVICE, "forward graph holds an unknown kernel");
+    }
+    g->nodes.push_back(nd);
+    g->params.push_back(kp);
+    g->kinds.push_back(kind);
+  }
+  if (e != hipSuccess) { graph_free(g); return device_status(e, "graph kernel nodes"); }
+  const size_t expect = 3u * max_sort_passes + 2 + 4 + 4;
+  if (g->nodes.size() != expect) {
+    const size_t got = g->nodes.size();
+    graph_free(g);
+    return fail(RUBIX_EDEVICE, "forward graph holds %zu kernels, expected %zu", got, expect);
+  }
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) { graph_free(g); return device_status(e, "graph instantiation"); }
+  *out = g;
+  return RUBIX_OK;
+}
+
+int rubix_graph_launch(rubix_graph g, const void *host_table, size_t host_table_bytes,
+                       void *stream) {
+  g_err.clear();
+  if (!g || !g->exec) return fail(RUBIX_EINVAL, "graph is NULL");
+  if (!host_table) return fail(RUBIX_EINVAL, "host_table is NULL");
+  if (host_table_bytes < sizeof(Table)) return fail(RUBIX_EINVAL, "host_table too small");
+  const Table *t = static_cast<const Table *>(host_table);
+  const int nj = t->h.n_jobs;
+  if (nj < 1 || nj > g->max_jobs)
+    return fail(RUBIX_EINVAL, "table holds %d jobs; the graph takes 1..%d", nj, g->max_jobs);
+  const size_t tb = table_bytes(nj);
+  if (host_table_bytes < tb)
+    return fail(RUBIX_EINVAL, "host_table of %zu bytes < %zu", host_table_bytes, tb);
+  if (t->h.max_passes > g->max_passes || t->h.max_psf_r > g->max_psf_r)
+    return fail(RUBIX_ERANGE, "table needs %d sort passes and PSF radius %d; the graph has %d, %d",
+                t->h.max_passes, t->h.max_psf_r, g->max_passes, g->max_psf_r);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(const_cast<void *>(g->dev_table), host_table, tb,
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return device_status(e, "table copy");
+  for (size_t i = 0; i < g->nodes.size(); ++i) {
+    hipKernelNodeParams kp = g->params[i];
+    const int64_t tot = t->h.total[g->kinds[i]];
+    kp.gridDim = dim3((unsigned)std::min<int64_t>(std::max<int64_t>(tot, 1), 0x7fffffff));
+    e = hipGraphExecKernelNodeSetParams(g->exec, g->nodes[i], &kp);
+    if (e != hipSuccess) return device_status(e, "graph grid update");
+  }
+  return device_status(hipGraphLaunch(g->exec, s), "graph launch");
+}
+
+int rubix_graph_destroy(rubix_graph g) {
+  g_err.clear();
+  graph_free(g);
+  return RUBIX_OK;
+}
+
 }  // extern "C"

@@ -129,20 +129,10 @@ struct JobDev {
   int64_t vb_start[NK];
 };
 
-// One work-item counter per kernel launch of the forward sequence (a kernel that runs once per
-// radix pass has one per pass).
-enum ClaimSlot {
-  C_ROT = 0, C_HIST = 1, C_SCAN = 5, C_SCAT = 9, C_SEG = 13, C_PREP = 14, C_CUBE = 15,
-  C_COMB = 16, C_LSF = 17, C_PSFY = 18, C_PSFX = 19, C_COPY = 20, kClaimSlots = 32
-};
-
 struct TableHeader {
   int32_t n_jobs, max_passes;   // max_passes: most radix-sort passes any job of the table needs
   int32_t max_psf_r, max_lsf_r; // largest PSF / LSF radius of the table (sizes LDS)
   int64_t total[NK];
-  // Work-item counters for grids smaller than their item count; zero in every table the host
-  // builds, so each upload (or copy) of a table resets them.
-  unsigned long long claim[kClaimSlots];
   SspDev ssp;
 };
 
@@ -158,39 +148,6 @@ __host__ __device__ inline const JobDev *table_jobs(const Table *t) {
 
 __host__ __device__ inline size_t table_bytes(int n_jobs) {
   return ((sizeof(Table) + 255) & ~size_t(255)) + size_t(n_jobs) * sizeof(JobDev);
-}
-
-// The work items of one launch. A grid with at least one block per item gives block b item b. A
-// smaller (persistent) grid hands items out in increasing order from the launch's counter, one at
-// a time per block, so blocks that draw heavy items take fewer of them. Every thread of the block
-// must call first()/next() (they contain block barriers); the item is block-uniform.
-// The counters sit in the table header but reach the kernels as a separate argument: the table
-// itself is never written during a launch, so the compiler may read it through the scalar cache.
-__device__ __forceinline__ int64_t claim_item(unsigned long long *ctr) {
-  __shared__ int64_t s_item;
-  __syncthreads();                            // the last item's readers are done with s_item
-  if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(ctr, 1ull);
-  __syncthreads();
-  const int64_t v = s_item;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-struct Items {
-  int64_t total;
-  bool dyn;
-  unsigned long long *ctr;
-  __device__ Items(const Table *t, int kind, unsigned long long *claim, int slot)
-      : total(t->h.total[kind]), dyn((int64_t)gridDim.x < t->h.total[kind]), ctr(claim + slot) {}
-  __device__ int64_t first() const { return dyn ? claim_item(ctr) : (int64_t)blockIdx.x; }
-  __device__ int64_t next(int64_t vb) const { return dyn ? claim_item(ctr) : vb + gridDim.x; }
-};
-
-// Device address of a table's claim counters.
-inline unsigned long long *table_claims(const Table *dt) {
-  return reinterpret_cast<unsigned long long *>(reinterpret_cast<uintptr_t>(dt) +
-                                                offsetof(TableHeader, claim));
 }
 
 // Largest job index j with jobs[j].vb_start[kind] <= vb (vb is wave-uniform).
@@ -210,5 +167,11 @@ hipError_t launch_rotate_bin(const Table *dt, const TableHeader &h, int grid_cap
 hipError_t launch_cube(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
 hipError_t launch_psf_lsf(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
 hipError_t launch_backward(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
+
+// Work-item kind (Kind) whose total sets the grid of a forward kernel, or -1 if `func` is not one
+// of that file's forward kernels (identifies the kernel nodes of a captured forward sequence).
+int rotate_bin_kernel_kind(const void *func);
+int cube_kernel_kind(const void *func);
+int psf_lsf_kernel_kind(const void *func);
 
 }  // namespace rubix

@@ -220,6 +220,26 @@ def rubix_forward_packed(dev_table: torch.Tensor, grid_blocks: int, max_psf_radi
                                    int(max_sort_passes), _stream(stream)))
 
 
+def rubix_graph_create(dev_table: torch.Tensor, max_jobs: int, max_psf_radius: int,
+                       max_sort_passes: int) -> int:
+    """Returns the graph handle (an address); release it with rubix_graph_destroy."""
+    lib = _lib.load()
+    out = c_void_p(None)
+    check(lib.rubix_graph_create(dev_table.data_ptr(), int(max_jobs), int(max_psf_radius),
+                                 int(max_sort_passes), byref(out)))
+    return int(out.value)
+
+
+def rubix_graph_launch(graph: int, host_table: torch.Tensor, stream=None) -> None:
+    lib = _lib.load()
+    check(lib.rubix_graph_launch(graph, host_table.data_ptr(), host_table.numel(),
+                                 _stream(stream)))
+
+
+def rubix_graph_destroy(graph: int) -> None:
+    check(_lib.load().rubix_graph_destroy(graph))
+
+
 # --------------------------------------------------------------------------------------------------
 # one galaxy through the pipeline
 # --------------------------------------------------------------------------------------------------

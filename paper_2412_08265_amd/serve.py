@@ -17,10 +17,10 @@ longer than `queue_timeout_s` fail with QueueTimeout. The queue is not persisted
 
 Executors:
   GraphExecutor  the batch's job table is packed on the host (rubix_forward_pack) into the lane's
-                 pinned buffer, copied to the lane's device table, and a HIP graph captured once
-                 per lane replays rubix_forward_packed: persistent kernels whose launch arguments
-                 never change, so one capture serves every batch. Particle uploads run on a copy
-                 stream, overlapping the kernels of the batch ahead.
+                 pinned buffer; the lane's forward graph (captured once by the library) copies it
+                 to the lane's device table and runs every kernel with the batch's grid, in one
+                 graph launch. Particle uploads run on a copy stream, overlapping the kernels of
+                 the batch ahead.
   PlainExecutor  one request at a time with the plain entry points rubix_rotate_bin, rubix_cube
                  and rubix_psf_lsf (no batching, no graph): the baseline.
 Both give bitwise the same cube for a request (the packed path runs the same kernels over the same
@@ -283,29 +283,58 @@ class _DeviceExecutorBase:
 
 
 class GraphExecutor(_DeviceExecutorBase):
-    """Batched forward passes replayed from HIP graphs (one captured graph per lane)."""
+    """Batched forward passes launched as HIP graphs, one graph per lane.
+
+    mode "native" (default): the library's forward graph (rubix_graph_create): each launch copies
+      the batch's packed table to the lane's device table and sets every kernel's grid to the
+      batch's work-item count, so the kernels run exactly as in the plain entry points.
+    mode "persistent": rubix_forward_packed captured once per lane in a torch CUDA graph and
+      replayed unchanged; every kernel runs grid_blocks blocks that stride over the work items.
+    """
 
     def __init__(self, ssp: ops.DeviceSSP, max_jobs: int = 16, lanes: int = 2,
-                 grid_blocks: int = 2048, max_psf_radius: int = 16, max_sort_passes: int = 2,
-                 device="cuda"):
+                 mode: str = "native", grid_blocks: int = 2048, max_psf_radius: int = 16,
+                 max_sort_passes: int = 2, device="cuda"):
         super().__init__(ssp, device)
         if not 1 <= max_jobs <= 64:
             raise ValueError("max_jobs must be in [1, 64]")
+        if mode not in ("native", "persistent"):
+            raise ValueError(f"unknown graph mode {mode!r}")
+        self.mode = mode
         self.max_jobs, self.lanes = max_jobs, lanes
         self.grid_blocks = grid_blocks
         self.max_psf_radius, self.max_sort_passes = max_psf_radius, max_sort_passes
         nb = ops.rubix_table_bytes(max_jobs)
         self._free: Deque[dict] = collections.deque()
+        self._graphs: List[int] = []
         self._warm()
         for _ in range(lanes):
             lane = {"dev": torch.empty(nb, dtype=torch.uint8, device=self.device),
-                    "host": torch.empty(nb, dtype=torch.uint8, pin_memory=True),
-                    "graph": torch.cuda.CUDAGraph()}
-            torch.cuda.synchronize(self.device)
-            with torch.cuda.graph(lane["graph"], stream=self.compute):
-                ops.rubix_forward_packed(lane["dev"], grid_blocks, max_psf_radius,
-                                         max_sort_passes)
+                    "host": torch.empty(nb, dtype=torch.uint8, pin_memory=True)}
+            if mode == "native":
+                lane["graph"] = ops.rubix_graph_create(lane["dev"], max_jobs, max_psf_radius,
+                                                       max_sort_passes)
+                self._graphs.append(lane["graph"])
+            else:
+                lane["graph"] = torch.cuda.CUDAGraph()
+                torch.cuda.synchronize(self.device)
+                with torch.cuda.graph(lane["graph"], stream=self.compute):
+                    ops.rubix_forward_packed(lane["dev"], grid_blocks, max_psf_radius,
+                                             max_sort_passes)
             self._free.append(lane)
+
+    def close(self) -> None:
+        """Release the native graphs (their launches must have completed)."""
+        torch.cuda.synchronize(self.device)
+        while self._graphs:
+            ops.rubix_graph_destroy(self._graphs.pop())
+
+    def __del__(self):
+        try:
+            if self._graphs:
+                self.close()
+        except Exception:                         # noqa: BLE001 (interpreter shutdown)
+            pass
 
     def _warm(self) -> None:
         """Run the packed launch sequence once eagerly on a tiny job, so that every kernel's code
@@ -353,8 +382,11 @@ class GraphExecutor(_DeviceExecutorBase):
             self.compute.wait_event(up)
             for d in hosts:
                 d.record_stream(self.compute)
-            lane["dev"][:nt].copy_(lane["host"][:nt], non_blocking=True)
-            lane["graph"].replay()
+            if self.mode == "native":
+                ops.rubix_graph_launch(lane["graph"], lane["host"][:nt])
+            else:
+                lane["dev"][:nt].copy_(lane["host"][:nt], non_blocking=True)
+                lane["graph"].replay()
             done = torch.cuda.Event()
             done.record(self.compute)
         return {"lane": lane, "done": done, "bufs": bufs, "hosts": hosts, "ws": ws,

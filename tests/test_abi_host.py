@@ -29,7 +29,8 @@ def test_exports_every_declared_symbol(lib):
     names = _declared()
     assert {"rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf", "rubix_cube_backward",
             "rubix_workspace_size", "rubix_last_error", "rubix_table_bytes",
-            "rubix_forward_pack", "rubix_forward_packed"} <= set(names)
+            "rubix_forward_pack", "rubix_forward_packed", "rubix_graph_create",
+            "rubix_graph_launch", "rubix_graph_destroy"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
     assert lib.rubix_version().decode().startswith("rubix-mi355x")
@@ -153,6 +154,22 @@ def test_packed_table_sizes_and_validation(lib):
     for args in ((None, 64, 8, 2), (0x1000, 0, 8, 2), (0x1000, 64, 65, 2), (0x1000, 64, 8, 0),
                  (0x1000, 64, 8, 5)):
         assert lib.rubix_forward_packed(*args, None) == _lib.RUBIX_EINVAL, args
+
+
+def test_graph_entry_points_validate_before_device_work(lib):
+    from paper_2412_08265_amd import _lib
+    out = ctypes.c_void_p(1)
+    create = lambda *a: lib.rubix_graph_create(*a, ctypes.byref(out))
+    assert create(None, 4, 8, 2) == _lib.RUBIX_EINVAL and out.value is None
+    assert create(0x1001, 4, 8, 2) == _lib.RUBIX_EINVAL          # misaligned table
+    assert create(0x1000, 0, 8, 2) == _lib.RUBIX_EINVAL
+    assert create(0x1000, 65, 8, 2) == _lib.RUBIX_EINVAL
+    assert create(0x1000, 4, 65, 2) == _lib.RUBIX_EINVAL
+    assert create(0x1000, 4, 8, 5) == _lib.RUBIX_EINVAL
+    assert lib.rubix_graph_create(0x1000, 4, 8, 2, None) == _lib.RUBIX_EINVAL
+    host = (ctypes.c_uint8 * 64)()
+    assert lib.rubix_graph_launch(None, host, 64, None) == _lib.RUBIX_EINVAL
+    assert lib.rubix_graph_destroy(None) == _lib.RUBIX_OK
 
 
 def test_product_path_never_touches_the_oracle():

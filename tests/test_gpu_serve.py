@@ -51,14 +51,15 @@ def _graph_batch(ex, reqs):
     return [res.cube.cpu() for res in ex.collect(h)]
 
 
-def test_alone_equals_in_mix_equals_plain(ssp_grid, dssp):
+@pytest.mark.parametrize("mode", ["native", "persistent"])
+def test_alone_equals_in_mix_equals_plain(ssp_grid, dssp, mode):
     ws = _workloads(ssp_grid, range(6))
     for w in ws:
         log(f"request {w.name}: n={w.particles.n} grid {w.nx}x{w.ny} n_tel={w.n_tel} "
             f"incl={w.angles_deg[0]:.1f}")
     reqs = _requests(ws)
     plain = _plain_cubes(dssp, reqs)
-    ex = GraphExecutor(dssp, max_jobs=8, lanes=1, grid_blocks=1024)
+    ex = GraphExecutor(dssp, max_jobs=8, lanes=1, mode=mode, grid_blocks=1024)
     alone = [_graph_batch(ex, [r])[0] for r in reqs]
     mix = _graph_batch(ex, reqs[::-1])[::-1]
     pair = _graph_batch(ex, [reqs[2], reqs[0]])
@@ -69,10 +70,11 @@ def test_alone_equals_in_mix_equals_plain(ssp_grid, dssp):
     assert torch.equal(pair[0], plain[2]) and torch.equal(pair[1], plain[0])
 
 
-def test_graph_replays_with_device_work_between(ssp_grid, dssp):
+@pytest.mark.parametrize("mode", ["native", "persistent"])
+def test_graph_replays_with_device_work_between(ssp_grid, dssp, mode):
     reqs = _requests(_workloads(ssp_grid, range(10, 14)))
     ref = _plain_cubes(dssp, reqs)
-    ex = GraphExecutor(dssp, max_jobs=4, lanes=2, grid_blocks=512)
+    ex = GraphExecutor(dssp, max_jobs=4, lanes=2, mode=mode, grid_blocks=512)
     junk = torch.randn(1 << 24, device="cuda")
     for rep in range(4):
         got = _graph_batch(ex, reqs if rep % 2 == 0 else reqs[1:])
@@ -84,7 +86,7 @@ def test_graph_replays_with_device_work_between(ssp_grid, dssp):
         assert np.isfinite(s)
         _plain_cubes(dssp, reqs[:1])
         torch.cuda.synchronize()
-        log(f"replay {rep} matches the eager result")
+        log(f"{mode} replay {rep} matches the eager result")
 
 
 def test_served_request_matches_oracle(ssp_grid, dssp):
