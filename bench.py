@@ -214,6 +214,8 @@ def main():
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
     err(f"timing {K} steps")
     torch.cuda.synchronize()
+    ops.rubix_cube_timer_read()                 # drop any earlier pairs
+    ops.rubix_cube_timer(True)                  # event pair around k_cube in every timed step
     t0 = time.perf_counter()
     for k in range(K):
         e = evs[k]
@@ -226,11 +228,15 @@ def main():
         e[3].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ops.rubix_cube_timer(False)
+    cube_kernel_ms, n_timed = ops.rubix_cube_timer_read()
+    assert n_timed == K, (n_timed, K)
+    cube_kernel_ms /= K
     ms_step = (t1 - t0) * 1e3 / K
     st = [sum(evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(K)) / K for i in range(3)]
     value = n_in * w.n_tel / (ms_step * 1e-3)
     units = n_in * w.n_tel
-    achieved = CUBE_FLOP_PER_UNIT * units / (st[1] * 1e-3) / 1e12
+    achieved = CUBE_FLOP_PER_UNIT * units / (cube_kernel_ms * 1e-3) / 1e12
     digest = source_digest("k_cube.hip")
     traffic = traffic_from_profile(digest)
     rot_gbs = ROTBIN_BYTES_PER_PARTICLE * w.particles.n / (st[0] * 1e-3) / 1e9
@@ -255,12 +261,14 @@ def main():
                                 f"spx, LSF {w.lsf_sigma_A} A"),
                    "particles": w.particles.n, "in_field": n_in, "spaxels": w.n_spaxels,
                    "bins": w.n_tel, "parallelism": "none (1 GPU)"},
-        "roofline": {"bound": "alu", "kernel": "k_cube (rubix_cube stage)",
+        "roofline": {"bound": "alu", "kernel": "k_cube",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
                      "flop_per_unit": CUBE_FLOP_PER_UNIT, "units_per_launch": units,
-                     "avg_ms": st[1], "source_digest": digest},
-        "stages_ms": {"rotate_bin": st[0], "cube": st[1], "psf_lsf": st[2]},
+                     "avg_ms": cube_kernel_ms, "source_digest": digest,
+                     "timing": "HIP event pair around k_cube on its stream, every timed step"},
+        "stages_ms": {"rotate_bin": st[0], "cube": st[1], "psf_lsf": st[2],
+                      "k_cube": cube_kernel_ms},
         "stages_hbm": {"rotate_bin_GBs": rot_gbs, "rotate_bin_frac": rot_gbs / PEAK_HBM_GBS,
                        "psf_lsf_GBs": psf_gbs, "psf_lsf_frac": psf_gbs / PEAK_HBM_GBS},
     }

@@ -221,6 +221,16 @@ int rubix_graph_launch(rubix_graph g, const void *host_table, size_t host_table_
 /* Releases the graph (NULL is ignored). Its launches must have completed. */
 int rubix_graph_destroy(rubix_graph g);
 
+/* ---- Measurement aid -------------------------------------------------------------------------
+ * rubix_cube_timer(1) makes the following rubix_cube calls on this thread record a HIP event pair
+ * on their stream right before and right after the cube-summation kernel (the step that sums
+ * the resampled spectra; rubix_cube also runs short preparation and combine kernels around it).
+ * rubix_cube_timer(0) stops recording. rubix_cube_timer_read waits for every pair recorded since
+ * the last read, returns their summed elapsed time in ms and their count, and releases them.
+ * The pairs are library state (HIP events), held until read. Graph launches are never timed. */
+int rubix_cube_timer(int enable);
+int rubix_cube_timer_read(double *total_ms, int *count);
+
 /* Message for the last non-zero status returned on this thread ("" if none). */
 const char *rubix_last_error(void);
 

@@ -52,7 +52,8 @@ class RubixJob(ctypes.Structure):
 EXPORTS = ("rubix_workspace_size", "rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf",
            "rubix_cube_backward", "rubix_last_error", "rubix_version", "rubix_table_bytes",
            "rubix_forward_pack", "rubix_forward_packed", "rubix_graph_create",
-           "rubix_graph_launch", "rubix_graph_destroy")
+           "rubix_graph_launch", "rubix_graph_destroy", "rubix_cube_timer",
+           "rubix_cube_timer_read")
 
 _lib = None
 
@@ -91,9 +92,12 @@ def load() -> ctypes.CDLL:
     lib.rubix_graph_create.argtypes = [c_void_p, c_int, c_int, c_int, POINTER(c_void_p)]
     lib.rubix_graph_launch.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
     lib.rubix_graph_destroy.argtypes = [c_void_p]
+    lib.rubix_cube_timer.argtypes = [c_int]
+    lib.rubix_cube_timer_read.argtypes = [POINTER(c_double), POINTER(c_int)]
     for f in ("rubix_workspace_size", "rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf",
               "rubix_cube_backward", "rubix_forward_pack", "rubix_forward_packed",
-              "rubix_graph_create", "rubix_graph_launch", "rubix_graph_destroy"):
+              "rubix_graph_create", "rubix_graph_launch", "rubix_graph_destroy",
+              "rubix_cube_timer", "rubix_cube_timer_read"):
         getattr(lib, f).restype = c_int
     lib.rubix_last_error.restype = ctypes.c_char_p
     lib.rubix_version.restype = ctypes.c_char_p

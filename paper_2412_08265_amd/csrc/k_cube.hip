@@ -49,6 +49,19 @@ __device__ __forceinline__ int cell_of(const double *thr, int n, double x) {
 
 __device__ __forceinline__ double clamp01(double t) { return fmin(1.0, fmax(0.0, t)); }
 
+// Doppler slope g of the node index (FP32, from FP64) and whether the node span of one wave's
+// kCubeWaveBins bins fits its 64-node window: q advances by bin_slope/(1+beta) nodes per bin, so
+// when 61 steps stay below 61.9 nodes the node indices of 62 consecutive bins span at most 63
+// nodes (0.1 node of margin is far above the FP32 error of q). k_prep and k_vbound both use it.
+__device__ __forceinline__ void doppler_slope(const JobDev &J, const SspDev &S, double v, float &g,
+                                              bool &fits) {
+  const double beta = v / kCkms;
+  const double opz = 1.0 + J.z_sys;
+  g = (float)(beta / (1.0 + beta) / (opz * S.lam_step));
+  const double beff = J.bin_slope / (1.0 + beta);
+  fits = isfinite((double)g) && beff > 0.0 && 61.0 * beff <= 61.9;
+}
+
 // mode 0: forward weights flux_scale*m*J*w_c; mode 1: plain bilinear weights w_c.
 __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__ T, int mode) {
   const SspDev &S = T->h.ssp;
@@ -77,20 +90,53 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__
     const double scale = mode == 0 ? J.flux_scale * m * jac : 1.0;
     PrepRec r;
     r.row = (ja * S.n_met + jz) * S.n_lam;
-    r.g = (float)(beta / (1.0 + beta) / (opz * S.lam_step));
+    bool fits;
+    doppler_slope(J, S, v, r.g, fits);
     r.a[0] = (float)(scale * (1.0 - ta) * (1.0 - tz));
     r.a[1] = (float)(scale * (1.0 - ta) * tz);
     r.a[2] = (float)(scale * ta * (1.0 - tz));
     r.a[3] = (float)(scale * ta * tz);
     r.spaxel = J.key[j];
-    // q advances by bin_slope/(1+beta) nodes per telescope bin; when 61 steps stay below 61.9
-    // nodes, the node indices of 62 consecutive bins span at most 63 nodes (0.1 node of margin
-    // is far above the FP32 error of q)
-    const double beff = J.bin_slope / (1.0 + beta);
-    const bool fits = isfinite((double)r.g) && beff > 0.0 && 61.0 * beff <= 61.9;
     if (!fits) r.row = ~r.row;
     r.pad = 0;
     J.prep[i] = r;
+  }
+}
+
+// Per job, over all its particles in input order: the largest |g| of a particle whose span fits,
+// and whether any particle's span does not fit (doppler_slope, exactly as k_prep decides). The
+// cube kernel uses them to find lambda tiles where every particle's window lies inside the SSP
+// grid. One atomic per work item; k_chunks zeroes counts[2..3] before this kernel runs.
+__global__ __launch_bounds__(256) void k_vbound(const Table *__restrict__ T) {
+  __shared__ int s_g[4], s_f[4];
+  const SspDev &S = T->h.ssp;
+  const JobDev *jobs = table_jobs(T);
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_VB]; vb += gridDim.x) {
+    const int jj = find_job(T, K_VB, vb);
+    const JobDev &J = jobs[jj];
+    const int64_t base = (vb - J.vb_start[K_VB]) * kVbParticles;
+    int gmax = 0, nofit = 0;
+    for (int q = threadIdx.x; q < kVbParticles; q += 256) {
+      const int64_t i = base + q;
+      if (i < J.n) {
+        float g;
+        bool fits;
+        doppler_slope(J, S, (double)J.vlos[i], g, fits);
+        if (fits) gmax = max(gmax, __float_as_int(fabsf(g)));   // non-negative: int order
+        else nofit = 1;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      gmax = max(gmax, __shfl_xor(gmax, off));
+      nofit |= __shfl_xor(nofit, off);
+    }
+    if ((threadIdx.x & 63) == 0) { s_g[threadIdx.x >> 6] = gmax; s_f[threadIdx.x >> 6] = nofit; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      atomicMax(&J.counts[2], max(max(s_g[0], s_g[1]), max(s_g[2], s_g[3])));
+      if (s_f[0] | s_f[1] | s_f[2] | s_f[3]) atomicOr(&J.counts[3], 1);
+    }
+    __syncthreads();
   }
 }
 
@@ -123,6 +169,7 @@ __global__ __launch_bounds__(1024) void k_chunks(const Table *__restrict__ T) {
     }
     uint32_t co = sc[t] - nc, so = ss[t] - nslot, bo = sb[t] - ncomb;
     if (t == 1023) { J.counts[0] = (int32_t)sc[t]; J.counts[1] = (int32_t)sb[t]; }
+    if (t == 0) { J.counts[2] = 0; J.counts[3] = 0; }          // k_vbound's reductions
     __syncthreads();
     for (int s = s0; s < s1; ++s) {
       const int p0 = J.seg_off[s], p1 = J.seg_off[s + 1];
@@ -147,8 +194,9 @@ typedef __attribute__((address_space(1))) const float GFloat;     // global memo
 // offset per lane; offsets past the end of the grid read 0 instead of faulting. The per-particle
 // part of the offset is added to the lane part in a VGPR rather than passed as the scalar
 // offset: a window that starts before node 0 of the first row has a negative per-particle part,
-// which must wrap modulo 2^32 together with the lane part (only the lane offset does), and on
-// the 1e7-particle workload the scalar-offset form measured 40.8 ms against 30.5 ms.
+// which must wrap modulo 2^32 together with the lane part (only the lane offset does). Even where
+// the offset is known to be non-negative the scalar-offset form is slower on gfx950: on the
+// 1e7-particle workload 39.5 ms against 29.0 ms for the interior path below.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t flux_rsrc(const SspDev &S) {
   const uint32_t bytes = (uint32_t)S.n_age * (uint32_t)S.n_met * (uint32_t)S.n_lam * 4u;
   return __builtin_amdgcn_make_buffer_rsrc((void *)S.flux, (short)0, (int)bytes, 0x00020000);
@@ -283,6 +331,60 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
     float acc = 0.f, tot = 0.f;
     int since = 0;
     int p = ch.p0;
+    // Interior wave: every particle of the job fits a window and, with |g| at most the job's
+    // largest, lane 0's window [n0, n0 + 63] lies inside the SSP grid for any g in [-gmax, gmax]
+    // (n0 is monotone in g), so the groups below need no per-particle checks.
+    bool interior = false;
+    if (!direct_job && ((CInt *)J.counts)[3] == 0) {
+      const float gm = __int_as_float(((CInt *)J.counts)[2]);
+      const float lam0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(lamf)));
+      const float qf0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(qf)));
+      const int lo = __builtin_amdgcn_readfirstlane(qi0 + floor_i32(fmaf(-lam0, gm, qf0)));
+      const int hi = __builtin_amdgcn_readfirstlane(qi0 + floor_i32(fmaf(lam0, gm, qf0)));
+      interior = lo >= 0 && hi + 63 <= nl - 1;
+    }
+    if (interior) {
+      for (; p + kCubeGroup <= ch.p1; p += kCubeGroup) {
+        PrepRec r[kCubeGroup];
+#pragma unroll
+        for (int u = 0; u < kCubeGroup; ++u) r[u] = load_rec(prep + p + u);
+        float tau[kCubeGroup];
+        uint32_t dl[kCubeGroup], so[kCubeGroup];
+#pragma unroll
+        for (int u = 0; u < kCubeGroup; ++u) {
+          const float t = fmaf(-lamf, r[u].g, qf);
+          tau[u] = __builtin_amdgcn_fractf(t);
+          const int fi = floor_i32(t);
+          const int fi0 = __builtin_amdgcn_readfirstlane(fi);
+          dl[u] = (uint32_t)(fi - fi0) * 4u;
+          so[u] = (uint32_t)(r[u].row + qi0 + fi0) * 4u;      // window base, >= 0 here
+        }
+        float v[kCubeGroup][4];
+#pragma unroll
+        for (int u = 0; u < kCubeGroup; ++u) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[u][c] = ldf(rs, lb[c], so[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kCubeGroup; ++u) {
+          float Sv = r[u].a[0] * v[u][0];
+          Sv = fmaf(r[u].a[1], v[u][1], Sv);
+          Sv = fmaf(r[u].a[2], v[u][2], Sv);
+          Sv = fmaf(r[u].a[3], v[u][3], Sv);
+          wslot[u * 64 + lane] = Sv;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int u = 0; u < kCubeGroup; ++u) {
+          const float *sp = (const float *)((const char *)wslot + abase + dl[u]) + u * 64;
+          const float s0 = sp[0], s1 = sp[1];
+          acc += fmaf(tau[u], s1 - s0, s0);
+        }
+        __builtin_amdgcn_wave_barrier();
+        since += kCubeGroup;
+        if (since >= kCubeSubsum) { tot += acc; acc = 0.f; since = 0; }
+      }
+    }
     // full groups: straight-line code, all row loads of the group in flight together
     for (; p + kCubeGroup <= ch.p1; p += kCubeGroup) {
       PrepRec r[kCubeGroup];
@@ -385,6 +487,8 @@ __global__ __launch_bounds__(kCubeThreads) void k_combine(const Table *__restric
   }
 }
 
+thread_local hipEvent_t t_cube_events[2] = {nullptr, nullptr};
+
 static inline int grid_for(int64_t total, int cap) {
   if (total <= 0) return 0;
   int64_t g = total;
@@ -395,12 +499,18 @@ static inline int grid_for(int64_t total, int cap) {
 
 hipError_t launch_cube(const Table *dt, const TableHeader &h, int cap, hipStream_t s) {
   int g;
-  if ((g = grid_for(h.total[K_PREP], cap)))
-    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, 0);
   if ((g = grid_for(h.total[K_CHUNK], cap)))
     hipLaunchKernelGGL(k_chunks, dim3(g), dim3(1024), 0, s, dt);
-  if ((g = grid_for(h.total[K_CUBE], cap)))
+  if ((g = grid_for(h.total[K_VB], cap)))
+    hipLaunchKernelGGL(k_vbound, dim3(g), dim3(256), 0, s, dt);
+  if ((g = grid_for(h.total[K_PREP], cap)))
+    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, 0);
+  if ((g = grid_for(h.total[K_CUBE], cap))) {
+    const bool timed = t_cube_events[0] && t_cube_events[1];
+    if (timed) (void)hipEventRecord(t_cube_events[0], s);
     hipLaunchKernelGGL(k_cube, dim3(g), dim3(kCubeThreads), 0, s, dt);
+    if (timed) (void)hipEventRecord(t_cube_events[1], s);
+  }
   if ((g = grid_for(h.total[K_COMB], cap)))
     hipLaunchKernelGGL(k_combine, dim3(g), dim3(kCubeThreads), 0, s, dt);
   return hipGetLastError();
@@ -417,6 +527,7 @@ hipError_t launch_prep_backward(const Table *dt, const TableHeader &h, int cap, 
 int cube_kernel_kind(const void *f) {
   if (f == (const void *)k_prep) return K_PREP;
   if (f == (const void *)k_chunks) return K_CHUNK;
+  if (f == (const void *)k_vbound) return K_VB;
   if (f == (const void *)k_cube) return K_CUBE;
   if (f == (const void *)k_combine) return K_COMB;
   return -1;

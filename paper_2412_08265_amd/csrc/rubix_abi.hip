@@ -21,6 +21,9 @@ hipError_t launch_prep_backward(const Table *dt, const TableHeader &h, int cap, 
 // error reporting
 // ---------------------------------------------------------------------------------------------
 static thread_local std::string g_err;
+// cube-kernel timer (measurement aid): on/off and the event pairs recorded since the last read
+static thread_local bool g_timer_on = false;
+static thread_local std::vector<std::pair<hipEvent_t, hipEvent_t>> g_timer_ev;
 
 static int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 static int fail(int code, const char *fmt, ...) {
@@ -386,6 +389,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
         /*K_BWD*/ cdiv(z.n, kBwdParticles),
         /*K_FIN*/ z.n_fin_blocks,
         /*K_ANG*/ 1,
+        /*K_VB*/ cdiv(z.n, kVbParticles),
     };
     for (int q = 0; q < NK; ++q) {
       d.vb_start[q] = start[q];
@@ -454,7 +458,47 @@ int rubix_cube(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, void *ws
   if ((rc = validate_ssp(ssp))) return rc;
   if ((rc = check_ws(jobs, n_jobs, ws, ws_bytes))) return rc;
   auto tab = build_table(jobs, n_jobs, ssp, ws, nullptr, nullptr);
-  return run(tab, ws, static_cast<hipStream_t>(stream), launch_cube, "rubix_cube");
+  if (!g_timer_on) return run(tab, ws, static_cast<hipStream_t>(stream), launch_cube, "rubix_cube");
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  if (e != hipSuccess) {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    return device_status(e, "cube timer events");
+  }
+  t_cube_events[0] = ev[0];
+  t_cube_events[1] = ev[1];
+  rc = run(tab, ws, static_cast<hipStream_t>(stream), launch_cube, "rubix_cube");
+  t_cube_events[0] = t_cube_events[1] = nullptr;
+  g_timer_ev.push_back({ev[0], ev[1]});
+  return rc;
+}
+
+int rubix_cube_timer(int enable) {
+  g_err.clear();
+  g_timer_on = enable != 0;
+  return RUBIX_OK;
+}
+
+int rubix_cube_timer_read(double *total_ms, int *count) {
+  g_err.clear();
+  if (!total_ms || !count) return fail(RUBIX_EINVAL, "total_ms/count is NULL");
+  double sum = 0.0;
+  hipError_t e = hipSuccess;
+  for (auto &p : g_timer_ev) {
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventSynchronize(p.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.first, p.second);
+    sum += ms;
+  }
+  *count = (int)g_timer_ev.size();
+  *total_ms = sum;
+  for (auto &p : g_timer_ev) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  g_timer_ev.clear();
+  return device_status(e, "cube timer read");
 }
 
 int rubix_psf_lsf(const rubix_job *jobs, int n_jobs, const float *const *in, float *const *out,
@@ -637,7 +681,7 @@ int rubix_graph_create(const void *dev_table, int max_jobs, int max_psf_radius,
     g->kinds.push_back(kind);
   }
   if (e != hipSuccess) { graph_free(g); return device_status(e, "graph kernel nodes"); }
-  const size_t expect = 3u * max_sort_passes + 2 + 4 + 4;
+  const size_t expect = 3u * max_sort_passes + 2 + 5 + 4;
   if (g->nodes.size() != expect) {
     const size_t got = g->nodes.size();
     graph_free(g);

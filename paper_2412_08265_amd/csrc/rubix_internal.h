@@ -30,6 +30,7 @@ constexpr int kPsfLanes = 64;       // bins per PSF work item
 constexpr int kPsfSeg = 64;         // spaxels of a line per PSF work item (16 per wave)
 constexpr int kBwdParticles = 16;   // particles per backward work item (4 per wave)
 constexpr int kFinThreads = 256;
+constexpr int kVbParticles = 16384; // particles per Doppler-bound work item
 
 enum Kind : int {
   K_ROT = 0,   // rotate/key and radix-sort tiles (per kSortTile particles)
@@ -47,6 +48,7 @@ enum Kind : int {
   K_BWD,       // per kBwdParticles sorted particles
   K_FIN,       // per kFinThreads sorted particles
   K_ANG,       // one per job
+  K_VB,        // per kVbParticles particles (Doppler bounds for the cube kernel)
   NK
 };
 
@@ -120,7 +122,8 @@ struct JobDev {
   PrepRec *prep;        // [n]
   ChunkRec *chunks;     // [n_chunk_ub]
   CombRec *combs;       // [n_comb_ub]
-  int32_t *counts;      // [0] chunks, [1] combine entries
+  int32_t *counts;      // [0] chunks, [1] combine entries, [2] bits of the largest |Doppler
+                        // slope| of the job, [3] nonzero if some particle's span does not fit
   float *partial;       // [n_comb_slots_ub][n_tel]
   float *tmp_cube;      // [cube_elems]
   float4 *bintab;       // [n_tel]: (node index integer part as int bits, frac, lambda, 0)
@@ -165,6 +168,9 @@ __device__ inline int find_job(const Table *t, int kind, int64_t vb) {
 hipError_t launch_upload(const void *host_table, size_t bytes, void *dev_table, hipStream_t s);
 hipError_t launch_rotate_bin(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
 hipError_t launch_cube(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
+// When both are non-null, launch_cube records them on its stream right before and right after
+// the cube-summation kernel (a measurement aid; set per call by the ABI, null otherwise).
+extern thread_local hipEvent_t t_cube_events[2];
 hipError_t launch_psf_lsf(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
 hipError_t launch_backward(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
 

@@ -240,6 +240,18 @@ def rubix_graph_destroy(graph: int) -> None:
     check(_lib.load().rubix_graph_destroy(graph))
 
 
+def rubix_cube_timer(enable: bool) -> None:
+    check(_lib.load().rubix_cube_timer(1 if enable else 0))
+
+
+def rubix_cube_timer_read():
+    """(summed ms, count) of the cube-summation kernel over the timed rubix_cube calls."""
+    lib = _lib.load()
+    ms, n = ctypes.c_double(0.0), ctypes.c_int(0)
+    check(lib.rubix_cube_timer_read(byref(ms), byref(n)))
+    return float(ms.value), int(n.value)
+
+
 # --------------------------------------------------------------------------------------------------
 # one galaxy through the pipeline
 # --------------------------------------------------------------------------------------------------
