@@ -75,7 +75,8 @@ def cpu_baseline(w, n_in_full: int, sample_particles: int):
     band_cfg = O.OracleConfig(cfg.angles_rad, cfg.nx, rows + 2 * r, cfg.spaxel_kpc,
                               cfg.tel_start, cfg.tel_step, cfg.n_tel, cfg.log_age_nodes,
                               cfg.met_nodes, cfg.ssp_lam_start, cfg.ssp_lam_step, cfg.ssp_flux,
-                              cfg.psf_sigma_spx, cfg.lsf_sigma_A)
+                              cfg.psf_sigma_spx, cfg.lsf_sigma_A, cfg.z_sys, cfg.flux_scale,
+                              cfg.log_lambda)
     band = c[: (rows + 2 * r) * cfg.nx]
     t1 = time.perf_counter()
     O.psf_lsf(band, band_cfg)

@@ -37,7 +37,8 @@ C_KMS = 299792.458  # km/s
 __all__ = [
     "C_KMS", "rotation_matrix", "rotation_matrix_derivs", "rotate_positions", "los_velocity",
     "spaxel_keys", "sort_by_key", "ssp_cell", "ssp_weights", "interp_templates",
-    "doppler_index", "node_decision", "resample_linear", "particle_spectra", "cube_raw", "gaussian_weights",
+    "rest_index", "doppler_index", "doppler_index_dbeta", "node_decision", "resample_linear",
+    "particle_spectra", "cube_raw", "gaussian_weights",
     "convolve_axis", "psf_lsf", "forward", "loss", "loss_grad_cube", "adjoint",
     "OracleConfig", "config_from_workload",
 ]
@@ -51,7 +52,8 @@ class OracleConfig:
 
     def __init__(self, angles_rad, nx, ny, spaxel_kpc, tel_start, tel_step, n_tel,
                  log_age_nodes, met_nodes, ssp_lam_start, ssp_lam_step, ssp_flux,
-                 psf_sigma_spx=0.0, lsf_sigma_A=0.0, z_sys=0.0, flux_scale=1.0):
+                 psf_sigma_spx=0.0, lsf_sigma_A=0.0, z_sys=0.0, flux_scale=1.0,
+                 log_lambda=False):
         self.angles_rad = tuple(float(a) for a in angles_rad)
         self.nx, self.ny = int(nx), int(ny)
         self.spaxel_kpc = float(spaxel_kpc)
@@ -64,15 +66,32 @@ class OracleConfig:
         self.lsf_sigma_A = float(lsf_sigma_A)
         self.z_sys = float(z_sys)
         self.flux_scale = float(flux_scale)
+        # both wavelength grids uniform in ln(lambda): value k is start * exp(k * step)
+        self.log_lambda = bool(log_lambda)
 
     @property
     def n_spaxels(self):
         return self.nx * self.ny
 
     def tel_lambda(self):
-        return self.tel_start + self.tel_step * np.arange(self.n_tel, dtype=np.float64)
+        k = np.arange(self.n_tel, dtype=np.float64)
+        if self.log_lambda:
+            return self.tel_start * np.exp(self.tel_step * k)
+        return self.tel_start + self.tel_step * k
+
+    def ssp_lambda(self):
+        k = np.arange(self.ssp_flux.shape[2], dtype=np.float64)
+        if self.log_lambda:
+            return self.ssp_lam_start * np.exp(self.ssp_lam_step * k)
+        return self.ssp_lam_start + self.ssp_lam_step * k
 
     def lsf_sigma_bins(self):
+        """LSF width in telescope bins. On a log grid a bin is lambda * step wide; the width is
+        taken at the grid's central wavelength and held constant in bins (a constant velocity
+        width), so the LSF stays one fixed kernel."""
+        if self.log_lambda:
+            lam_c = self.tel_start * math.exp(self.tel_step * (self.n_tel - 1) / 2.0)
+            return self.lsf_sigma_A / (lam_c * self.tel_step)
         return self.lsf_sigma_A / self.tel_step
 
 
@@ -81,7 +100,8 @@ def config_from_workload(w) -> OracleConfig:
     s = w.ssp
     return OracleConfig(w.angles_rad, w.nx, w.ny, w.spaxel_kpc, w.tel_start, w.tel_step, w.n_tel,
                         s.log_age_nodes, s.met_nodes, s.lam_start, s.lam_step, s.flux,
-                        w.psf_sigma_spx, w.lsf_sigma_A, w.z_sys, w.flux_scale)
+                        w.psf_sigma_spx, w.lsf_sigma_A, w.z_sys, w.flux_scale,
+                        getattr(w, "log_lambda", False))
 
 
 def _p64(p, name):
@@ -220,35 +240,68 @@ def interp_templates(flux: np.ndarray, ja, jz, w) -> np.ndarray:
 # --------------------------------------------------------------------------------------------------
 # steps 4-5: Doppler shift and resampling (Sec. 3)
 # --------------------------------------------------------------------------------------------------
-def doppler_index(lam_tel: np.ndarray, vlos: np.ndarray, z_sys: float, ssp_start: float,
-                  ssp_step: float) -> np.ndarray:
-    """Fractional SSP node index of the rest-frame wavelength seen at each telescope bin centre:
-    q_ij = (lam_j / ((1+z_sys)(1+beta_i)) - lam0_ssp) / dlam_ssp, shape [n, n_tel]."""
+def rest_index(cfg: OracleConfig) -> np.ndarray:
+    """SSP node index of each telescope bin centre for a source at rest in the galaxy frame (beta
+    = 0), FP64: Q_j = (lam_j/(1+z_sys) - lam0_ssp)/dlam_ssp on linear grids; on log grids
+    Q_j = off + j * ratio with off = (ln lam0_tel - ln lam0_ssp - ln(1+z_sys))/dln_ssp and
+    ratio = dln_tel/dln_ssp (this grouping is exact when the two grids coincide)."""
+    j = np.arange(cfg.n_tel, dtype=np.float64)
+    if cfg.log_lambda:
+        off = ((math.log(cfg.tel_start) - math.log(cfg.ssp_lam_start)) - math.log1p(cfg.z_sys)) \
+            / cfg.ssp_lam_step
+        return off + j * (cfg.tel_step / cfg.ssp_lam_step)
+    return (cfg.tel_lambda() / (1.0 + cfg.z_sys) - cfg.ssp_lam_start) / cfg.ssp_lam_step
+
+
+def doppler_index(cfg: OracleConfig, vlos: np.ndarray) -> np.ndarray:
+    """Fractional SSP node index of the rest-frame wavelength seen at each telescope bin centre,
+    shape [n, n_tel]: the rest wavelength is lam_j / ((1+z_sys)(1+beta_i)), so
+    q_ij = (lam_j / ((1+z_sys)(1+beta_i)) - lam0_ssp) / dlam_ssp on linear grids and
+    q_ij = Q_j - ln(1+beta_i) / dln_ssp on log grids (a Doppler shift is a constant shift of the
+    log-grid index)."""
     beta = np.asarray(vlos, dtype=np.float64) / C_KMS
-    lam_rest = lam_tel[None, :] / ((1.0 + z_sys) * (1.0 + beta[:, None]))
-    return (lam_rest - ssp_start) / ssp_step
+    if cfg.log_lambda:
+        return rest_index(cfg)[None, :] - np.log1p(beta)[:, None] / cfg.ssp_lam_step
+    lam_rest = cfg.tel_lambda()[None, :] / ((1.0 + cfg.z_sys) * (1.0 + beta[:, None]))
+    return (lam_rest - cfg.ssp_lam_start) / cfg.ssp_lam_step
 
 
-def node_decision(lam_tel: np.ndarray, vlos: np.ndarray, z_sys: float, ssp_start: float,
-                  ssp_step: float, n_nodes: int):
+def doppler_index_dbeta(cfg: OracleConfig, vlos: np.ndarray) -> np.ndarray:
+    """dq_ij/dbeta_i: -lam_j/((1+z)(1+beta)^2 dlam) on linear grids, -1/((1+beta) dln) on log
+    grids; shape [n, n_tel] (broadcast)."""
+    beta = np.asarray(vlos, dtype=np.float64) / C_KMS
+    if cfg.log_lambda:
+        return np.broadcast_to(-1.0 / ((1.0 + beta[:, None]) * cfg.ssp_lam_step),
+                               (beta.shape[0], cfg.n_tel))
+    return -cfg.tel_lambda()[None, :] / ((1.0 + cfg.z_sys) * (1.0 + beta[:, None]) ** 2
+                                         * cfg.ssp_lam_step)
+
+
+def node_decision(cfg: OracleConfig, vlos: np.ndarray, n_nodes: int):
     """Integer SSP node index k_ij = floor(q_ij) and the in-range mask, decided in FP32 the way
     the GPU kernels decide them, so that both sides put every bin in the same node interval.
 
     The fraction inside the interval stays FP64 (q - k); only the integer decision is shared.
-    The split form: q = Qi_j + t with Q_j = (lam_j/(1+z) - lam0)/dlam (FP64), Qi_j = floor(Q_j),
-    t = fl32(fl32(Q_j - Qi_j) - fl32(lam_j) * g) rounded once (a fused multiply-add), where
-    g = fl32(beta/(1+beta) / ((1+z) dlam)) and beta = fl32(v_los)/c. In range iff k >= 0 and
-    (k < n-1, or k = n-1 with t's fraction exactly 0)."""
-    lam = np.asarray(lam_tel, dtype=np.float64)
-    Q = (lam / (1.0 + z_sys) - ssp_start) / ssp_step
+    The split form: q = Qi_j + t with Q_j = rest_index (FP64), Qi_j = floor(Q_j),
+    t = fl32(fl32(Q_j - Qi_j) - L_j * g) rounded once (a fused multiply-add), where, with
+    beta = fl32(v_los)/c,
+      linear grids: L_j = fl32(lam_j), g = fl32(beta/(1+beta) / ((1+z) dlam));
+      log grids:    L_j = 1,           g = fl32(ln(1+beta) / dln).
+    In range iff k >= 0 and (k < n-1, or k = n-1 with t's fraction exactly 0)."""
+    Q = rest_index(cfg)
     Qi = np.floor(Q)
     Qf = (Q - Qi).astype(np.float32).astype(np.float64)
-    lam32 = lam.astype(np.float32).astype(np.float64)
     beta = np.asarray(vlos, dtype=np.float32).astype(np.float64) / C_KMS
-    g32 = (beta / (1.0 + beta) / ((1.0 + z_sys) * ssp_step)).astype(np.float32).astype(np.float64)
+    if cfg.log_lambda:
+        L = np.ones(cfg.n_tel)
+        g32 = (np.log1p(beta) / cfg.ssp_lam_step).astype(np.float32).astype(np.float64)
+    else:
+        L = cfg.tel_lambda().astype(np.float32).astype(np.float64)
+        g32 = (beta / (1.0 + beta) / ((1.0 + cfg.z_sys) * cfg.ssp_lam_step)
+               ).astype(np.float32).astype(np.float64)
     # the product of two FP32 values is exact in FP64 and so is the difference here: rounding it
     # once to FP32 reproduces a fused multiply-add
-    t = (Qf[None, :] - lam32[None, :] * g32[:, None]).astype(np.float32)
+    t = (Qf[None, :] - L[None, :] * g32[:, None]).astype(np.float32)
     fl = np.floor(t)
     frac = t - fl
     k = Qi[None, :].astype(np.int64) + fl.astype(np.int64)
@@ -283,9 +336,8 @@ def particle_spectra(p, idx: np.ndarray, vlos: np.ndarray, cfg: OracleConfig) ->
     v = vlos[idx]
     ja, jz, ta, tz, w, _, _ = ssp_weights(age, met, cfg.log_age_nodes, cfg.met_nodes)
     S = interp_templates(cfg.ssp_flux, ja, jz, w)
-    q = doppler_index(cfg.tel_lambda(), v, cfg.z_sys, cfg.ssp_lam_start, cfg.ssp_lam_step)
-    k, valid = node_decision(cfg.tel_lambda(), v, cfg.z_sys, cfg.ssp_lam_start,
-                             cfg.ssp_lam_step, S.shape[1])
+    q = doppler_index(cfg, v)
+    k, valid = node_decision(cfg, v, S.shape[1])
     J = 1.0 / ((1.0 + cfg.z_sys) * (1.0 + v / C_KMS))
     return (cfg.flux_scale * mass * J)[:, None] * resample_linear(S, q, k, valid)
 
@@ -453,7 +505,6 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
         return _adjoint_angles(p, cfg, R, idx, out)
     n_s = cfg.n_spaxels
     out = {k: np.zeros(idx.shape[0]) for k in ("mass", "age", "met", "vlos")}
-    lam = cfg.tel_lambda()
     nl = cfg.ssp_flux.shape[2]
     T = cfg.ssp_flux
     la_nodes, mz_nodes = cfg.log_age_nodes, cfg.met_nodes
@@ -468,8 +519,8 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
         v = vlos[ii]
         beta = v / C_KMS
         ja, jz, ta, tz, w, ina, inz = ssp_weights(age, met, la_nodes, mz_nodes)
-        q = doppler_index(lam, v, cfg.z_sys, cfg.ssp_lam_start, cfg.ssp_lam_step)
-        k, valid = node_decision(lam, v, cfg.z_sys, cfg.ssp_lam_start, cfg.ssp_lam_step, nl)
+        q = doppler_index(cfg, v)
+        k, valid = node_decision(cfg, v, nl)
         k = np.where(valid, np.minimum(k, nl - 2), 0)
         tau = np.where(valid, q - k, 0.0)
         g = G[key[ii]]                                   # [m, n_tel]
@@ -497,8 +548,7 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
         out["age"][sel] = np.where(ina, d_ua / (age * math.log(10.0)), 0.0)
         out["met"][sel] = np.where(inz, d_uz, 0.0)
         dJ = -J / (1.0 + beta)
-        dq = -lam[None, :] / ((1.0 + cfg.z_sys) * (1.0 + beta[:, None]) ** 2
-                              * cfg.ssp_lam_step)
+        dq = doppler_index_dbeta(cfg, v)
         dbeta = fs * mass * np.sum(g * (dJ[:, None] * Sl + J[:, None] * dS * dq), axis=1)
         out["vlos"][sel] = dbeta / C_KMS
     return _adjoint_angles(p, cfg, R, idx, out)

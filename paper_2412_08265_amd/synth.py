@@ -141,14 +141,15 @@ def make_galaxy(n: int, seed: int, bulge_frac: float = 0.2) -> Particles:
 class SSPGrid:
     """SSP template grid. flux[n_age][n_met][n_lam] FP32, lambda contiguous.
 
-    Nodes: log10(age/Gyr) (strictly increasing), [M/H] (strictly increasing); uniform lambda nodes
-    lam_start + k*lam_step [Angstrom].
+    Nodes: log10(age/Gyr) (strictly increasing), [M/H] (strictly increasing); lambda nodes
+    lam_start + k*lam_step [Angstrom], or lam_start * exp(k*lam_step) when log_lambda.
     """
     log_age_nodes: np.ndarray
     met_nodes: np.ndarray
     lam_start: float
     lam_step: float
     flux: np.ndarray
+    log_lambda: bool = False
 
     @property
     def n_age(self):
@@ -163,7 +164,10 @@ class SSPGrid:
         return int(self.flux.shape[2])
 
     def lam(self) -> np.ndarray:
-        return self.lam_start + self.lam_step * np.arange(self.n_lam, dtype=np.float64)
+        k = np.arange(self.n_lam, dtype=np.float64)
+        if self.log_lambda:
+            return self.lam_start * np.exp(self.lam_step * k)
+        return self.lam_start + self.lam_step * k
 
 
 def _planck_lambda(lam_A, T):
@@ -174,13 +178,14 @@ def _planck_lambda(lam_A, T):
 
 def make_ssp(n_age: int, n_met: int, lam_start: float, lam_step: float, n_lam: int,
              n_lines: int = 20, line_seed: int = 12345, age_range=(0.1, 13.0),
-             met_range=(-2.0, 0.3)) -> SSPGrid:
+             met_range=(-2.0, 0.3), log_lambda: bool = False) -> SSPGrid:
     """Synthetic SSP grid: blackbody-like continuum whose temperature falls with age and rises
     with decreasing metallicity, times 20 Gaussian absorption lines whose depths grow with age and
     metallicity. The lines are shared by all templates (seeded once)."""
     ages = np.geomspace(age_range[0], age_range[1], n_age)
     mets = np.linspace(met_range[0], met_range[1], n_met)
-    lam = lam_start + lam_step * np.arange(n_lam, dtype=np.float64)
+    k = np.arange(n_lam, dtype=np.float64)
+    lam = lam_start * np.exp(lam_step * k) if log_lambda else lam_start + lam_step * k
     lam_lo, lam_hi = lam[0], lam[-1]
     lrng = np.random.default_rng(line_seed)
     margin = min(50.0, 0.25 * (lam_hi - lam_lo))
@@ -199,21 +204,23 @@ def make_ssp(n_age: int, n_met: int, lam_start: float, lam_step: float, n_lam: i
             absorb = np.prod(1.0 - depth[:, None] * prof, axis=0)
             flux[ia, iz] = cont * absorb
     return SSPGrid(_f32(np.log10(ages)), _f32(mets), float(lam_start), float(lam_step),
-                   _f32(flux))
+                   _f32(flux), bool(log_lambda))
 
 
 def make_line_ssp(lam_start: float, lam_step: float, n_lam: int, line_center: float,
-                  line_sigma: float, n_age=2, n_met=2, amplitude=1.0) -> SSPGrid:
+                  line_sigma: float, n_age=2, n_met=2, amplitude=1.0,
+                  log_lambda: bool = False) -> SSPGrid:
     """Emission-line-only templates (compact support, zero continuum): every template is the same
     Gaussian line. Used by the line-position and flux-conservation invariants."""
-    lam = lam_start + lam_step * np.arange(n_lam, dtype=np.float64)
+    k = np.arange(n_lam, dtype=np.float64)
+    lam = lam_start * np.exp(lam_step * k) if log_lambda else lam_start + lam_step * k
     prof = amplitude * np.exp(-0.5 * ((lam - line_center) / line_sigma) ** 2)
     prof[prof < 1e-30] = 0.0
     flux = np.broadcast_to(prof, (n_age, n_met, n_lam)).copy()
     ages = np.geomspace(0.1, 13.0, n_age)
     mets = np.linspace(-2.0, 0.3, n_met)
     return SSPGrid(_f32(np.log10(ages)), _f32(mets), float(lam_start), float(lam_step),
-                   _f32(flux))
+                   _f32(flux), bool(log_lambda))
 
 
 # --------------------------------------------------------------------------------------------------
@@ -236,6 +243,7 @@ class Workload:
     lsf_sigma_A: float = 0.0
     z_sys: float = 0.0
     flux_scale: float = 1.0
+    log_lambda: bool = False     # telescope bins tel_start * exp(k * tel_step) (as the SSP grid)
 
     @property
     def angles_rad(self):

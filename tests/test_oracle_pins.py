@@ -24,7 +24,7 @@ def _cfg(nx=8, ny=8, s=1.0, angles=(0.0, 0.0, 0.0), ssp=None, tel=None, psf=0.0,
     tel = tel or (ssp.lam_start, ssp.lam_step, ssp.n_lam)
     return O.OracleConfig(angles, nx, ny, s, tel[0], tel[1], tel[2], ssp.log_age_nodes,
                           ssp.met_nodes, ssp.lam_start, ssp.lam_step, ssp.flux, psf, lsf,
-                          z_sys, flux_scale)
+                          z_sys, flux_scale, ssp.log_lambda)
 
 
 def _parts(n, seed=0, r=5.0, vmax=300.0):
@@ -285,6 +285,61 @@ def test_flux_conserved_for_shifts_inside_band():
                     assert abs(F * (1 + beta) - F0) / F0 > bound
 
 
+# log-lambda grids: nodes start * exp(k * step)
+def test_log_grid_at_rest_is_interpolation_in_ln_lambda():
+    """At rest a log-grid spectrum is the template interpolated linearly in ln(lambda): on the
+    same grid it is the template itself; on an offset, finer grid it is np.interp in ln(lambda)."""
+    ssp = synth.make_ssp(6, 4, 4000.0, 4e-4, 300, log_lambda=True)
+    p = _single(mass=2.0)
+    same = _cfg(ssp=ssp)
+    f = O.particle_spectra(p, np.array([0]), np.zeros(1), same)[0]
+    ja, jz, ta, tz, w, _, _ = O.ssp_weights(p.age, p.met, same.log_age_nodes, same.met_nodes)
+    S = O.interp_templates(same.ssp_flux, ja, jz, w)[0]
+    np.testing.assert_allclose(f, 2.0 * S, rtol=1e-10)
+    tel = (4000.0 * math.exp(0.37 * 4e-4), 2.7e-4, 480)          # runs past the SSP end
+    off = _cfg(ssp=ssp, tel=tel)
+    f = O.particle_spectra(p, np.array([0]), np.zeros(1), off)[0]
+    ref = 2.0 * np.interp(np.log(off.tel_lambda()), np.log(ssp.lam()), S, left=0.0, right=0.0)
+    np.testing.assert_allclose(f, ref, rtol=1e-9, atol=1e-13 * np.abs(ref).max())
+    assert f[-1] == 0.0 and f[0] != 0.0
+
+
+@pytest.mark.parametrize("m", [3, -5])
+def test_log_grid_velocity_is_an_index_shift(m):
+    """On identical log grids a Doppler factor 1+beta = exp(m * step) moves the spectrum by
+    exactly m bins and scales it by J = 1/(1+beta)."""
+    step = 4e-4
+    ssp = synth.make_ssp(6, 4, 4000.0, step, 300, log_lambda=True)
+    cfg = _cfg(ssp=ssp)
+    beta = math.expm1(m * step)
+    v = beta * O.C_KMS
+    p = _single(mass=1.5, vlos=v)
+    f = O.particle_spectra(p, np.array([0]), np.array([v]), cfg)[0]
+    ja, jz, ta, tz, w, _, _ = O.ssp_weights(p.age, p.met, cfg.log_age_nodes, cfg.met_nodes)
+    S = O.interp_templates(cfg.ssp_flux, ja, jz, w)[0]
+    ref = np.zeros_like(S)
+    if m > 0:
+        ref[m:] = S[:-m]
+    else:
+        ref[:m] = S[-m:]
+    np.testing.assert_allclose(f, 1.5 * ref / (1 + beta), rtol=1e-8,
+                               atol=1e-8 * np.abs(ref).max())
+
+
+def test_log_grid_line_moves_and_lsf_width():
+    step = 1e-4
+    ssp = synth.make_line_ssp(5000.0, step, 4000, 6000.0, 0.6, log_lambda=True)
+    cfg = _cfg(ssp=ssp, lsf=2.0)
+    for v in (250.0, -400.0):
+        f = O.particle_spectra(_single(vlos=v), np.array([0]), np.array([v]), cfg)[0]
+        lam = cfg.tel_lambda()
+        expect = 6000.0 * (1 + v / O.C_KMS)
+        assert abs(math.log(lam[np.argmax(f)] / expect)) <= 0.5 * step + 1e-12
+    # the LSF width in bins is sigma / (lambda_c * step) at the grid's central wavelength
+    lam_c = 5000.0 * math.exp(step * 3999 / 2)
+    assert abs(cfg.lsf_sigma_bins() - 2.0 / (lam_c * step)) <= 1e-12
+
+
 def test_out_of_band_is_zero_and_last_node_is_included():
     ssp = synth.make_ssp(3, 3, 5000.0, 1.0, 10)
     cfg = _cfg(ssp=ssp, tel=(4995.0, 1.0, 20))
@@ -375,8 +430,9 @@ def test_psf_lsf_delta_flux_and_adjoint():
 
 
 # ------------------------------------------------------------------ adjoint
-def _grad_setup(seed=21, n=300):
-    ssp = synth.make_ssp(7, 5, 4000.0, 2.0, 220)
+def _grad_setup(seed=21, n=300, log_lambda=False):
+    ssp = (synth.make_ssp(7, 5, 4000.0, 5e-4, 220, log_lambda=True) if log_lambda
+           else synth.make_ssp(7, 5, 4000.0, 2.0, 220))
     cfg = _cfg(nx=9, ny=8, s=1.0, angles=(math.radians(55), 0.2, 0.3), ssp=ssp, psf=1.2,
                lsf=3.1)
     p = _parts(n, seed, r=4.5)
@@ -402,8 +458,9 @@ def _delta_L(cfg, fw, target, key_s, f_plus, f_minus):
     return out[0] - out[1]
 
 
-def test_adjoint_matches_central_differences():
-    p, cfg, fw, target, G = _grad_setup()
+@pytest.mark.parametrize("log_lambda", [False, True])
+def test_adjoint_matches_central_differences(log_lambda):
+    p, cfg, fw, target, G = _grad_setup(log_lambda=log_lambda)
     g = O.adjoint(p, cfg, G, fw)
     key, vlos = fw["key"], fw["vlos"]
     rng = np.random.default_rng(0)
