@@ -52,11 +52,16 @@ typedef struct {
   double  spaxel_kpc;
 } rubix_grid;
 
-/* Uniform wavelength grid: value k is start + k*step [Angstrom], k = 0..n-1, step > 0. */
+/* Wavelength grid, k = 0..n-1, step > 0:
+ *   log_spaced = 0: value k is start + k*step [Angstrom] (uniform in lambda);
+ *   log_spaced = 1: value k is start * exp(k*step), start > 0 [Angstrom], step in ln(lambda)
+ *                   (uniform in ln lambda: a Doppler shift is then a constant index shift).
+ * The SSP grid and every telescope grid used with it must be of the same kind. */
 typedef struct {
   double  start;
   double  step;
   int32_t n;
+  int32_t log_spaced;
 } rubix_lgrid;
 
 /* SSP template library (the paper's "simple stellar population (SSP) library", Sec. 3).
@@ -91,7 +96,10 @@ typedef struct {
   double      z_sys;            /* systemic redshift (> -1); 0 for a galaxy at rest            */
   double      flux_scale;       /* overall flux factor (e.g. distance dimming); 1 by default   */
   double      psf_sigma_spx;    /* Gaussian PSF sigma in spaxels; 0 = none                     */
-  double      lsf_sigma_A;      /* Gaussian LSF sigma in Angstrom; 0 = none                    */
+  double      lsf_sigma_A;      /* Gaussian LSF sigma in Angstrom; 0 = none. On a log-spaced
+                                   telescope grid it is converted to bins at the grid's central
+                                   wavelength start*exp(step*(n-1)/2) and held constant in bins
+                                   (a constant velocity width)                                   */
   int32_t    *key;              /* [n]           written by rubix_rotate_bin                   */
   int32_t    *perm;             /* [n]           written by rubix_rotate_bin                   */
   int32_t    *seg_off;          /* [nx*ny + 1]   written by rubix_rotate_bin                   */
@@ -136,7 +144,8 @@ int rubix_cube(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, void *ws
 /* Step 7 of Sec. 3: LSF then PSF, out[j] = A in[j] for each job j (in[j], out[j] DEVICE cubes of
  * that job's shape, not overlapping). Separable sampled Gaussians exp(-k^2/(2 sigma^2)),
  * |k| <= int(4 sigma + 0.5), normalised to unit sum, zero padding outside the cube: along lambda
- * with sigma = lsf_sigma_A / tel.step bins, then along y and along x with sigma = psf_sigma_spx.
+ * with sigma = lsf_sigma_A / tel.step bins (log grids: see rubix_job.lsf_sigma_A), then along y
+ * and along x with sigma = psf_sigma_spx.
  * sigma = 0 skips that axis. The operator is symmetric, so the same call applies its adjoint. */
 int rubix_psf_lsf(const rubix_job *jobs, int n_jobs, const float *const *in, float *const *out,
                   void *ws, size_t ws_bytes, void *stream);

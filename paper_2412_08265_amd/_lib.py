@@ -27,7 +27,7 @@ class RubixGrid(ctypes.Structure):
 
 
 class RubixLGrid(ctypes.Structure):
-    _fields_ = [("start", c_double), ("step", c_double), ("n", c_int32)]
+    _fields_ = [("start", c_double), ("step", c_double), ("n", c_int32), ("log_spaced", c_int32)]
 
 
 class RubixSSP(ctypes.Structure):

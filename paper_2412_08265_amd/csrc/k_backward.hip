@@ -26,11 +26,20 @@ __global__ __launch_bounds__(256) void k_bintab(const Table *__restrict__ T) {
     const JobDev &J = jobs[jj];
     const int jb = (int)((vb - J.vb_start[K_BINTAB]) * 256 + threadIdx.x);
     if (jb >= J.n_tel) continue;
-    const double lam = J.tel_start + (double)jb * J.tel_step;
-    const double Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
+    // as the forward kernel's split index: Q and the factor of the Doppler term (lambda or 1)
+    double Q;
+    float lamf;
+    if (J.log_lambda) {
+      Q = J.q_off + (double)jb * J.q_ratio;
+      lamf = 1.0f;
+    } else {
+      const double lam = J.tel_start + (double)jb * J.tel_step;
+      Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
+      lamf = (float)lam;
+    }
     const double Qfl = floor(Q);
     const int qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
-    J.bintab[jb] = make_float4(__int_as_float(qi), (float)(Q - Qfl), (float)lam, 0.f);
+    J.bintab[jb] = make_float4(__int_as_float(qi), (float)(Q - Qfl), lamf, 0.f);
   }
 }
 
@@ -143,7 +152,10 @@ __global__ __launch_bounds__(kFinThreads) void k_bwd_final(const Table *__restri
         if (in_a) ga = (float)(A * sa / (S.log_age[ja + 1] - S.log_age[ja]) / (age * 2.302585092994046));
         if (in_z) gz = (float)(A * sz / (S.met[jz + 1] - S.met[jz]));
         const double dJ = -jac / (1.0 + beta);
-        const double dq = -1.0 / (opz * (1.0 + beta) * (1.0 + beta) * S.lam_step);
+        // dq/dbeta per unit of the bin factor accumulated in Y (lambda on linear grids, 1 on
+        // log grids, where q = Q - ln(1+beta)/dln)
+        const double dq = J.log_lambda ? -1.0 / ((1.0 + beta) * S.lam_step)
+                                       : -1.0 / (opz * (1.0 + beta) * (1.0 + beta) * S.lam_step);
         const double dbeta = fs * m * (dJ * sm + jac * dq * Y);
         const double dv = dbeta / kCkmsB;
         gv = (float)dv;

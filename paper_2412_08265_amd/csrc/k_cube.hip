@@ -53,12 +53,20 @@ __device__ __forceinline__ double clamp01(double t) { return fmin(1.0, fmax(0.0,
 // kCubeWaveBins bins fits its 64-node window: q advances by bin_slope/(1+beta) nodes per bin, so
 // when 61 steps stay below 61.9 nodes the node indices of 62 consecutive bins span at most 63
 // nodes (0.1 node of margin is far above the FP32 error of q). k_prep and k_vbound both use it.
+// On log grids the Doppler term is the constant index shift ln(1+beta)/dln and the node step per
+// bin does not depend on beta.
 __device__ __forceinline__ void doppler_slope(const JobDev &J, const SspDev &S, double v, float &g,
                                               bool &fits) {
   const double beta = v / kCkms;
-  const double opz = 1.0 + J.z_sys;
-  g = (float)(beta / (1.0 + beta) / (opz * S.lam_step));
-  const double beff = J.bin_slope / (1.0 + beta);
+  double beff;
+  if (J.log_lambda) {
+    g = (float)(log1p(beta) / S.lam_step);
+    beff = (beta > -1.0) ? J.bin_slope : -1.0;
+  } else {
+    const double opz = 1.0 + J.z_sys;
+    g = (float)(beta / (1.0 + beta) / (opz * S.lam_step));
+    beff = J.bin_slope / (1.0 + beta);
+  }
   fits = isfinite((double)g) && beff > 0.0 && 61.0 * beff <= 61.9;
 }
 
@@ -284,14 +292,23 @@ __device__ __forceinline__ float slot_contrib(const PrepRec &r, __amdgpu_buffer_
   return (k == nl - 1) ? s0 : fmaf(tau, s1 - s0, s0);
 }
 
+// Rest-frame node index Q of bin jb split into an integer and an FP32 fraction, and the factor
+// that multiplies the particle's Doppler term g: the bin wavelength on linear grids, 1 on log
+// grids (where q = Q - g).
 __device__ __forceinline__ void split_index(const JobDev &J, const SspDev &S, int jb, int &qi,
                                             float &qf, float &lamf) {
-  const double lam = J.tel_start + (double)jb * J.tel_step;
-  const double Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
+  double Q;
+  if (J.log_lambda) {
+    Q = J.q_off + (double)jb * J.q_ratio;
+    lamf = 1.0f;
+  } else {
+    const double lam = J.tel_start + (double)jb * J.tel_step;
+    Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
+    lamf = (float)lam;
+  }
   const double Qfl = floor(Q);
   qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
   qf = (float)(Q - Qfl);
-  lamf = (float)lam;
 }
 
 __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__ T) {

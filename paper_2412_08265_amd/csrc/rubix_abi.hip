@@ -84,6 +84,15 @@ struct JobSizes {
 
 static int radius_of(double sigma) { return sigma > 0.0 ? (int)(4.0 * sigma + 0.5) : 0; }
 
+// LSF width in telescope bins; on a log grid taken at the central wavelength (constant in bins).
+static double lsf_bins(const rubix_job &j) {
+  if (j.tel.log_spaced) {
+    const double lam_c = j.tel.start * exp(j.tel.step * (j.tel.n - 1) / 2.0);
+    return j.lsf_sigma_A / (lam_c * j.tel.step);
+  }
+  return j.lsf_sigma_A / j.tel.step;
+}
+
 static JobSizes sizes_of(const rubix_job &j) {
   JobSizes z{};
   z.n = j.p.n;
@@ -98,7 +107,7 @@ static JobSizes sizes_of(const rubix_job &j) {
   z.n_chunk_ub = (int)(z.n_s + cdiv(z.n, kCubeChunk));
   z.n_comb_ub = z.n > kCubeChunk ? (int)(z.n / (kCubeChunk + 1) + 1) : 0;
   z.n_slot_ub = (int)(2 * cdiv(z.n, kCubeChunk) + 2);
-  z.lsf_sigma_bins = j.lsf_sigma_A / j.tel.step;
+  z.lsf_sigma_bins = lsf_bins(j);
   z.lsf_r = radius_of(z.lsf_sigma_bins);
   z.psf_r = radius_of(j.psf_sigma_spx);
   z.n_psf_tiles = (int)cdiv(z.n_tel, kPsfLanes);
@@ -157,6 +166,10 @@ static int validate_ssp(const rubix_ssp *ssp) {
   if (ssp->lam.n < 2) return fail(RUBIX_EINVAL, "ssp.lam.n=%d < 2", ssp->lam.n);
   if (!finite_pos(ssp->lam.step) || !isfinite(ssp->lam.start))
     return fail(RUBIX_EINVAL, "ssp.lam start/step invalid");
+  if (ssp->lam.log_spaced != 0 && ssp->lam.log_spaced != 1)
+    return fail(RUBIX_EINVAL, "ssp.lam.log_spaced must be 0 or 1");
+  if (ssp->lam.log_spaced && !finite_pos(ssp->lam.start))
+    return fail(RUBIX_EINVAL, "a log-spaced SSP grid needs start > 0");
   if ((int64_t)ssp->n_age * ssp->n_met * ssp->lam.n > INT32_MAX)
     return fail(RUBIX_ERANGE, "ssp grid has more than 2^31-1 values");
   return RUBIX_OK;
@@ -178,6 +191,10 @@ static int validate_jobs(const rubix_job *jobs, int n_jobs, Call call) {
     if (j.tel.n < 1) return fail(RUBIX_EINVAL, "job %d: tel.n=%d < 1", k, j.tel.n);
     if (!finite_pos(j.tel.step) || !isfinite(j.tel.start))
       return fail(RUBIX_EINVAL, "job %d: telescope grid start/step invalid", k);
+    if (j.tel.log_spaced != 0 && j.tel.log_spaced != 1)
+      return fail(RUBIX_EINVAL, "job %d: tel.log_spaced must be 0 or 1", k);
+    if (j.tel.log_spaced && !finite_pos(j.tel.start))
+      return fail(RUBIX_EINVAL, "job %d: a log-spaced telescope grid needs start > 0", k);
     if (!(j.z_sys > -1.0) || !isfinite(j.z_sys)) return fail(RUBIX_EINVAL, "job %d: z_sys must be > -1", k);
     if (!isfinite(j.flux_scale)) return fail(RUBIX_EINVAL, "job %d: flux_scale not finite", k);
     for (int a = 0; a < 3; ++a)
@@ -186,7 +203,7 @@ static int validate_jobs(const rubix_job *jobs, int n_jobs, Call call) {
         !isfinite(j.lsf_sigma_A))
       return fail(RUBIX_EINVAL, "job %d: PSF/LSF sigma must be finite and >= 0", k);
     if (radius_of(j.psf_sigma_spx) > RUBIX_MAX_RADIUS ||
-        radius_of(j.lsf_sigma_A / j.tel.step) > RUBIX_MAX_RADIUS)
+        radius_of(lsf_bins(j)) > RUBIX_MAX_RADIUS)
       return fail(RUBIX_ERANGE, "job %d: PSF/LSF radius exceeds %d", k, RUBIX_MAX_RADIUS);
     if (call == CALL_SIZE) continue;
     const bool need_pos = call == CALL_ROTATE || call == CALL_PACK;
@@ -209,6 +226,16 @@ static int validate_jobs(const rubix_job *jobs, int n_jobs, Call call) {
       return fail(RUBIX_EINVAL, "job %d: cube_raw is NULL", k);
     if (call == CALL_PACK && !j.cube) return fail(RUBIX_EINVAL, "job %d: cube is NULL", k);
   }
+  return RUBIX_OK;
+}
+
+// Every telescope grid must be of the SSP grid's kind (both uniform in lambda or in ln lambda).
+static int check_grid_kinds(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp) {
+  for (int k = 0; k < n_jobs; ++k)
+    if (jobs[k].tel.log_spaced != ssp->lam.log_spaced)
+      return fail(RUBIX_EINVAL, "job %d: telescope grid %s but SSP grid %s", k,
+                  jobs[k].tel.log_spaced ? "log-spaced" : "linear",
+                  ssp->lam.log_spaced ? "log-spaced" : "linear");
   return RUBIX_OK;
 }
 
@@ -267,6 +294,7 @@ static void fill_ssp(SspDev &S, const rubix_ssp *ssp) {
   S.flux = ssp->flux;
   S.n_age = ssp->n_age; S.n_met = ssp->n_met; S.n_lam = ssp->lam.n;
   S.lam_start = ssp->lam.start; S.lam_step = ssp->lam.step;
+  S.log_lambda = ssp->lam.log_spaced;
   for (int i = 0; i < ssp->n_age; ++i) {
     S.log_age[i] = (double)ssp->log_age_nodes[i];
     S.age_thr[i] = pow(10.0, S.log_age[i]);
@@ -311,7 +339,15 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
     gauss_weights(z.lsf_sigma_bins, z.lsf_r, d.lsf_w);
     gauss_weights(j.psf_sigma_spx, z.psf_r, d.psf_w);
     d.n_tel = (int32_t)z.n_tel; d.passes = z.passes; d.n_sort_tiles = z.n_sort_tiles; d.n_tiles = z.n_tiles;
-    d.bin_slope = ssp ? j.tel.step / ((1.0 + j.z_sys) * ssp->lam.step) : 1.0;
+    d.log_lambda = j.tel.log_spaced;
+    if (ssp && j.tel.log_spaced) {
+      // node index of bin j at rest: q_off + j q_ratio (exact when the two grids coincide)
+      d.q_off = ((log(j.tel.start) - log(ssp->lam.start)) - log1p(j.z_sys)) / ssp->lam.step;
+      d.q_ratio = j.tel.step / ssp->lam.step;
+      d.bin_slope = d.q_ratio;
+    } else {
+      d.bin_slope = ssp ? j.tel.step / ((1.0 + j.z_sys) * ssp->lam.step) : 1.0;
+    }
     // a telescope grid coarser than the SSP grid needs node windows wider than a wave; such jobs
     // gather their two taps per corner directly from the template grid
     d.cube_direct = d.bin_slope > 1.0 ? 1 : 0;
@@ -437,6 +473,7 @@ int rubix_workspace_size(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp
   int rc = validate_jobs(jobs, n_jobs, CALL_SIZE);
   if (rc) return rc;
   if (ssp && (rc = validate_ssp(ssp))) return rc;
+  if (ssp && (rc = check_grid_kinds(jobs, n_jobs, ssp))) return rc;
   *bytes = workspace_bytes(jobs, n_jobs);
   return RUBIX_OK;
 }
@@ -456,6 +493,7 @@ int rubix_cube(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, void *ws
   int rc;
   if ((rc = validate_jobs(jobs, n_jobs, CALL_CUBE))) return rc;
   if ((rc = validate_ssp(ssp))) return rc;
+  if ((rc = check_grid_kinds(jobs, n_jobs, ssp))) return rc;
   if ((rc = check_ws(jobs, n_jobs, ws, ws_bytes))) return rc;
   auto tab = build_table(jobs, n_jobs, ssp, ws, nullptr, nullptr);
   if (!g_timer_on) return run(tab, ws, static_cast<hipStream_t>(stream), launch_cube, "rubix_cube");
@@ -528,6 +566,7 @@ int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
   int rc;
   if ((rc = validate_jobs(jobs, n_jobs, CALL_BWD))) return rc;
   if ((rc = validate_ssp(ssp))) return rc;
+  if ((rc = check_grid_kinds(jobs, n_jobs, ssp))) return rc;
   if (!grad_raw || !d_mass || !d_age || !d_met || !d_vlos || !d_angles)
     return fail(RUBIX_EINVAL, "gradient array argument is NULL");
   for (int k = 0; k < n_jobs; ++k) {
@@ -553,6 +592,7 @@ int rubix_forward_pack(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, 
   int rc;
   if ((rc = validate_jobs(jobs, n_jobs, CALL_PACK))) return rc;
   if ((rc = validate_ssp(ssp))) return rc;
+  if ((rc = check_grid_kinds(jobs, n_jobs, ssp))) return rc;
   if ((rc = check_ws_regions(jobs, n_jobs, ws, ws_bytes))) return rc;
   if (!host_table) return fail(RUBIX_EINVAL, "host_table is NULL");
   if (host_table_bytes < al(table_bytes(n_jobs)))

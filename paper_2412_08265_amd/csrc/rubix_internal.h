@@ -57,7 +57,8 @@ struct PrepRec {
   int32_t row;      // flux offset of corner (ja, jz): (ja*n_met + jz)*n_lam, stored as ~offset
                     // (negative) when the particle's node span does not fit a wave window (see
                     // prep_row): the 62 node indices of a wave's bins then span more than 63 nodes
-  float g;          // beta/(1+beta) / ((1+z_sys) dlam_ssp): Doppler slope of the node index
+  float g;          // Doppler term of the node index: beta/(1+beta) / ((1+z_sys) dlam_ssp)
+                    // per Angstrom of bin wavelength, or ln(1+beta)/dln_ssp on log grids
   float a[4];       // corner weights (forward: flux_scale m J w_c; backward: w_c)
   int32_t spaxel;   // key of the particle
   int32_t pad;
@@ -76,7 +77,7 @@ struct CombRec {
 
 struct SspDev {
   const float *flux;
-  int32_t n_age, n_met, n_lam, pad;
+  int32_t n_age, n_met, n_lam, log_lambda;   // log_lambda: nodes lam_start * exp(k lam_step)
   double lam_start, lam_step;
   double age_thr[RUBIX_MAX_AGE_NODES];   // 10^(log age node), FP64 cell thresholds in Gyr
   double log_age[RUBIX_MAX_AGE_NODES];   // log10 age nodes (FP64 copies of the FP32 inputs)
@@ -97,7 +98,9 @@ struct JobDev {
   float lsf_w[kWArray];
   float psf_w[kWArray];
   int32_t n_tel, passes, n_sort_tiles, n_tiles;     // n_tiles: cube lambda tiles of kCubeTL bins
-  int32_t cube_direct, pad_;                         // 1 = gather taps from global (coarse grids)
+  int32_t cube_direct, log_lambda;                   // 1 = gather taps from global (coarse grids);
+                                                     // 1 = both grids uniform in ln(lambda)
+  double q_off, q_ratio;  // log grids: rest-frame node index of bin j is q_off + j * q_ratio
   double bin_slope;                                  // d(node index)/d(bin) at rest
   int32_t n_chunk_ub, n_comb_ub, lsf_r, psf_r;
   int32_t n_psf_tiles, n_psf_seg_y, n_psf_seg_x, n_fin_blocks;

@@ -32,23 +32,28 @@ C_KMS = 299792.458
 class DeviceSSP:
     """SSP template grid resident in device memory (flux [n_age][n_met][n_lam] FP32)."""
 
-    def __init__(self, log_age_nodes, met_nodes, lam_start, lam_step, flux, device="cuda"):
+    def __init__(self, log_age_nodes, met_nodes, lam_start, lam_step, flux, device="cuda",
+                 log_lambda=False):
         self.log_age_nodes = np.ascontiguousarray(log_age_nodes, dtype=np.float32)
         self.met_nodes = np.ascontiguousarray(met_nodes, dtype=np.float32)
         flux = np.ascontiguousarray(flux, dtype=np.float32)
         self.flux = torch.from_numpy(flux).to(device)
         self.lam_start, self.lam_step = float(lam_start), float(lam_step)
         self.n_lam = int(flux.shape[2])
+        self.log_lambda = bool(log_lambda)
         self.c = RubixSSP(self.log_age_nodes.shape[0], self.met_nodes.shape[0],
                           self.log_age_nodes.ctypes.data_as(POINTER(c_float)),
                           self.met_nodes.ctypes.data_as(POINTER(c_float)),
-                          RubixLGrid(self.lam_start, self.lam_step, self.n_lam),
+                          RubixLGrid(self.lam_start, self.lam_step, self.n_lam,
+                                     int(self.log_lambda)),
                           self.flux.data_ptr())
 
     @classmethod
     def from_grid(cls, g, device="cuda") -> "DeviceSSP":
-        """From any object with log_age_nodes, met_nodes, lam_start, lam_step, flux."""
-        return cls(g.log_age_nodes, g.met_nodes, g.lam_start, g.lam_step, g.flux, device)
+        """From any object with log_age_nodes, met_nodes, lam_start, lam_step, flux (and
+        optionally log_lambda)."""
+        return cls(g.log_age_nodes, g.met_nodes, g.lam_start, g.lam_step, g.flux, device,
+                   getattr(g, "log_lambda", False))
 
 
 FIELDS = ("x", "y", "z", "vx", "vy", "vz", "mass", "age", "met")
@@ -90,11 +95,13 @@ class Observation:
     lsf_sigma_A: float = 0.0
     z_sys: float = 0.0
     flux_scale: float = 1.0
+    log_lambda: bool = False     # telescope bins tel_start * exp(k * tel_step)
 
     @classmethod
     def from_workload(cls, w) -> "Observation":
         return cls(tuple(w.angles_rad), w.nx, w.ny, w.spaxel_kpc, w.tel_start, w.tel_step,
-                   w.n_tel, w.psf_sigma_spx, w.lsf_sigma_A, w.z_sys, w.flux_scale)
+                   w.n_tel, w.psf_sigma_spx, w.lsf_sigma_A, w.z_sys, w.flux_scale,
+                   bool(getattr(w, "log_lambda", False)))
 
     @property
     def n_spaxels(self):
@@ -127,7 +134,8 @@ def make_job(gal: DeviceGalaxy, obs: Observation, buf: JobBuffers) -> RubixJob:
     for k in range(3):
         j.angles_rad[k] = float(obs.angles_rad[k])
     j.grid = RubixGrid(int(obs.nx), int(obs.ny), float(obs.spaxel_kpc))
-    j.tel = RubixLGrid(float(obs.tel_start), float(obs.tel_step), int(obs.n_tel))
+    j.tel = RubixLGrid(float(obs.tel_start), float(obs.tel_step), int(obs.n_tel),
+                       int(obs.log_lambda))
     j.z_sys, j.flux_scale = float(obs.z_sys), float(obs.flux_scale)
     j.psf_sigma_spx, j.lsf_sigma_A = float(obs.psf_sigma_spx), float(obs.lsf_sigma_A)
     j.key, j.perm, j.seg_off = buf.key.data_ptr(), buf.perm.data_ptr(), buf.seg_off.data_ptr()

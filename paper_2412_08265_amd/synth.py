@@ -236,7 +236,7 @@ class Workload:
     ny: int
     spaxel_kpc: float
     tel_start: float             # telescope bin centre of bin 0 [A]
-    tel_step: float              # [A]
+    tel_step: float              # [A], or the ln(lambda) step when log_lambda
     n_tel: int
     ssp: SSPGrid
     psf_sigma_spx: float = 0.0
@@ -283,6 +283,17 @@ def medium_workload(seed=2, n=1_000_000) -> Workload:
     ssp = cached_ssp(100, 12, 3600.0, step, 3000)
     return Workload("disk+bulge-1e6", p, (60.0, 0.0, 0.0), 50, 50, 0.6,
                     3600.0, step, 3000, ssp, psf_sigma_spx=1.5, lsf_sigma_A=2.5)
+
+
+def log_workload(seed=5, n=200_000) -> Workload:
+    """Wavelength grids uniform in ln(lambda): 2e5 particles (disk + bulge), 30x30 spaxels of
+    1 kpc, SSP 40x8x3000 from 3600 A with dln = 1.2e-4 (36 km/s per node), telescope 3300 bins of
+    dln = 1e-4 starting 0.37 node above the SSP start, systemic z 0.002, PSF 1 spx, LSF 1.2 A."""
+    p = make_galaxy(n, seed)
+    ssp = cached_ssp(40, 8, 3600.0, 1.2e-4, 3000, log_lambda=True)
+    return Workload("loglam-2e5", p, (60.0, 0.0, 0.0), 30, 30, 1.0,
+                    3600.0 * math.exp(0.37 * 1.2e-4), 1.0e-4, 3300, ssp, psf_sigma_spx=1.0,
+                    lsf_sigma_A=1.2, z_sys=0.002, log_lambda=True)
 
 
 def large_workload(seed=3, n=10_000_000, spaxel_kpc=0.2) -> Workload:

@@ -172,6 +172,23 @@ def test_graph_entry_points_validate_before_device_work(lib):
     assert lib.rubix_graph_destroy(None) == _lib.RUBIX_OK
 
 
+def test_wavelength_grid_kinds_are_validated(lib):
+    from paper_2412_08265_amd import _lib
+    ssp, keep = _ssp_c([-1, 0, 1], [-2, 0])
+    j = _job()
+    assert _ws_size(lib, [j], ctypes.byref(ssp))[0] == _lib.RUBIX_OK
+    ssp.lam.log_spaced = 1                      # log SSP grid, linear telescope grid
+    assert _ws_size(lib, [j], ctypes.byref(ssp))[0] == _lib.RUBIX_EINVAL
+    assert b"log-spaced" in lib.rubix_last_error()
+    j.tel.log_spaced = 1
+    assert _ws_size(lib, [j], ctypes.byref(ssp))[0] == _lib.RUBIX_OK
+    j.tel.log_spaced = 2
+    assert _ws_size(lib, [j])[0] == _lib.RUBIX_EINVAL
+    j.tel.log_spaced = 1
+    j.tel.start = -5.0                          # ln of a negative start
+    assert _ws_size(lib, [j])[0] == _lib.RUBIX_EINVAL
+
+
 def test_product_path_never_touches_the_oracle():
     """The HIP package and its binding import nothing from the oracle (and vice versa)."""
     pkg = os.path.join(ROOT, "paper_2412_08265_amd")

@@ -243,3 +243,29 @@ def test_first_ssp_cell_with_window_before_node_zero():
     # the blue end is where the missing light showed up
     ref = fo["cube_raw"][:, :64]
     assert np.abs(g["cube_raw"][:, :64] - ref).max() <= 1e-5 * np.abs(fo["cube_raw"]).max()
+
+
+def test_log_grid_forward_matches_oracle():
+    """Both wavelength grids uniform in ln(lambda) (Doppler shift = index shift), telescope grid
+    offset from and finer than the SSP grid, systemic redshift, PSF and LSF."""
+    w = synth.log_workload()
+    log(f"log grids: {w.particles.n} particles, {w.nx}x{w.ny}x{w.n_tel}")
+    _, g = gpu_forward(w)
+    cfg = O.config_from_workload(w)
+    fo = O.forward(w.particles, cfg, workers=WORKERS)
+    _check_rotate_bin(w, g, fo)
+    assert_cube_close(g["cube_raw"], fo["cube_raw"], what="log-grid cube_raw")
+    assert_cube_close(g["cube"], fo["cube"], what="log-grid cube")
+
+
+def test_grid_kinds_must_match():
+    from paper_2412_08265_amd import _lib, ops
+    w = synth.log_workload(n=1000)
+    gal = ops.DeviceGalaxy.from_host(w.particles)
+    ssp = ops.DeviceSSP.from_grid(w.ssp)
+    obs = ops.Observation.from_workload(w)
+    obs.log_lambda = False
+    obs.lsf_sigma_A = 0.0           # (1.2 A would be 12000 bins of a linear 1e-4 A step)
+    with pytest.raises(_lib.RubixError) as e:
+        ops.Forward(gal, obs, ssp)()
+    assert e.value.code == _lib.RUBIX_EINVAL
