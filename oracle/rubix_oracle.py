@@ -38,7 +38,7 @@ __all__ = [
     "C_KMS", "rotation_matrix", "rotation_matrix_derivs", "rotate_positions", "los_velocity",
     "spaxel_keys", "sort_by_key", "ssp_cell", "ssp_weights", "interp_templates",
     "rest_index", "doppler_index", "doppler_index_dbeta", "node_decision", "resample_linear",
-    "particle_spectra", "cube_raw", "gaussian_weights",
+    "integral_linear", "bin_edge_indices", "particle_spectra", "cube_raw", "gaussian_weights",
     "convolve_axis", "psf_lsf", "forward", "loss", "loss_grad_cube", "adjoint",
     "OracleConfig", "config_from_workload",
 ]
@@ -53,7 +53,7 @@ class OracleConfig:
     def __init__(self, angles_rad, nx, ny, spaxel_kpc, tel_start, tel_step, n_tel,
                  log_age_nodes, met_nodes, ssp_lam_start, ssp_lam_step, ssp_flux,
                  psf_sigma_spx=0.0, lsf_sigma_A=0.0, z_sys=0.0, flux_scale=1.0,
-                 log_lambda=False):
+                 log_lambda=False, resample=0):
         self.angles_rad = tuple(float(a) for a in angles_rad)
         self.nx, self.ny = int(nx), int(ny)
         self.spaxel_kpc = float(spaxel_kpc)
@@ -68,6 +68,11 @@ class OracleConfig:
         self.flux_scale = float(flux_scale)
         # both wavelength grids uniform in ln(lambda): value k is start * exp(k * step)
         self.log_lambda = bool(log_lambda)
+        # resampling reading: 0 = the shifted spectrum sampled at bin centres (linear
+        # interpolation); 1 = its average over each telescope bin (flux conserving; linear grids)
+        self.resample = int(resample)
+        if self.resample not in (0, 1) or (self.resample == 1 and self.log_lambda):
+            raise ValueError("resample must be 0, or 1 on linear grids")
 
     @property
     def n_spaxels(self):
@@ -101,7 +106,7 @@ def config_from_workload(w) -> OracleConfig:
     return OracleConfig(w.angles_rad, w.nx, w.ny, w.spaxel_kpc, w.tel_start, w.tel_step, w.n_tel,
                         s.log_age_nodes, s.met_nodes, s.lam_start, s.lam_step, s.flux,
                         w.psf_sigma_spx, w.lsf_sigma_A, w.z_sys, w.flux_scale,
-                        getattr(w, "log_lambda", False))
+                        getattr(w, "log_lambda", False), getattr(w, "resample", 0))
 
 
 def _p64(p, name):
@@ -327,15 +332,55 @@ def resample_linear(S: np.ndarray, q: np.ndarray, k: Optional[np.ndarray] = None
     return np.where(valid, (1.0 - tau) * s0 + tau * s1, 0.0)
 
 
+def integral_linear(S: np.ndarray, q_lo: np.ndarray, q_hi: np.ndarray) -> np.ndarray:
+    """Integral of the piecewise-linear interpolant of row i of S (in node-index units) over
+    [q_lo[i, j], q_hi[i, j]], with the interpolant zero outside [0, n-1]; FP64. Uses the exact
+    antiderivative: F(q) = C_k + S_k t + (S_{k+1} - S_k) t^2 / 2 on segment k (t = q - k), C_k
+    the trapezoid sum of segments 0..k-1, q clipped to [0, n-1]."""
+    n = S.shape[1]
+    C = np.zeros_like(S)
+    C[:, 1:] = np.cumsum(0.5 * (S[:, :-1] + S[:, 1:]), axis=1)
+
+    def F(q):
+        q = np.clip(q, 0.0, n - 1.0)
+        k = np.minimum(np.floor(q), n - 2).astype(np.int64)
+        t = q - k
+        s0 = np.take_along_axis(S, k, axis=1)
+        s1 = np.take_along_axis(S, k + 1, axis=1)
+        return np.take_along_axis(C, k, axis=1) + s0 * t + (s1 - s0) * t * t / 2.0
+
+    return F(q_hi) - F(q_lo)
+
+
+def bin_edge_indices(cfg: OracleConfig, vlos: np.ndarray):
+    """Rest-frame SSP node index of the lower and upper edge of every telescope bin (centre
+    lam_j, width dlam), shape [n, n_tel] each; linear grids."""
+    beta = np.asarray(vlos, dtype=np.float64) / C_KMS
+    f = (1.0 + cfg.z_sys) * (1.0 + beta[:, None])
+    lam = cfg.tel_lambda()[None, :]
+    lo = ((lam - 0.5 * cfg.tel_step) / f - cfg.ssp_lam_start) / cfg.ssp_lam_step
+    hi = ((lam + 0.5 * cfg.tel_step) / f - cfg.ssp_lam_start) / cfg.ssp_lam_step
+    return lo, hi
+
+
 def particle_spectra(p, idx: np.ndarray, vlos: np.ndarray, cfg: OracleConfig) -> np.ndarray:
-    """Observed spectrum of each particle in `idx` on the telescope grid, shape [len(idx), n_tel]:
-    f_i(lam_j) = flux_scale * m_i * J_i * Slin_i(q_ij), J_i = 1/((1+z_sys)(1+beta_i))."""
+    """Observed spectrum of each particle in `idx` on the telescope grid, shape [len(idx), n_tel].
+
+    resample 0: f_i(lam_j) = flux_scale m_i J_i Slin_i(q_ij), J_i = 1/((1+z_sys)(1+beta_i)).
+    resample 1: the mean of the observed flux density over bin j,
+      f_i(j) = (1/dlam) int_{bin j} flux_scale m_i J_i Slin_i(q(lam)) dlam
+             = flux_scale m_i (dlam_ssp / dlam) int_{q_lo}^{q_hi} Slin_i(q) dq
+    (the substitution lam -> q cancels J); summed over bins this conserves the flux exactly."""
     age = _p64(p, "age")[idx]
     met = _p64(p, "met")[idx]
     mass = _p64(p, "mass")[idx]
     v = vlos[idx]
     ja, jz, ta, tz, w, _, _ = ssp_weights(age, met, cfg.log_age_nodes, cfg.met_nodes)
     S = interp_templates(cfg.ssp_flux, ja, jz, w)
+    if cfg.resample == 1:
+        q_lo, q_hi = bin_edge_indices(cfg, v)
+        scale = cfg.flux_scale * mass * (cfg.ssp_lam_step / cfg.tel_step)
+        return scale[:, None] * integral_linear(S, q_lo, q_hi)
     q = doppler_index(cfg, v)
     k, valid = node_decision(cfg, v, S.shape[1])
     J = 1.0 / ((1.0 + cfg.z_sys) * (1.0 + v / C_KMS))
@@ -472,7 +517,8 @@ def loss_grad_cube(cube: np.ndarray, target: np.ndarray, cfg: OracleConfig) -> n
 def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
             idx: Optional[np.ndarray] = None, chunk: int = 512,
             workers: int = 1) -> Dict[str, np.ndarray]:
-    """Analytic gradients of L given G = dL/dC_raw, for particles `idx` (default: all).
+    """Analytic gradients of L given G = dL/dC_raw, for particles `idx` (default: all); the
+    resampling of reading 0 only.
 
     Per particle i in the field (spaxel s), with a_ic = flux_scale m_i J_i w_ic and
     X_ic = sum_j G[s, j] Tlin_c(q_ij):
@@ -486,6 +532,8 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
       dL/dphi_k = sum_i dL/dvlos_i (dR/dphi_k v_i)_z,   dL/dv_i = dL/dvlos_i R[2, :].
     Particles outside the field get zero. Positions get no gradient (binning is piecewise
     constant)."""
+    if cfg.resample != 0:
+        raise NotImplementedError("the adjoint covers the bin-centre resampling only")
     if fw is None:
         fw = forward(p, cfg, with_cube=False)
     R, key, vlos = fw["R"], fw["key"], fw["vlos"]

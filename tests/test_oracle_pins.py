@@ -19,12 +19,12 @@ pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
 
 def _cfg(nx=8, ny=8, s=1.0, angles=(0.0, 0.0, 0.0), ssp=None, tel=None, psf=0.0, lsf=0.0,
-         z_sys=0.0, flux_scale=1.0):
+         z_sys=0.0, flux_scale=1.0, resample=0):
     ssp = ssp or synth.make_ssp(6, 4, 4000.0, 2.0, 300)
     tel = tel or (ssp.lam_start, ssp.lam_step, ssp.n_lam)
     return O.OracleConfig(angles, nx, ny, s, tel[0], tel[1], tel[2], ssp.log_age_nodes,
                           ssp.met_nodes, ssp.lam_start, ssp.lam_step, ssp.flux, psf, lsf,
-                          z_sys, flux_scale, ssp.log_lambda)
+                          z_sys, flux_scale, ssp.log_lambda, resample)
 
 
 def _parts(n, seed=0, r=5.0, vmax=300.0):
@@ -338,6 +338,69 @@ def test_log_grid_line_moves_and_lsf_width():
     # the LSF width in bins is sigma / (lambda_c * step) at the grid's central wavelength
     lam_c = 5000.0 * math.exp(step * 3999 / 2)
     assert abs(cfg.lsf_sigma_bins() - 2.0 / (lam_c * step)) <= 1e-12
+
+
+# bin-average resampling (flux conserving), linear grids
+def _bin_avg(ssp, tel, v, z_sys=0.0, mass=1.0, flux_scale=1.0):
+    cfg = _cfg(ssp=ssp, tel=tel, z_sys=z_sys, flux_scale=flux_scale, resample=1)
+    return cfg, O.particle_spectra(_single(mass=mass, vlos=v), np.array([0]), np.array([v]),
+                                   cfg)[0]
+
+
+def test_bin_average_matches_midpoint_quadrature():
+    """Brute force: the mean of the observed flux density over each bin by a 4000-point midpoint
+    rule on f_obs(lam) = fs m J np.interp(lam / ((1+z)(1+beta)), lam_ssp, S, 0, 0)."""
+    ssp = synth.make_ssp(5, 3, 4000.0, 2.0, 200)
+    tel = (4011.3, 2.7, 150)
+    v, z, m, fs = 333.0, 0.004, 2.5, 0.7
+    cfg, f = _bin_avg(ssp, tel, v, z, m, fs)
+    p = _single(mass=m, vlos=v)
+    ja, jz, ta, tz, w, _, _ = O.ssp_weights(p.age, p.met, cfg.log_age_nodes, cfg.met_nodes)
+    S = O.interp_templates(cfg.ssp_flux, ja, jz, w)[0]
+    fac = (1 + z) * (1 + v / O.C_KMS)
+    u = (np.arange(4000) + 0.5) / 4000.0 - 0.5
+    for j in (0, 1, 40, 77, 149):
+        lam = tel[0] + j * tel[1] + u * tel[1]
+        ref = fs * m / fac * np.interp(lam / fac, ssp.lam(), S, left=0.0, right=0.0).mean()
+        assert abs(f[j] - ref) <= 1e-6 * abs(ref), (j, f[j], ref)
+
+
+def test_bin_average_at_rest_on_identical_grids():
+    """Bin j covers node indices [j - 1/2, j + 1/2]: mean = (S[j-1] + 6 S[j] + S[j+1]) / 8."""
+    ssp = synth.make_ssp(5, 3, 4000.0, 2.0, 200)
+    cfg, f = _bin_avg(ssp, None, 0.0, mass=1.0)
+    p = _single(mass=1.0)
+    ja, jz, ta, tz, w, _, _ = O.ssp_weights(p.age, p.met, cfg.log_age_nodes, cfg.met_nodes)
+    S = O.interp_templates(cfg.ssp_flux, ja, jz, w)[0]
+    ref = (S[:-2] + 6 * S[1:-1] + S[2:]) / 8
+    np.testing.assert_allclose(f[1:-1], ref, rtol=1e-12)
+    # the two end bins lose the half-segment outside the grid
+    np.testing.assert_allclose(f[0], (3 * S[0] + S[1]) / 8, rtol=1e-12)
+
+
+def test_bin_average_conserves_flux_exactly():
+    """For a line inside the band, sum_j f_j dlam = fs m dlam_ssp int Slin dq for every shift
+    (reading 0 conserves it only to O(beta))."""
+    ssp = synth.make_line_ssp(5000.0, 1.0, 2000, 6000.0, 3.0)
+    S = ssp.flux[0, 0].astype(np.float64)
+    total = 1.0 * np.sum(0.5 * (S[:-1] + S[1:]))                 # dlam_ssp * trapezoid sum
+    for tel in (None, (5003.7, 1.3, 1500), (4990.2, 0.8, 2600)):
+        for v in (-600.0, -150.0, 0.0, 40.0, 600.0):
+            cfg, f = _bin_avg(ssp, tel, v)
+            assert abs(f.sum() * cfg.tel_step - total) <= 1e-12 * total, (tel, v)
+
+
+def test_bin_average_of_a_constant_and_reading_check():
+    """A constant spectrum c gives J c in every bin inside the band; the bin-average reading is
+    refused on log grids."""
+    ssp = synth.make_line_ssp(5000.0, 1.0, 400, 5200.0, 3.0)
+    ssp.flux = np.full_like(ssp.flux, 2.0)
+    v = 500.0
+    cfg, f = _bin_avg(ssp, (5050.3, 1.7, 150), v, mass=3.0)
+    np.testing.assert_allclose(f, 3.0 * 2.0 / (1 + v / O.C_KMS), rtol=1e-12)
+    log_ssp = synth.make_ssp(3, 3, 4000.0, 1e-4, 50, log_lambda=True)
+    with pytest.raises(ValueError):
+        _cfg(ssp=log_ssp, resample=1)
 
 
 def test_out_of_band_is_zero_and_last_node_is_included():
