@@ -175,6 +175,10 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 1 GiB device to device once (a known-size kernel "
                          "for calibrating profiler byte counters)")
+    ap.add_argument("--variant", choices=("centre", "binmean", "loglam"), default="centre",
+                    help="resampling reading / grid kind of the forward step: bin-centre sampling "
+                         "on linear grids (default, the headline), bin mean (flux conserving), "
+                         "or grids uniform in ln(lambda)")
     ap.add_argument("--serve", action="store_true",
                     help="print the serving report (request stream, batched graph path vs "
                          "one-at-a-time plain launches) instead of the forward-step line")
@@ -198,8 +202,13 @@ def main():
     import torch
     from paper_2412_08265_amd import ops, synth
 
-    err("generating the 1e7-particle workload")
-    w = synth.large_workload(n=args.n)
+    err(f"generating the 1e7-particle workload ({args.variant})")
+    if args.variant == "loglam":
+        w = synth.large_log_workload(n=args.n)
+    else:
+        w = synth.large_workload(n=args.n)
+        if args.variant == "binmean":
+            w.resample = 1
     dev = "cuda"
     gal = ops.DeviceGalaxy.from_host(w.particles, dev)
     ssp = ops.DeviceSSP.from_grid(w.ssp, dev)
@@ -239,7 +248,7 @@ def main():
     units = n_in * w.n_tel
     achieved = CUBE_FLOP_PER_UNIT * units / (cube_kernel_ms * 1e-3) / 1e12
     digest = source_digest("k_cube.hip")
-    traffic = traffic_from_profile(digest)
+    traffic = traffic_from_profile(digest) if args.variant == "centre" else None
     rot_gbs = ROTBIN_BYTES_PER_PARTICLE * w.particles.n / (st[0] * 1e-3) / 1e9
     psf_gbs = PSF_BYTES_PER_VOXEL * w.n_spaxels * w.n_tel / (st[2] * 1e-3) / 1e9
     out = {
@@ -255,14 +264,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded disk+bulge galaxy and SSP grid)",
-        "config": {"workload": (f"disk+bulge-{w.particles.n:.0e}: {w.particles.n} particles "
+        "config": {"workload": (f"{w.name}{'' if args.variant == 'centre' else ' ' + args.variant}: "
+                                f"{w.particles.n} particles "
                                 f"({n_in} in field), {w.nx}x{w.ny} spaxels of {w.spaxel_kpc} kpc, "
-                                f"{w.n_tel} bins of {w.tel_step} A from {w.tel_start} A, SSP "
+                                f"{w.n_tel} bins of {w.tel_step} "
+                                f"{'ln(A)' if w.log_lambda else 'A'} from {w.tel_start} A, SSP "
                                 f"{w.ssp.n_age}x{w.ssp.n_met}x{w.ssp.n_lam}, PSF {w.psf_sigma_spx} "
                                 f"spx, LSF {w.lsf_sigma_A} A"),
                    "particles": w.particles.n, "in_field": n_in, "spaxels": w.n_spaxels,
-                   "bins": w.n_tel, "parallelism": "none (1 GPU)"},
-        "roofline": {"bound": "alu", "kernel": "k_cube",
+                   "bins": w.n_tel, "resampling": "bin mean" if w.resample else "bin centre",
+                   "grids": "log-lambda" if w.log_lambda else "linear",
+                   "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "alu", "kernel": "k_cube_bin" if w.resample else "k_cube",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
                      "flop_per_unit": CUBE_FLOP_PER_UNIT, "units_per_launch": units,

@@ -106,6 +106,9 @@ typedef struct {
   float      *vlos;             /* [n]           written by rubix_rotate_bin                   */
   float      *cube_raw;         /* [ny][nx][tel.n] written by rubix_cube                       */
   float      *cube;             /* [ny][nx][tel.n] optional; rubix_psf_lsf may write it        */
+  int32_t     resample;         /* 0: bin-centre sampling (below); 1: bin mean (flux conserving,
+                                   linear grids only; no adjoint)                               */
+  int32_t     reserved;         /* 0                                                            */
 } rubix_job;
 
 /* Bytes of workspace that every entry point below needs for these jobs (the maximum over all
@@ -135,7 +138,12 @@ int rubix_rotate_bin(const rubix_job *jobs, int n_jobs, void *ws, size_t ws_byte
  *  - Doppler + resampling: f_i(lam_j) = flux_scale m_i J_i Slin_i(q_ij) with
  *    q_ij = (lam_j / ((1+z_sys)(1+beta_i)) - lam0_ssp) / dlam_ssp, beta_i = vlos_i / c,
  *    J_i = 1/((1+z_sys)(1+beta_i)) (flux-density Jacobian), Slin the linear interpolant of the
- *    bilinear SSP spectrum between wavelength nodes, 0 for q < 0 or q > n-1.
+ *    bilinear SSP spectrum between wavelength nodes, 0 for q < 0 or q > n-1 (resample = 0; on
+ *    log-spaced grids q_ij = Q_j - ln(1+beta_i)/dln_ssp).
+ *    resample = 1 (linear grids): the mean of the observed flux density over bin j,
+ *    f_i(j) = flux_scale m_i (dlam_ssp / tel.step) * integral of Slin_i over the rest-frame node
+ *    interval [q_ij(lam_j - step/2), q_ij(lam_j + step/2)] (exact for the piecewise-linear
+ *    spectrum; the sum over bins conserves the flux of any shift inside the band).
  *  - cube_raw[s][j] = sum of f_i(lam_j) over the particles of spaxel s, FP32, accumulated per
  *    work item in a fixed order (deterministic; independent of the other jobs in the batch). */
 int rubix_cube(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, void *ws,
@@ -232,8 +240,9 @@ int rubix_graph_destroy(rubix_graph g);
 
 /* ---- Measurement aid -------------------------------------------------------------------------
  * rubix_cube_timer(1) makes the following rubix_cube calls on this thread record a HIP event pair
- * on their stream right before and right after the cube-summation kernel (the step that sums
- * the resampled spectra; rubix_cube also runs short preparation and combine kernels around it).
+ * on their stream right before and right after the cube-summation kernels (the step that sums
+ * the resampled spectra, bin-centre and bin-mean jobs; rubix_cube also runs short preparation
+ * and combine kernels around it).
  * rubix_cube_timer(0) stops recording. rubix_cube_timer_read waits for every pair recorded since
  * the last read, returns their summed elapsed time in ms and their count, and releases them.
  * The pairs are library state (HIP events), held until read. Graph launches are never timed. */

@@ -46,7 +46,8 @@ class RubixJob(ctypes.Structure):
                 ("tel", RubixLGrid), ("z_sys", c_double), ("flux_scale", c_double),
                 ("psf_sigma_spx", c_double), ("lsf_sigma_A", c_double),
                 ("key", c_void_p), ("perm", c_void_p), ("seg_off", c_void_p),
-                ("vlos", c_void_p), ("cube_raw", c_void_p), ("cube", c_void_p)]
+                ("vlos", c_void_p), ("cube_raw", c_void_p), ("cube", c_void_p),
+                ("resample", c_int32), ("reserved", c_int32)]
 
 
 EXPORTS = ("rubix_workspace_size", "rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf",

@@ -95,7 +95,10 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__
     const double beta = v / kCkms;
     const double opz = 1.0 + J.z_sys;
     const double jac = 1.0 / (opz * (1.0 + beta));
-    const double scale = mode == 0 ? J.flux_scale * m * jac : 1.0;
+    // forward weights: flux_scale m J for bin-centre sampling; for the bin mean the Jacobian
+    // cancels against the change of variable lambda -> node index, leaving dlam_ssp/dlam_tel
+    const double scale = mode != 0 ? 1.0
+                         : J.resample ? J.flux_scale * m * J.bin_scale : J.flux_scale * m * jac;
     PrepRec r;
     r.row = (ja * S.n_met + jz) * S.n_lam;
     bool fits;
@@ -485,6 +488,126 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Bin-mean resampling (flux conserving): cube_raw[s][j] = sum over the spaxel's particles of
+//   a_i . integral of the particle's piecewise-linear spectrum over the rest-frame node interval
+//   [q_lo, q_hi] of bin j (a_i = corner weights x flux_scale m dlam_ssp/dlam_tel),
+// with the interval clipped to [0, n-1] (the spectrum is zero outside the grid). On a node
+// segment k the integral from fraction x to y is S_k (y - x) + (S_{k+1} - S_k)(y^2 - x^2)/2.
+// Work items as k_cube's, on tiles of kBinTL bins: each wave owns kBinWaveBins bins and stages
+// the particle's spectrum at 64 consecutive nodes n0 .. n0+63 in its LDS slot (n0 = lane 0's
+// clipped lower node), which covers every lane's interval when the bins span at most 63 nodes
+// and no bin spans more than two segments; otherwise the particle's segments are gathered from
+// the template grid directly (both cases give the same sum of the same terms).
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ float seg_integral(float s0, float s1, float x, float y) {
+  return fmaf(s0, y - x, 0.5f * (s1 - s0) * (y * y - x * x));
+}
+
+// Node interval and fraction of an edge, clipped to [0, n-1] as (k, t) with k in [0, n-2].
+__device__ __forceinline__ void clip_node(int &k, float &t, int nl) {
+  if (k < 0) { k = 0; t = 0.f; }
+  else if (k > nl - 2) { k = nl - 2; t = 1.f; }
+}
+
+__device__ __forceinline__ void edge_index(const JobDev &J, const SspDev &S, double lam, int &qi,
+                                           float &qf, float &lamf) {
+  const double Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
+  const double Qfl = floor(Q);
+  qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
+  qf = (float)(Q - Qfl);
+  lamf = (float)lam;
+}
+
+__global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restrict__ T) {
+  __shared__ float slots[kCubeThreads / 64][64];
+  const SspDev &S = T->h.ssp;
+  const JobDev *jobs = table_jobs(T);
+  const __amdgpu_buffer_rsrc_t rs = flux_rsrc(S);
+  const int nl = S.n_lam;
+  const int o1 = nl, o2 = S.n_met * nl, o3 = o2 + nl;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float *wslot = slots[w];
+  const uint32_t lb[4] = {(uint32_t)lane * 4u, (uint32_t)(lane + o1) * 4u,
+                          (uint32_t)(lane + o2) * 4u, (uint32_t)(lane + o3) * 4u};
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_CUBEB]; vb += gridDim.x) {
+    const int jj = find_job(T, K_CUBEB, vb);
+    const JobDev &J = jobs[jj];
+    const int64_t local = vb - J.vb_start[K_CUBEB];
+    const int tile = (int)(local / J.n_chunk_ub);
+    const int c = (int)(local - (int64_t)tile * J.n_chunk_ub);
+    if (c >= ((CInt *)J.counts)[0]) continue;
+    const int jw = tile * kBinTL + w * kBinWaveBins;
+    if (jw >= J.n_tel) continue;                           // wave-uniform
+    CInt *chp = (CInt *)(J.chunks + c);
+    const ChunkRec ch{chp[0], chp[1], chp[2], chp[3]};
+    const int jb = jw + lane;
+    const bool act = (lane < kBinWaveBins) && (jb < J.n_tel);
+    // lanes past the wave's bins take its last bin, so the node span stays that of the bins
+    const int jc = min(jw + min(lane, kBinWaveBins - 1), J.n_tel - 1);
+    const double lam = J.tel_start + (double)jc * J.tel_step;
+    int qlo, qhi;
+    float flo, fhi, llo, lhi;
+    edge_index(J, S, lam - 0.5 * J.tel_step, qlo, flo, llo);
+    edge_index(J, S, lam + 0.5 * J.tel_step, qhi, fhi, lhi);
+    const PrepRec *prep = J.prep;
+    float acc = 0.f, tot = 0.f;
+    int since = 0;
+    for (int p = ch.p0; p < ch.p1; ++p) {
+      const PrepRec r = load_rec(prep + p);
+      const int row = prep_row(r.row);
+      const float tl = fmaf(-llo, r.g, flo), th = fmaf(-lhi, r.g, fhi);
+      int klo = qlo + floor_i32(tl), khi = qhi + floor_i32(th);
+      float a = __builtin_amdgcn_fractf(tl), b = __builtin_amdgcn_fractf(th);
+      clip_node(klo, a, nl);
+      clip_node(khi, b, nl);
+      const bool empty = (klo > khi) || (klo == khi && !(a < b));
+      const int n0 = __builtin_amdgcn_readfirstlane(klo);
+      const int nmax = __builtin_amdgcn_readlane(khi, 63) + 1;    // last bin's upper node
+      const bool two = !empty && (khi - klo > 1);
+      const bool window = (nmax - n0 <= 63) && !__builtin_amdgcn_ballot_w64(two);
+      float v = 0.f;
+      if (window) {
+        const uint32_t so = (uint32_t)(row + n0) * 4u;
+        float Sv = r.a[0] * ldf(rs, lb[0], so);
+        Sv = fmaf(r.a[1], ldf(rs, lb[1], so), Sv);
+        Sv = fmaf(r.a[2], ldf(rs, lb[2], so), Sv);
+        Sv = fmaf(r.a[3], ldf(rs, lb[3], so), Sv);
+        wslot[lane] = Sv;
+        __builtin_amdgcn_wave_barrier();
+        const int i0 = min(max(klo - n0, 0), 62);
+        const float s0 = wslot[i0], s1 = wslot[i0 + 1], s2 = wslot[min(i0 + 2, 63)];
+        __builtin_amdgcn_wave_barrier();
+        if (!empty)
+          v = (khi == klo) ? seg_integral(s0, s1, a, b)
+                           : seg_integral(s0, s1, a, 1.f) + seg_integral(s1, s2, 0.f, b);
+      } else if (!empty) {
+        // any number of segments, gathered from the template grid
+        for (int k = klo; k <= khi; ++k) {
+          const uint32_t e = (uint32_t)(row + k) * 4u;
+          const uint32_t b1 = (uint32_t)o1 * 4u, b2 = (uint32_t)o2 * 4u, b3 = (uint32_t)o3 * 4u;
+          float s0 = r.a[0] * ldf(rs, e, 0);
+          s0 = fmaf(r.a[1], ldf(rs, e + b1, 0), s0);
+          s0 = fmaf(r.a[2], ldf(rs, e + b2, 0), s0);
+          s0 = fmaf(r.a[3], ldf(rs, e + b3, 0), s0);
+          float s1 = r.a[0] * ldf(rs, e + 4u, 0);
+          s1 = fmaf(r.a[1], ldf(rs, e + b1 + 4u, 0), s1);
+          s1 = fmaf(r.a[2], ldf(rs, e + b2 + 4u, 0), s1);
+          s1 = fmaf(r.a[3], ldf(rs, e + b3 + 4u, 0), s1);
+          v += seg_integral(s0, s1, k == klo ? a : 0.f, k == khi ? b : 1.f);
+        }
+      }
+      acc += v;
+      if (++since == kCubeSubsum) { tot += acc; acc = 0.f; since = 0; }
+    }
+    tot += acc;
+    if (act) {
+      if (ch.slot < 0) J.cube_raw[(int64_t)ch.s * J.n_tel + jb] = tot;
+      else J.partial[(int64_t)ch.slot * J.n_tel + jb] = tot;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kCubeThreads) void k_combine(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_COMB]; vb += gridDim.x) {
@@ -522,12 +645,14 @@ hipError_t launch_cube(const Table *dt, const TableHeader &h, int cap, hipStream
     hipLaunchKernelGGL(k_vbound, dim3(g), dim3(256), 0, s, dt);
   if ((g = grid_for(h.total[K_PREP], cap)))
     hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, 0);
-  if ((g = grid_for(h.total[K_CUBE], cap))) {
-    const bool timed = t_cube_events[0] && t_cube_events[1];
-    if (timed) (void)hipEventRecord(t_cube_events[0], s);
+  // the summation kernels (bin-centre and bin-mean jobs), timed together when requested
+  const bool timed = t_cube_events[0] && t_cube_events[1];
+  if (timed) (void)hipEventRecord(t_cube_events[0], s);
+  if ((g = grid_for(h.total[K_CUBE], cap)))
     hipLaunchKernelGGL(k_cube, dim3(g), dim3(kCubeThreads), 0, s, dt);
-    if (timed) (void)hipEventRecord(t_cube_events[1], s);
-  }
+  if ((g = grid_for(h.total[K_CUBEB], cap)))
+    hipLaunchKernelGGL(k_cube_bin, dim3(g), dim3(kCubeThreads), 0, s, dt);
+  if (timed) (void)hipEventRecord(t_cube_events[1], s);
   if ((g = grid_for(h.total[K_COMB], cap)))
     hipLaunchKernelGGL(k_combine, dim3(g), dim3(kCubeThreads), 0, s, dt);
   return hipGetLastError();
@@ -545,6 +670,7 @@ int cube_kernel_kind(const void *f) {
   if (f == (const void *)k_prep) return K_PREP;
   if (f == (const void *)k_chunks) return K_CHUNK;
   if (f == (const void *)k_vbound) return K_VB;
+  if (f == (const void *)k_cube_bin) return K_CUBEB;
   if (f == (const void *)k_cube) return K_CUBE;
   if (f == (const void *)k_combine) return K_COMB;
   return -1;

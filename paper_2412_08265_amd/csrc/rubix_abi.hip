@@ -71,7 +71,7 @@ enum Call { CALL_ROTATE, CALL_CUBE, CALL_PSF, CALL_BWD, CALL_SIZE, CALL_PACK };
 
 struct JobSizes {
   int64_t n, n_s, n_tel, cube_elems;
-  int passes, n_sort_tiles, n_tiles, n_chunk_ub, n_comb_ub, n_slot_ub;
+  int passes, n_sort_tiles, n_tiles, n_tiles_b, n_chunk_ub, n_comb_ub, n_slot_ub;
   int lsf_r, psf_r, n_psf_tiles, n_psf_seg_y, n_psf_seg_x, n_fin_blocks;
   double lsf_sigma_bins;
   // byte offsets inside the job's workspace region
@@ -104,6 +104,7 @@ static JobSizes sizes_of(const rubix_job &j) {
   z.passes = std::max(1, (bits + 7) / 8);
   z.n_sort_tiles = (int)cdiv(z.n, kSortTile);
   z.n_tiles = (int)cdiv(z.n_tel, kCubeTL);
+  z.n_tiles_b = (int)cdiv(z.n_tel, kBinTL);
   z.n_chunk_ub = (int)(z.n_s + cdiv(z.n, kCubeChunk));
   z.n_comb_ub = z.n > kCubeChunk ? (int)(z.n / (kCubeChunk + 1) + 1) : 0;
   z.n_slot_ub = (int)(2 * cdiv(z.n, kCubeChunk) + 2);
@@ -195,6 +196,12 @@ static int validate_jobs(const rubix_job *jobs, int n_jobs, Call call) {
       return fail(RUBIX_EINVAL, "job %d: tel.log_spaced must be 0 or 1", k);
     if (j.tel.log_spaced && !finite_pos(j.tel.start))
       return fail(RUBIX_EINVAL, "job %d: a log-spaced telescope grid needs start > 0", k);
+    if (j.resample != 0 && j.resample != 1)
+      return fail(RUBIX_EINVAL, "job %d: resample must be 0 or 1", k);
+    if (j.resample == 1 && j.tel.log_spaced)
+      return fail(RUBIX_EINVAL, "job %d: bin-mean resampling needs linear grids", k);
+    if (j.resample == 1 && call == CALL_BWD)
+      return fail(RUBIX_EINVAL, "job %d: no adjoint for bin-mean resampling", k);
     if (!(j.z_sys > -1.0) || !isfinite(j.z_sys)) return fail(RUBIX_EINVAL, "job %d: z_sys must be > -1", k);
     if (!isfinite(j.flux_scale)) return fail(RUBIX_EINVAL, "job %d: flux_scale not finite", k);
     for (int a = 0; a < 3; ++a)
@@ -340,6 +347,9 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
     gauss_weights(j.psf_sigma_spx, z.psf_r, d.psf_w);
     d.n_tel = (int32_t)z.n_tel; d.passes = z.passes; d.n_sort_tiles = z.n_sort_tiles; d.n_tiles = z.n_tiles;
     d.log_lambda = j.tel.log_spaced;
+    d.resample = j.resample;
+    d.n_tiles_b = z.n_tiles_b;
+    d.bin_scale = ssp ? ssp->lam.step / j.tel.step : 1.0;
     if (ssp && j.tel.log_spaced) {
       // node index of bin j at rest: q_off + j q_ratio (exact when the two grids coincide)
       d.q_off = ((log(j.tel.start) - log(ssp->lam.start)) - log1p(j.z_sys)) / ssp->lam.step;
@@ -415,7 +425,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
         /*K_SEG*/ cdiv(z.n_s + 1, 256),
         /*K_PREP*/ cdiv(z.n, kPrepThreads),
         /*K_CHUNK*/ 1,
-        /*K_CUBE*/ (int64_t)z.n_tiles * z.n_chunk_ub,
+        /*K_CUBE*/ j.resample ? 0 : (int64_t)z.n_tiles * z.n_chunk_ub,
         /*K_COMB*/ (int64_t)z.n_tiles * z.n_comb_ub,
         /*K_LSF*/ n_lsf,
         /*K_PSFY*/ n_psfy,
@@ -426,6 +436,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
         /*K_FIN*/ z.n_fin_blocks,
         /*K_ANG*/ 1,
         /*K_VB*/ cdiv(z.n, kVbParticles),
+        /*K_CUBEB*/ j.resample ? (int64_t)z.n_tiles_b * z.n_chunk_ub : 0,
     };
     for (int q = 0; q < NK; ++q) {
       d.vb_start[q] = start[q];
@@ -721,7 +732,7 @@ int rubix_graph_create(const void *dev_table, int max_jobs, int max_psf_radius,
     g->kinds.push_back(kind);
   }
   if (e != hipSuccess) { graph_free(g); return device_status(e, "graph kernel nodes"); }
-  const size_t expect = 3u * max_sort_passes + 2 + 5 + 4;
+  const size_t expect = 3u * max_sort_passes + 2 + 6 + 4;
   if (g->nodes.size() != expect) {
     const size_t got = g->nodes.size();
     graph_free(g);

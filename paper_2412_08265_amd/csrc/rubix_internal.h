@@ -22,6 +22,8 @@ constexpr int kCubeWaveBins = 62;   // telescope bins per wave; its 64 lanes sta
 constexpr int kCubeTL = 4 * kCubeWaveBins;  // telescope bins per cube tile
 constexpr int kCubeGroup = 4;       // particles staged per wave at once (their loads overlap)
 constexpr int kCubeChunk = 2048;    // max particles per cube work item
+constexpr int kBinWaveBins = 60;    // bin-mean kernel: telescope bins per wave
+constexpr int kBinTL = 4 * kBinWaveBins;
 constexpr int kCubeSubsum = 256;    // particles per inner FP32 partial sum
 constexpr int kWPad = 4;            // zero weights before a padded filter
 constexpr int kWArray = 2 * RUBIX_MAX_RADIUS + 1 + 16;   // padded filter array (zeros after)
@@ -49,6 +51,7 @@ enum Kind : int {
   K_FIN,       // per kFinThreads sorted particles
   K_ANG,       // one per job
   K_VB,        // per kVbParticles particles (Doppler bounds for the cube kernel)
+  K_CUBEB,     // per (lambda tile of kBinTL bins, chunk slot): bin-mean resampling jobs
   NK
 };
 
@@ -101,6 +104,8 @@ struct JobDev {
   int32_t cube_direct, log_lambda;                   // 1 = gather taps from global (coarse grids);
                                                      // 1 = both grids uniform in ln(lambda)
   double q_off, q_ratio;  // log grids: rest-frame node index of bin j is q_off + j * q_ratio
+  int32_t resample, n_tiles_b;  // 1 = bin-mean resampling; its tiles of kBinTL bins
+  double bin_scale;             // bin mean: dlam_ssp / dlam_tel
   double bin_slope;                                  // d(node index)/d(bin) at rest
   int32_t n_chunk_ub, n_comb_ub, lsf_r, psf_r;
   int32_t n_psf_tiles, n_psf_seg_y, n_psf_seg_x, n_fin_blocks;

@@ -96,12 +96,13 @@ class Observation:
     z_sys: float = 0.0
     flux_scale: float = 1.0
     log_lambda: bool = False     # telescope bins tel_start * exp(k * tel_step)
+    resample: int = 0            # 0 bin-centre sampling, 1 bin mean (flux conserving)
 
     @classmethod
     def from_workload(cls, w) -> "Observation":
         return cls(tuple(w.angles_rad), w.nx, w.ny, w.spaxel_kpc, w.tel_start, w.tel_step,
                    w.n_tel, w.psf_sigma_spx, w.lsf_sigma_A, w.z_sys, w.flux_scale,
-                   bool(getattr(w, "log_lambda", False)))
+                   bool(getattr(w, "log_lambda", False)), int(getattr(w, "resample", 0)))
 
     @property
     def n_spaxels(self):
@@ -138,6 +139,7 @@ def make_job(gal: DeviceGalaxy, obs: Observation, buf: JobBuffers) -> RubixJob:
                        int(obs.log_lambda))
     j.z_sys, j.flux_scale = float(obs.z_sys), float(obs.flux_scale)
     j.psf_sigma_spx, j.lsf_sigma_A = float(obs.psf_sigma_spx), float(obs.lsf_sigma_A)
+    j.resample = int(obs.resample)
     j.key, j.perm, j.seg_off = buf.key.data_ptr(), buf.perm.data_ptr(), buf.seg_off.data_ptr()
     j.vlos, j.cube_raw, j.cube = buf.vlos.data_ptr(), buf.cube_raw.data_ptr(), buf.cube.data_ptr()
     return j

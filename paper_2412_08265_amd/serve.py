@@ -235,6 +235,7 @@ def _size_job(req: Request) -> RubixJob:
     j.grid = RubixGrid(int(o.nx), int(o.ny), float(o.spaxel_kpc))
     j.tel = RubixLGrid(float(o.tel_start), float(o.tel_step), int(o.n_tel), int(o.log_lambda))
     j.psf_sigma_spx, j.lsf_sigma_A = float(o.psf_sigma_spx), float(o.lsf_sigma_A)
+    j.resample = int(o.resample)
     return j
 
 

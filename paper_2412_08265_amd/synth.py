@@ -244,6 +244,7 @@ class Workload:
     z_sys: float = 0.0
     flux_scale: float = 1.0
     log_lambda: bool = False     # telescope bins tel_start * exp(k * tel_step) (as the SSP grid)
+    resample: int = 0            # 0 bin-centre sampling, 1 bin mean (flux conserving)
 
     @property
     def angles_rad(self):
@@ -294,6 +295,17 @@ def log_workload(seed=5, n=200_000) -> Workload:
     return Workload("loglam-2e5", p, (60.0, 0.0, 0.0), 30, 30, 1.0,
                     3600.0 * math.exp(0.37 * 1.2e-4), 1.0e-4, 3300, ssp, psf_sigma_spx=1.0,
                     lsf_sigma_A=1.2, z_sys=0.002, log_lambda=True)
+
+
+def large_log_workload(seed=3, n=10_000_000, spaxel_kpc=0.2) -> Workload:
+    """The 1e7-particle galaxy on grids uniform in ln(lambda): 4563 SSP nodes and telescope bins
+    from 4700 A with dln = 1.6e-4 (48 km/s per bin; 4700-9763 A), SSP 106x12, PSF 2 spx,
+    LSF 2.7 A at the central wavelength."""
+    p = make_galaxy(n, seed)
+    ssp = cached_ssp(106, 12, 4700.0, 1.6e-4, 4563, log_lambda=True)
+    return Workload("disk+bulge-1e7-loglam", p, (60.0, 0.0, 0.0), 150, 150, spaxel_kpc,
+                    4700.0, 1.6e-4, 4563, ssp, psf_sigma_spx=2.0, lsf_sigma_A=2.7,
+                    log_lambda=True)
 
 
 def large_workload(seed=3, n=10_000_000, spaxel_kpc=0.2) -> Workload:

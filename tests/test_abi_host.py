@@ -189,6 +189,25 @@ def test_wavelength_grid_kinds_are_validated(lib):
     assert _ws_size(lib, [j])[0] == _lib.RUBIX_EINVAL
 
 
+def test_resample_mode_is_validated(lib):
+    from paper_2412_08265_amd import _lib
+    j = _job()
+    j.resample = 1
+    assert _ws_size(lib, [j])[0] == _lib.RUBIX_OK
+    j.resample = 2
+    assert _ws_size(lib, [j])[0] == _lib.RUBIX_EINVAL
+    j.resample = 1
+    j.tel.log_spaced = 1                         # bin mean on a log grid
+    assert _ws_size(lib, [j])[0] == _lib.RUBIX_EINVAL
+    j.tel.log_spaced = 0
+    ssp, keep = _ssp_c([-1, 0, 1], [-2, 0])
+    ptrs = (ctypes.c_void_p * 1)(0x1000)
+    # the adjoint refuses bin-mean jobs before any device work
+    rc = lib.rubix_cube_backward(_arr(j), 1, ctypes.byref(ssp), ptrs, ptrs, ptrs, ptrs, ptrs,
+                                 None, 0x1000, 0x1000, 1 << 40, None)
+    assert rc == _lib.RUBIX_EINVAL and b"bin-mean" in lib.rubix_last_error()
+
+
 def test_product_path_never_touches_the_oracle():
     """The HIP package and its binding import nothing from the oracle (and vice versa)."""
     pkg = os.path.join(ROOT, "paper_2412_08265_amd")
