@@ -174,6 +174,25 @@ int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
                         float *const *d_vel, double *d_angles, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* Noise (Sec. 3 ends with realistic noise; the paper gives no model). Reading taken: every voxel
+ * v of the cube gets independent Gaussian noise of variance gain * max(C_v, 0) + sigma_floor^2.
+ * The deviate of voxel v (C order in [ny][nx][tel.n]) is eps = sqrt(-2 ln u0) cos(2 pi u1) with
+ * u = (x + 1/2) 2^-32 from the first two outputs x0, x1 of Philox-4x32-10 (Salmon et al., SC
+ * 2011) keyed by `seed` (low word first) with counter (v_lo, v_hi, stream, 0), in FP64; the
+ * noisy value is rounded to FP32 once. It depends only on (seed, stream, v, C_v). */
+typedef struct {
+  uint64_t seed;
+  uint32_t stream;        /* independent sequences for one seed (e.g. one per observation)     */
+  uint32_t reserved;      /* 0                                                                  */
+  double   gain;          /* noise variance per unit of cube value, >= 0                       */
+  double   sigma_floor;   /* standard deviation of the floor, >= 0                             */
+} rubix_noise;
+
+/* Adds noise in place to cubes[k] (DEVICE, the shape of jobs[k]) with noise[k] (HOST array of
+ * n_jobs). Only the jobs' grid and tel.n are read. No workspace. */
+int rubix_add_noise(const rubix_job *jobs, int n_jobs, const rubix_noise *noise,
+                    float *const *cubes, void *stream);
+
 /* ---- Batched forward pass for replayed launches (serving) -----------------------------------
  * The calls above upload their job table through kernel arguments. For a serving loop that
  * replays one captured launch sequence (a HIP graph) for every batch, the table instead lives in

@@ -41,6 +41,11 @@ class RubixParticles(ctypes.Structure):
                                    ("x", "y", "z", "vx", "vy", "vz", "mass", "age", "met")]
 
 
+class RubixNoise(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("stream", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("gain", c_double), ("sigma_floor", c_double)]
+
+
 class RubixJob(ctypes.Structure):
     _fields_ = [("p", RubixParticles), ("angles_rad", c_double * 3), ("grid", RubixGrid),
                 ("tel", RubixLGrid), ("z_sys", c_double), ("flux_scale", c_double),
@@ -54,7 +59,7 @@ EXPORTS = ("rubix_workspace_size", "rubix_rotate_bin", "rubix_cube", "rubix_psf_
            "rubix_cube_backward", "rubix_last_error", "rubix_version", "rubix_table_bytes",
            "rubix_forward_pack", "rubix_forward_packed", "rubix_graph_create",
            "rubix_graph_launch", "rubix_graph_destroy", "rubix_cube_timer",
-           "rubix_cube_timer_read")
+           "rubix_cube_timer_read", "rubix_add_noise")
 
 _lib = None
 
@@ -93,12 +98,14 @@ def load() -> ctypes.CDLL:
     lib.rubix_graph_create.argtypes = [c_void_p, c_int, c_int, c_int, POINTER(c_void_p)]
     lib.rubix_graph_launch.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
     lib.rubix_graph_destroy.argtypes = [c_void_p]
+    lib.rubix_add_noise.argtypes = [POINTER(RubixJob), c_int, POINTER(RubixNoise),
+                                    POINTER(c_void_p), c_void_p]
     lib.rubix_cube_timer.argtypes = [c_int]
     lib.rubix_cube_timer_read.argtypes = [POINTER(c_double), POINTER(c_int)]
     for f in ("rubix_workspace_size", "rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf",
               "rubix_cube_backward", "rubix_forward_pack", "rubix_forward_packed",
               "rubix_graph_create", "rubix_graph_launch", "rubix_graph_destroy",
-              "rubix_cube_timer", "rubix_cube_timer_read"):
+              "rubix_cube_timer", "rubix_cube_timer_read", "rubix_add_noise"):
         getattr(lib, f).restype = c_int
     lib.rubix_last_error.restype = ctypes.c_char_p
     lib.rubix_version.restype = ctypes.c_char_p

@@ -591,6 +591,30 @@ int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
   return run(tab, ws, static_cast<hipStream_t>(stream), launch_backward, "rubix_cube_backward");
 }
 
+int rubix_add_noise(const rubix_job *jobs, int n_jobs, const rubix_noise *noise,
+                    float *const *cubes, void *stream) {
+  g_err.clear();
+  if (!jobs || !noise || !cubes) return fail(RUBIX_EINVAL, "jobs/noise/cubes is NULL");
+  if (n_jobs < 1 || n_jobs > RUBIX_MAX_JOBS)
+    return fail(RUBIX_EINVAL, "n_jobs=%d outside [1, %d]", n_jobs, RUBIX_MAX_JOBS);
+  for (int k = 0; k < n_jobs; ++k) {
+    const rubix_noise &p = noise[k];
+    if (!cubes[k]) return fail(RUBIX_EINVAL, "job %d: cube is NULL", k);
+    if (jobs[k].grid.nx < 1 || jobs[k].grid.ny < 1 || jobs[k].tel.n < 1)
+      return fail(RUBIX_EINVAL, "job %d: empty cube shape", k);
+    if (!(p.gain >= 0.0) || !isfinite(p.gain) || !(p.sigma_floor >= 0.0) || !isfinite(p.sigma_floor))
+      return fail(RUBIX_EINVAL, "job %d: gain and sigma_floor must be finite and >= 0", k);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int k = 0; k < n_jobs; ++k) {
+    const int64_t n = (int64_t)jobs[k].grid.nx * jobs[k].grid.ny * jobs[k].tel.n;
+    hipError_t e = launch_noise(cubes[k], n, noise[k].seed, noise[k].stream, noise[k].gain,
+                                noise[k].sigma_floor, s);
+    if (e != hipSuccess) return device_status(e, "rubix_add_noise");
+  }
+  return RUBIX_OK;
+}
+
 size_t rubix_table_bytes(int n_jobs) {
   if (n_jobs < 1 || n_jobs > RUBIX_MAX_JOBS) return 0;
   return al(table_bytes(n_jobs));

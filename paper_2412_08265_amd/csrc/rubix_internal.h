@@ -182,6 +182,9 @@ extern thread_local hipEvent_t t_cube_events[2];
 hipError_t launch_psf_lsf(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
 hipError_t launch_backward(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);
 
+hipError_t launch_noise(float *cube, int64_t n, uint64_t seed, uint32_t stream, double gain,
+                        double sigma_floor, hipStream_t s);
+
 // Work-item kind (Kind) whose total sets the grid of a forward kernel, or -1 if `func` is not one
 // of that file's forward kernels (identifies the kernel nodes of a captured forward sequence).
 int rotate_bin_kernel_kind(const void *func);

@@ -250,6 +250,19 @@ def rubix_graph_destroy(graph: int) -> None:
     check(_lib.load().rubix_graph_destroy(graph))
 
 
+def rubix_add_noise(jobs, noise: Sequence[dict], cubes: Sequence[torch.Tensor],
+                    stream=None) -> None:
+    """noise[k] = dict(seed=..., stream=..., gain=..., sigma_floor=...) for jobs[k]; adds the
+    noise to cubes[k] in place."""
+    lib = _lib.load()
+    arr = (_lib.RubixNoise * len(jobs))()
+    for k, p in enumerate(noise):
+        arr[k] = _lib.RubixNoise(int(p["seed"]), int(p.get("stream", 0)), 0, float(p["gain"]),
+                                 float(p["sigma_floor"]))
+    check(lib.rubix_add_noise(_jobs_array(jobs), len(jobs), arr,
+                              ptr_array([c.data_ptr() for c in cubes]), _stream(stream)))
+
+
 def rubix_cube_timer(enable: bool) -> None:
     check(_lib.load().rubix_cube_timer(1 if enable else 0))
 
