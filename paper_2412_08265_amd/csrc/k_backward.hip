@@ -69,34 +69,57 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
       const float w0 = r.a[0], w1 = r.a[1], w2 = r.a[2], w3 = r.a[3];
       const float ta = w2 + w3, tz = w1 + w3;   // bilinear fractions recovered from the weights
       float sm = 0.f, sa = 0.f, sz = 0.f, y = 0.f;
-      for (int jb = lane; jb < J.n_tel; jb += 64) {
-        const float4 bt = J.bintab[jb];
-        const float tq = fmaf(-bt.z, r.g, bt.y);
-        const float fl = floorf(tq);
-        const float tau = tq - fl;
-        const int k = __float_as_int(bt.x) + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
-        const bool ok = (k >= 0) && ((k < nl - 1) || (k == nl - 1 && tau == 0.f));
-        if (ok) {
-          const int kk = min(k, nl - 2);
-          const float tt = (k > kk) ? 1.f : tau;
-          const float *b = flux + prep_row(r.row) + kk;
-          const float p0 = b[0], q0 = b[1], p1 = b[o1], q1 = b[o1 + 1];
-          const float p2 = b[o2], q2 = b[o2 + 1], p3 = b[o3], q3 = b[o3 + 1];
+      const int row = prep_row(r.row);
+      // kBwdUnroll bins per lane per iteration, every load unconditional (indices clamped to
+      // the grid, a bin outside the SSP range or past the band weighted by 0), so the
+      // iteration's loads are in flight together; bins are accumulated in increasing order
+      for (int jb0 = lane; jb0 < J.n_tel; jb0 += 64 * kBwdUnroll) {
+        float4 bt[kBwdUnroll];
+        float gw[kBwdUnroll];
+#pragma unroll
+        for (int u = 0; u < kBwdUnroll; ++u) {
+          const int jb = jb0 + 64 * u;
+          const int jc = min(jb, J.n_tel - 1);
+          bt[u] = J.bintab[jc];
+          gw[u] = jb < J.n_tel ? G[jc] : 0.f;
+        }
+        float tt[kBwdUnroll], pv[kBwdUnroll][4], qv[kBwdUnroll][4];
+#pragma unroll
+        for (int u = 0; u < kBwdUnroll; ++u) {
+          const float tq = fmaf(-bt[u].z, r.g, bt[u].y);
+          const float fl = floorf(tq);
+          const float tau = tq - fl;
+          const int k = __float_as_int(bt[u].x) + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
+          const bool ok = (k >= 0) && ((k < nl - 1) || (k == nl - 1 && tau == 0.f));
+          if (!ok) gw[u] = 0.f;
+          const int kk = min(max(k, 0), nl - 2);
+          tt[u] = (k > kk) ? 1.f : tau;
+          const float *b = flux + row + kk;
+          pv[u][0] = b[0]; qv[u][0] = b[1];
+          pv[u][1] = b[o1]; qv[u][1] = b[o1 + 1];
+          pv[u][2] = b[o2]; qv[u][2] = b[o2 + 1];
+          pv[u][3] = b[o3]; qv[u][3] = b[o3 + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kBwdUnroll; ++u) {
+          const float p0 = pv[u][0], q0 = qv[u][0], p1 = pv[u][1], q1 = qv[u][1];
+          const float p2 = pv[u][2], q2 = qv[u][2], p3 = pv[u][3], q3 = qv[u][3];
+          const float t = tt[u];
           const float d0 = q0 - p0, d1 = q1 - p1, d2 = q2 - p2, d3 = q3 - p3;
-          const float S = w0 * fmaf(tt, d0, p0) + w1 * fmaf(tt, d1, p1) +
-                          w2 * fmaf(tt, d2, p2) + w3 * fmaf(tt, d3, p3);
+          const float S = w0 * fmaf(t, d0, p0) + w1 * fmaf(t, d1, p1) +
+                          w2 * fmaf(t, d2, p2) + w3 * fmaf(t, d3, p3);
           const float dS = w0 * d0 + w1 * d1 + w2 * d2 + w3 * d3;
           // age direction: (1-tz)(Tlin_2 - Tlin_0) + tz (Tlin_3 - Tlin_1)
           const float ea = p2 - p0, fa = q2 - q0, eb = p3 - p1, fb = q3 - q1;
-          const float Aa = (1.f - tz) * fmaf(tt, fa - ea, ea) + tz * fmaf(tt, fb - eb, eb);
+          const float Aa = (1.f - tz) * fmaf(t, fa - ea, ea) + tz * fmaf(t, fb - eb, eb);
           // metallicity direction: (1-ta)(Tlin_1 - Tlin_0) + ta (Tlin_3 - Tlin_2)
           const float ez = p1 - p0, fz = q1 - q0, ez2 = p3 - p2, fz2 = q3 - q2;
-          const float Az = (1.f - ta) * fmaf(tt, fz - ez, ez) + ta * fmaf(tt, fz2 - ez2, ez2);
-          const float g = G[jb];
+          const float Az = (1.f - ta) * fmaf(t, fz - ez, ez) + ta * fmaf(t, fz2 - ez2, ez2);
+          const float g = gw[u];
           sm = fmaf(g, S, sm);
           sa = fmaf(g, Aa, sa);
           sz = fmaf(g, Az, sz);
-          y = fmaf(g * bt.z, dS, y);
+          y = fmaf(g * bt[u].z, dS, y);
         }
       }
       const double Sm = wave_sum(sm), Sa = wave_sum(sa), Sz = wave_sum(sz), Y = wave_sum(y);
