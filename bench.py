@@ -287,7 +287,7 @@ def main():
                        "psf_lsf_GBs": psf_gbs, "psf_lsf_frac": psf_gbs / PEAK_HBM_GBS},
     }
     err(f"step {ms_step:.3f} ms, stages {st}")
-    if not args.no_backward:
+    if not args.no_backward and not w.resample:     # (the bin mean has no adjoint)
         # gradient pass beside the forward: adjoint PSF/LSF of a seeded dL/dcube, then the
         # per-particle adjoint (mass, age, [M/H], v_los, velocities, angles)
         gen = torch.Generator(device=dev).manual_seed(7)
