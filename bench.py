@@ -25,6 +25,10 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 CUBE_FLOP_PER_UNIT = 16        # 4 SSP corners x 2 resampling taps x 1 multiply-add (2 FLOP)
+# template bytes gathered per particle*bin: 4 corner rows x 4 B at 64 staged nodes per 62 bins
+CUBE_GATHER_BYTES_PER_UNIT = 16.0 * 64.0 / 62.0
+# aggregate L2 read rate: 8 XCDs x 16 channels x 128 B/clk x 2.4 GHz
+PEAK_L2_TBS = 8 * 16 * 128 * 2.4e9 / 1e12
 ROTBIN_BYTES_PER_PARTICLE = 100  # rotate + key + vlos + two radix passes + offsets (design figure)
 PSF_BYTES_PER_VOXEL = 24       # three 1-D passes, each reads and writes the cube once (FP32)
 
@@ -247,6 +251,7 @@ def main():
     value = n_in * w.n_tel / (ms_step * 1e-3)
     units = n_in * w.n_tel
     achieved = CUBE_FLOP_PER_UNIT * units / (cube_kernel_ms * 1e-3) / 1e12
+    gather_tbs = CUBE_GATHER_BYTES_PER_UNIT * units / (cube_kernel_ms * 1e-3) / 1e12
     digest = source_digest("k_cube.hip")
     traffic = traffic_from_profile(digest) if args.variant == "centre" else None
     rot_gbs = ROTBIN_BYTES_PER_PARTICLE * w.particles.n / (st[0] * 1e-3) / 1e9
@@ -281,6 +286,11 @@ def main():
                      "flop_per_unit": CUBE_FLOP_PER_UNIT, "units_per_launch": units,
                      "avg_ms": cube_kernel_ms, "source_digest": digest,
                      "timing": "HIP event pair around k_cube on its stream, every timed step"},
+        "onchip": None if w.resample else {
+            "bound": "l2", "kernel": "k_cube", "achieved": gather_tbs, "peak": PEAK_L2_TBS,
+            "unit": "TB/s", "frac": gather_tbs / PEAK_L2_TBS,
+            "bytes_per_unit": CUBE_GATHER_BYTES_PER_UNIT,
+            "what": "template rows gathered from L1/L2 into the LDS windows"},
         "stages_ms": {"rotate_bin": st[0], "cube": st[1], "psf_lsf": st[2],
                       "k_cube": cube_kernel_ms},
         "stages_hbm": {"rotate_bin_GBs": rot_gbs, "rotate_bin_frac": rot_gbs / PEAK_HBM_GBS,

@@ -364,44 +364,49 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
       interior = lo >= 0 && hi + 63 <= nl - 1;
     }
     if (interior) {
-      for (; p + kCubeGroup <= ch.p1; p += kCubeGroup) {
-        PrepRec r[kCubeGroup];
+      // blocks of groups that end on the partial-sum boundaries (every kCubeSubsum particles of
+      // the chunk the partial sum moves into the total)
+      while (p + kCubeGroup <= ch.p1) {
+        const int pe = p + min(kCubeSubsum - since, (ch.p1 - p) / kCubeGroup * kCubeGroup);
+        since += pe - p;
+        for (; p < pe; p += kCubeGroup) {
+          PrepRec r[kCubeGroup];
 #pragma unroll
-        for (int u = 0; u < kCubeGroup; ++u) r[u] = load_rec(prep + p + u);
-        float tau[kCubeGroup];
-        uint32_t dl[kCubeGroup], so[kCubeGroup];
+          for (int u = 0; u < kCubeGroup; ++u) r[u] = load_rec(prep + p + u);
+          float tau[kCubeGroup];
+          uint32_t dl[kCubeGroup], so[kCubeGroup];
 #pragma unroll
-        for (int u = 0; u < kCubeGroup; ++u) {
-          const float t = fmaf(-lamf, r[u].g, qf);
-          tau[u] = __builtin_amdgcn_fractf(t);
-          const int fi = floor_i32(t);
-          const int fi0 = __builtin_amdgcn_readfirstlane(fi);
-          dl[u] = (uint32_t)(fi - fi0) * 4u;
-          so[u] = (uint32_t)(r[u].row + qi0 + fi0) * 4u;      // window base, >= 0 here
+          for (int u = 0; u < kCubeGroup; ++u) {
+            const float t = fmaf(-lamf, r[u].g, qf);
+            tau[u] = __builtin_amdgcn_fractf(t);
+            const int fi = floor_i32(t);
+            const int fi0 = __builtin_amdgcn_readfirstlane(fi);
+            dl[u] = (uint32_t)(fi - fi0) * 4u;
+            so[u] = (uint32_t)(r[u].row + qi0 + fi0) * 4u;      // window base, >= 0 here
+          }
+          float v[kCubeGroup][4];
+#pragma unroll
+          for (int u = 0; u < kCubeGroup; ++u) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[u][c] = ldf(rs, lb[c], so[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < kCubeGroup; ++u) {
+            float Sv = r[u].a[0] * v[u][0];
+            Sv = fmaf(r[u].a[1], v[u][1], Sv);
+            Sv = fmaf(r[u].a[2], v[u][2], Sv);
+            Sv = fmaf(r[u].a[3], v[u][3], Sv);
+            wslot[u * 64 + lane] = Sv;
+          }
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int u = 0; u < kCubeGroup; ++u) {
+            const float *sp = (const float *)((const char *)wslot + abase + dl[u]) + u * 64;
+            const float s0 = sp[0], s1 = sp[1];
+            acc += fmaf(tau[u], s1 - s0, s0);
+          }
+          __builtin_amdgcn_wave_barrier();
         }
-        float v[kCubeGroup][4];
-#pragma unroll
-        for (int u = 0; u < kCubeGroup; ++u) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) v[u][c] = ldf(rs, lb[c], so[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < kCubeGroup; ++u) {
-          float Sv = r[u].a[0] * v[u][0];
-          Sv = fmaf(r[u].a[1], v[u][1], Sv);
-          Sv = fmaf(r[u].a[2], v[u][2], Sv);
-          Sv = fmaf(r[u].a[3], v[u][3], Sv);
-          wslot[u * 64 + lane] = Sv;
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int u = 0; u < kCubeGroup; ++u) {
-          const float *sp = (const float *)((const char *)wslot + abase + dl[u]) + u * 64;
-          const float s0 = sp[0], s1 = sp[1];
-          acc += fmaf(tau[u], s1 - s0, s0);
-        }
-        __builtin_amdgcn_wave_barrier();
-        since += kCubeGroup;
         if (since >= kCubeSubsum) { tot += acc; acc = 0.f; since = 0; }
       }
     }

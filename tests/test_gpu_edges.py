@@ -123,3 +123,16 @@ def test_batch_of_the_largest_number_of_jobs():
         assert torch.equal(ref.cube, bufs[k].cube), k
         assert torch.equal(ref.perm, bufs[k].perm), k
     log("64-job batch equals single calls")
+
+
+@pytest.mark.parametrize("n_tel", [61, 62, 63, 247, 248, 249, 993])
+def test_wave_and_tile_tails(n_tel):
+    """Telescope grids whose last wave ends one bin short of, at and one past a wave's 62 bins,
+    at a tile edge (248 bins) and past it; the longest grid also reaches the red end of the SSP
+    grid, where waves leave the unchecked path."""
+    p = _particles(5000, 40 + n_tel, r=0.9)
+    ssp = synth.cached_ssp(8, 5, 3600.0, 7.615230460921844, 500)
+    w = synth.Workload(f"tel{n_tel}", p, (20.0, 5.0, 0.0), 6, 5, 0.4, 3700.3, 3.7, n_tel, ssp,
+                       psf_sigma_spx=0.9, lsf_sigma_A=4.0)
+    log(f"wave/tile tails: n_tel={n_tel}")
+    _run(w)
