@@ -49,13 +49,53 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// One bin's terms of the four dots from the template values around its node: p_c at kk and q_c at
+// kk + 1 in corner row c, interpolation fraction t, gradient weight g (0 where the bin is out of
+// range) and the bin's Doppler factor lamf.
+__device__ __forceinline__ void bwd_bin(float w0, float w1, float w2, float w3, float ta, float tz,
+                                        float t, float g, float lamf, const float (&pv)[4],
+                                        const float (&qv)[4], float &sm, float &sa, float &sz,
+                                        float &y) {
+  const float p0 = pv[0], q0 = qv[0], p1 = pv[1], q1 = qv[1];
+  const float p2 = pv[2], q2 = qv[2], p3 = pv[3], q3 = qv[3];
+  const float d0 = q0 - p0, d1 = q1 - p1, d2 = q2 - p2, d3 = q3 - p3;
+  const float S = w0 * fmaf(t, d0, p0) + w1 * fmaf(t, d1, p1) + w2 * fmaf(t, d2, p2) +
+                  w3 * fmaf(t, d3, p3);
+  const float dS = w0 * d0 + w1 * d1 + w2 * d2 + w3 * d3;
+  // age direction: (1-tz)(Tlin_2 - Tlin_0) + tz (Tlin_3 - Tlin_1)
+  const float ea = p2 - p0, fa = q2 - q0, eb = p3 - p1, fb = q3 - q1;
+  const float Aa = (1.f - tz) * fmaf(t, fa - ea, ea) + tz * fmaf(t, fb - eb, eb);
+  // metallicity direction: (1-ta)(Tlin_1 - Tlin_0) + ta (Tlin_3 - Tlin_2)
+  const float ez = p1 - p0, fz = q1 - q0, ez2 = p3 - p2, fz2 = q3 - q2;
+  const float Az = (1.f - ta) * fmaf(t, fz - ez, ez) + ta * fmaf(t, fz2 - ez2, ez2);
+  sm = fmaf(g, S, sm);
+  sa = fmaf(g, Aa, sa);
+  sz = fmaf(g, Az, sz);
+  y = fmaf(g * lamf, dS, y);
+}
+
+// One wave per particle, walking the telescope grid in windows of kCubeWaveBins bins (lane l
+// takes bin jw + l; lanes 62 and 63 only stage). Where the particle's span fits a window (the
+// forward kernel's decision, carried in the record's sign) and the window's 64 nodes n0 .. n0+63
+// (n0 = lane 0's node) lie inside the SSP grid, the four corner rows are staged in the wave's
+// LDS rows with one coalesced load each and every bin reads its two taps per row from there;
+// otherwise each lane gathers its eight template values directly. Each lane accumulates its bins
+// in increasing order; the wave's sums are reduced in FP64.
 __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
+  __shared__ float rows[4][4][64];     // [wave][corner][node - n0]
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
   const float *__restrict__ flux = S.flux;
   const int nl = S.n_lam;
   const int o1 = nl, o2 = S.n_met * nl, o3 = o2 + nl;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t fbytes = (uint32_t)S.n_age * (uint32_t)S.n_met * (uint32_t)nl * 4u;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)flux, (short)0, (int)fbytes, 0x00020000);
+  // byte offsets of this lane's node in the four corner rows relative to corner (ja, jz)
+  const uint32_t lb[4] = {(uint32_t)lane * 4u, (uint32_t)(lane + o1) * 4u,
+                          (uint32_t)(lane + o2) * 4u, (uint32_t)(lane + o3) * 4u};
+  float *wr = &rows[w][0][0];
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_BWD]; vb += gridDim.x) {
     const int jj = find_job(T, K_BWD, vb);
     const JobDev &J = jobs[jj];
@@ -68,59 +108,51 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
       const float *__restrict__ G = J.grad_raw + (int64_t)r.spaxel * J.n_tel;
       const float w0 = r.a[0], w1 = r.a[1], w2 = r.a[2], w3 = r.a[3];
       const float ta = w2 + w3, tz = w1 + w3;   // bilinear fractions recovered from the weights
-      float sm = 0.f, sa = 0.f, sz = 0.f, y = 0.f;
+      const bool fits = r.row >= 0;
       const int row = prep_row(r.row);
-      // kBwdUnroll bins per lane per iteration, every load unconditional (indices clamped to
-      // the grid, a bin outside the SSP range or past the band weighted by 0), so the
-      // iteration's loads are in flight together; bins are accumulated in increasing order
-      for (int jb0 = lane; jb0 < J.n_tel; jb0 += 64 * kBwdUnroll) {
-        float4 bt[kBwdUnroll];
-        float gw[kBwdUnroll];
+      float sm = 0.f, sa = 0.f, sz = 0.f, y = 0.f;
+      for (int jw = 0; jw < J.n_tel; jw += kCubeWaveBins) {
+        const int jb = jw + lane;
+        const bool act = (lane < kCubeWaveBins) && (jb < J.n_tel);
+        // lanes past the window's bins take its last bin, so their nodes stay in the window
+        const int jc = min(jw + min(lane, kCubeWaveBins - 1), J.n_tel - 1);
+        const float4 bt = J.bintab[jc];
+        const float gj = act ? G[jc] : 0.f;
+        const float tq = fmaf(-bt.z, r.g, bt.y);
+        const float fl = floorf(tq);
+        const float tau = tq - fl;
+        const int k = __float_as_int(bt.x) + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
+        // bins whose node lies outside the SSP grid carry no gradient (a select, not a store
+        // under a branch)
+        const bool ok = (k >= 0) & ((k < nl - 1) | ((k == nl - 1) & (tau == 0.f)));
+        const float g = ok ? gj : 0.f;
+        const int kk = min(max(k, 0), nl - 2);
+        const float t = (k > kk) ? 1.f : tau;
+        const int n0 = __builtin_amdgcn_readfirstlane(k);
+        float pv[4], qv[4];
+        if (fits && n0 >= 0 && n0 + 63 <= nl - 1) {
+          const uint32_t so = (uint32_t)(row + n0) * 4u;
 #pragma unroll
-        for (int u = 0; u < kBwdUnroll; ++u) {
-          const int jb = jb0 + 64 * u;
-          const int jc = min(jb, J.n_tel - 1);
-          bt[u] = J.bintab[jc];
-          gw[u] = jb < J.n_tel ? G[jc] : 0.f;
-        }
-        float tt[kBwdUnroll], pv[kBwdUnroll][4], qv[kBwdUnroll][4];
+          for (int c = 0; c < 4; ++c)
+            wr[c * 64 + lane] = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(rs, lb[c] + so, 0, 0));
+          __builtin_amdgcn_wave_barrier();
+          // kk = k in [n0, n0 + 62] for every lane here; the clamp only guards the LDS rows
+          const int i = min(max(kk - n0, 0), 62);
 #pragma unroll
-        for (int u = 0; u < kBwdUnroll; ++u) {
-          const float tq = fmaf(-bt[u].z, r.g, bt[u].y);
-          const float fl = floorf(tq);
-          const float tau = tq - fl;
-          const int k = __float_as_int(bt[u].x) + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
-          const bool ok = (k >= 0) && ((k < nl - 1) || (k == nl - 1 && tau == 0.f));
-          if (!ok) gw[u] = 0.f;
-          const int kk = min(max(k, 0), nl - 2);
-          tt[u] = (k > kk) ? 1.f : tau;
+          for (int c = 0; c < 4; ++c) {
+            pv[c] = wr[c * 64 + i];
+            qv[c] = wr[c * 64 + i + 1];
+          }
+          __builtin_amdgcn_wave_barrier();
+        } else {
           const float *b = flux + row + kk;
-          pv[u][0] = b[0]; qv[u][0] = b[1];
-          pv[u][1] = b[o1]; qv[u][1] = b[o1 + 1];
-          pv[u][2] = b[o2]; qv[u][2] = b[o2 + 1];
-          pv[u][3] = b[o3]; qv[u][3] = b[o3 + 1];
+          pv[0] = b[0]; qv[0] = b[1];
+          pv[1] = b[o1]; qv[1] = b[o1 + 1];
+          pv[2] = b[o2]; qv[2] = b[o2 + 1];
+          pv[3] = b[o3]; qv[3] = b[o3 + 1];
         }
-#pragma unroll
-        for (int u = 0; u < kBwdUnroll; ++u) {
-          const float p0 = pv[u][0], q0 = qv[u][0], p1 = pv[u][1], q1 = qv[u][1];
-          const float p2 = pv[u][2], q2 = qv[u][2], p3 = pv[u][3], q3 = qv[u][3];
-          const float t = tt[u];
-          const float d0 = q0 - p0, d1 = q1 - p1, d2 = q2 - p2, d3 = q3 - p3;
-          const float S = w0 * fmaf(t, d0, p0) + w1 * fmaf(t, d1, p1) +
-                          w2 * fmaf(t, d2, p2) + w3 * fmaf(t, d3, p3);
-          const float dS = w0 * d0 + w1 * d1 + w2 * d2 + w3 * d3;
-          // age direction: (1-tz)(Tlin_2 - Tlin_0) + tz (Tlin_3 - Tlin_1)
-          const float ea = p2 - p0, fa = q2 - q0, eb = p3 - p1, fb = q3 - q1;
-          const float Aa = (1.f - tz) * fmaf(t, fa - ea, ea) + tz * fmaf(t, fb - eb, eb);
-          // metallicity direction: (1-ta)(Tlin_1 - Tlin_0) + ta (Tlin_3 - Tlin_2)
-          const float ez = p1 - p0, fz = q1 - q0, ez2 = p3 - p2, fz2 = q3 - q2;
-          const float Az = (1.f - ta) * fmaf(t, fz - ez, ez) + ta * fmaf(t, fz2 - ez2, ez2);
-          const float g = gw[u];
-          sm = fmaf(g, S, sm);
-          sa = fmaf(g, Aa, sa);
-          sz = fmaf(g, Az, sz);
-          y = fmaf(g * bt[u].z, dS, y);
-        }
+        bwd_bin(w0, w1, w2, w3, ta, tz, t, g, bt.z, pv, qv, sm, sa, sz, y);
       }
       const double Sm = wave_sum(sm), Sa = wave_sum(sa), Sz = wave_sum(sz), Y = wave_sum(y);
       if (lane == 0) {

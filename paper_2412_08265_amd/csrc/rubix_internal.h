@@ -31,7 +31,6 @@ constexpr int kLsfOut = 1024;       // bins per LSF work item (4 consecutive per
 constexpr int kPsfLanes = 64;       // bins per PSF work item
 constexpr int kPsfSeg = 64;         // spaxels of a line per PSF work item (16 per wave)
 constexpr int kBwdParticles = 16;   // particles per backward work item (4 per wave)
-constexpr int kBwdUnroll = 4;       // telescope bins per lane per backward iteration
 constexpr int kFinThreads = 256;
 constexpr int kVbParticles = 16384; // particles per Doppler-bound work item
 

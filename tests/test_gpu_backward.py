@@ -82,6 +82,33 @@ def test_backward_kernel_on_seeded_gradient():
     _compare(g, ref, 2e-5, "seeded-G")
 
 
+def _edges_workload(n=3000, seed=37):
+    """Telescope bins on the SSP nodes, running 5 nodes past both ends of the SSP grid."""
+    p = synth.make_galaxy(n, seed)
+    ssp = synth.cached_ssp(12, 6, 3600.0, 3.8, 1000)
+    return synth.Workload("grad-edges", p, (55.0, 12.0, 20.0), 14, 12, 2.0, 3600.0 - 5 * 3.8,
+                          3.8, 1010, ssp, psf_sigma_spx=1.2, lsf_sigma_A=6.0)
+
+
+def test_seeded_gradient_with_bins_past_both_ends_of_the_ssp_grid():
+    """Bins whose rest-frame node lies below the first or above the last SSP node carry no
+    gradient; with the telescope grid running past both ends of the SSP grid every particle has
+    such bins (redshifted ones more at the blue end, blueshifted ones at the red end). A seeded
+    random dL/dC_raw weights them as much as any other bin, so a bin leaking into the dots shows
+    at once. Oracle on every particle and FP64 finite differences."""
+    w = _edges_workload()
+    cfg = O.config_from_workload(w)
+    fo = O.forward(w.particles, cfg)
+    vl = fo["vlos"]
+    assert (vl < 0).sum() > 100 and (vl > 0).sum() > 100
+    rng = np.random.default_rng(11)
+    G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
+    _, g = _gpu_grads(w, G)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo)
+    _compare(g, ref, 2e-5, "edges seeded-G")
+    _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False)
+
+
 def _fd_delta_L(cfg, G, s, dplus, dminus, quadratic=True):
     """L(+) - L(-) when one particle of spaxel s changes its spectrum by d+/d- (FP64).
     For the loss L = |A C - T|^2 / 2 with G = A(A C - T):
