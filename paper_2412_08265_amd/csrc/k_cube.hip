@@ -2,9 +2,11 @@
 // the telescope grid and the per-spaxel sum.
 //
 // Data flow (all on the caller's stream):
-//   k_prep    one thread per sorted in-field particle: gathers (mass, age, [M/H], v_los) through
-//             perm, finds the SSP cell, and writes a 32-byte record {flux row, Doppler slope g,
-//             4 corner weights, spaxel, window flag} in spaxel order.
+//   k_vbound  streams the particles in input order: the job's largest Doppler slope and window
+//             flag for the cube kernel, and a packed 16-byte (mass, age, [M/H], v_los) record each.
+//   k_prep    one thread per sorted in-field particle: gathers the packed record through perm,
+//             finds the SSP cell, and writes a 32-byte record {flux row, Doppler slope g,
+//             4 corner weights, window flag} in spaxel order.
 //   k_chunks  one block per job: splits every spaxel's particle range into chunks of at most
 //             kCubeChunk particles (load balance for dense central spaxels); chunks of a spaxel
 //             with several chunks get partial-sum slots.
@@ -81,7 +83,15 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__
     const int n_in = J.seg_off[J.n_s];
     if (i >= n_in) continue;
     const int j = J.perm[i];
-    const double age = J.age[j], m = J.mass[j], met = J.met[j], v = J.vlos[j];
+    // forward: one 16-byte gather of the particle's (mass, age, [M/H], vlos), packed in input
+    // order by k_vbound; backward: the particle arrays (and its key) directly
+    double age, m, met, v;
+    if (mode == 0) {
+      const float4 pr = J.pay[j];
+      m = pr.x; age = pr.y; met = pr.z; v = pr.w;
+    } else {
+      age = J.age[j]; m = J.mass[j]; met = J.met[j]; v = J.vlos[j];
+    }
     const int ja = cell_of(S.age_thr, S.n_age, age);
     double ta;
     if (!(age > S.age_thr[0])) ta = 0.0;
@@ -107,7 +117,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__
     r.a[1] = (float)(scale * (1.0 - ta) * tz);
     r.a[2] = (float)(scale * ta * (1.0 - tz));
     r.a[3] = (float)(scale * ta * tz);
-    r.spaxel = J.key[j];
+    r.spaxel = mode == 0 ? -1 : J.key[j];
     if (!fits) r.row = ~r.row;
     r.pad = 0;
     J.prep[i] = r;
@@ -117,7 +127,9 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__
 // Per job, over all its particles in input order: the largest |g| of a particle whose span fits,
 // and whether any particle's span does not fit (doppler_slope, exactly as k_prep decides). The
 // cube kernel uses them to find lambda tiles where every particle's window lies inside the SSP
-// grid. One atomic per work item; k_chunks zeroes counts[2..3] before this kernel runs.
+// grid. One atomic per work item; k_chunks zeroes counts[2..3] before this kernel runs. The same
+// pass packs each particle's (mass, age, [M/H], vlos) into one 16-byte record, so that k_prep
+// gathers one record per sorted particle instead of four scattered floats.
 __global__ __launch_bounds__(256) void k_vbound(const Table *__restrict__ T) {
   __shared__ int s_g[4], s_f[4];
   const SspDev &S = T->h.ssp;
@@ -130,9 +142,11 @@ __global__ __launch_bounds__(256) void k_vbound(const Table *__restrict__ T) {
     for (int q = threadIdx.x; q < kVbParticles; q += 256) {
       const int64_t i = base + q;
       if (i < J.n) {
+        const float vl = J.vlos[i];
+        J.pay[i] = make_float4(J.mass[i], J.age[i], J.met[i], vl);
         float g;
         bool fits;
-        doppler_slope(J, S, (double)J.vlos[i], g, fits);
+        doppler_slope(J, S, (double)vl, g, fits);
         if (fits) gmax = max(gmax, __float_as_int(fabsf(g)));   // non-negative: int order
         else nofit = 1;
       }

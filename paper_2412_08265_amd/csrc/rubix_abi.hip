@@ -76,7 +76,7 @@ struct JobSizes {
   double lsf_sigma_bins;
   // byte offsets inside the job's workspace region
   size_t o_k0, o_k1, o_v0, o_v1, o_hist, o_dtot;                       // sort
-  size_t o_prep, o_chunks, o_combs, o_counts, o_partial;              // cube
+  size_t o_prep, o_chunks, o_combs, o_counts, o_partial, o_pay;       // cube
   size_t o_tmp;                                                       // psf/lsf
   size_t o_bintab, o_dots, o_ang;                                     // backward (+ o_prep)
   size_t region;
@@ -132,6 +132,7 @@ static JobSizes sizes_of(const rubix_job &j) {
   z.o_combs = o; o += al(sizeof(CombRec) * (size_t)std::max(1, z.n_comb_ub));
   z.o_counts = o; o += al(16);
   z.o_partial = o; o += z.n_comb_ub > 0 ? al(4ull * z.n_slot_ub * z.n_tel) : 0;
+  z.o_pay = o; o += al(16ull * z.n);
   size_t cube_end = o;
   // psf/lsf region
   z.o_tmp = 0;
@@ -379,6 +380,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
     d.combs = reinterpret_cast<CombRec *>(region + z.o_combs);
     d.counts = reinterpret_cast<int32_t *>(region + z.o_counts);
     d.partial = reinterpret_cast<float *>(region + z.o_partial);
+    d.pay = reinterpret_cast<float4 *>(region + z.o_pay);
     d.tmp_cube = reinterpret_cast<float *>(region + z.o_tmp);
     d.bintab = reinterpret_cast<float4 *>(region + z.o_bintab);
     d.dots = reinterpret_cast<double *>(region + z.o_dots);

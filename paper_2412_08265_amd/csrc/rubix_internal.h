@@ -63,7 +63,7 @@ struct PrepRec {
   float g;          // Doppler term of the node index: beta/(1+beta) / ((1+z_sys) dlam_ssp)
                     // per Angstrom of bin wavelength, or ln(1+beta)/dln_ssp on log grids
   float a[4];       // corner weights (forward: flux_scale m J w_c; backward: w_c)
-  int32_t spaxel;   // key of the particle
+  int32_t spaxel;   // key of the particle (backward records; -1 in forward records)
   int32_t pad;
 };
 
@@ -128,6 +128,7 @@ struct JobDev {
   uint32_t *hist;       // [256][n_sort_tiles], digit major
   uint32_t *dtot;       // [256]
   PrepRec *prep;        // [n]
+  float4 *pay;          // [n]: (mass, age, [M/H], vlos) in input order (forward cube call)
   ChunkRec *chunks;     // [n_chunk_ub]
   CombRec *combs;       // [n_comb_ub]
   int32_t *counts;      // [0] chunks, [1] combine entries, [2] bits of the largest |Doppler
