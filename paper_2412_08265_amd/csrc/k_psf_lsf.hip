@@ -16,6 +16,8 @@
 
 namespace rubix {
 
+constexpr int kStageBatch = 8;   // staging loads per thread in flight together
+
 __global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T) {
   __shared__ __attribute__((aligned(16))) float buf[kLsfOut + 2 * RUBIX_MAX_RADIUS + 8];
   const JobDev *jobs = table_jobs(T);
@@ -32,9 +34,20 @@ __global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T) {
     float *__restrict__ dst = J.pl_dst[0] + s * J.n_tel;
     const int j0 = t * kLsfOut;
     const int nload = kLsfOut + 2 * r + 4;       // + 4: the last float4 of a lane's window
-    for (int q = tid; q < nload; q += 256) {
-      const int jj2 = j0 - r + q;
-      buf[q] = (jj2 >= 0 && jj2 < J.n_tel) ? src[jj2] : 0.f;
+    // staging in batches of kStageBatch loads per thread, all in flight before the LDS writes:
+    // each load reads a clamped, always valid index and a bit mask zeroes what lies outside the
+    // row (no load sits behind a branch)
+    for (int q0 = tid; q0 < nload; q0 += 256 * kStageBatch) {
+      uint32_t v[kStageBatch];
+#pragma unroll
+      for (int b = 0; b < kStageBatch; ++b) {
+        const int jj2 = j0 - r + q0 + 256 * b;
+        const uint32_t x = __float_as_uint(src[min(max(jj2, 0), J.n_tel - 1)]);
+        v[b] = x & ((jj2 >= 0 && jj2 < J.n_tel) ? 0xffffffffu : 0u);
+      }
+#pragma unroll
+      for (int b = 0; b < kStageBatch; ++b)
+        if (q0 + 256 * b < nload) buf[q0 + 256 * b] = __uint_as_float(v[b]);
     }
     __syncthreads();
     // out[4t + i] = sum_{k=0..2r} w_k buf[4t + i + k] = sum_o wp[o - i] buf[4t + o], o = 0..2r+3,
@@ -107,11 +120,22 @@ __global__ __launch_bounds__(256) void k_psf(const Table *__restrict__ T) {
     };
     // rows q0 - r .. q0 + kPsfSeg + r + 3 (the last rows only feed masked blocked outputs)
     const int nrow = kPsfSeg + 2 * r + 4;
-    for (int t = w; t < nrow; t += 4) {
-      const int q = q0 - r + t;
-      float v = 0.f;
-      if (act && q >= 0 && q < L) v = src[spx(q) * J.n_tel + jb];
-      buf[t * kPsfLanes + lane] = v;
+    // staging in batches of kStageBatch rows per wave with every load in flight before the LDS
+    // writes: each load reads a clamped, always valid element of the line, and the zero padding
+    // is a bit mask on the loaded value (no load sits behind a branch)
+    const float *col = src + spx(0) * J.n_tel + min(jb, J.n_tel - 1);
+    const int64_t stride = (AXIS == 0 ? (int64_t)J.nx : 1) * J.n_tel;
+    for (int t0 = w; t0 < nrow; t0 += 4 * kStageBatch) {
+      uint32_t v[kStageBatch];
+#pragma unroll
+      for (int b = 0; b < kStageBatch; ++b) {
+        const int q = q0 - r + t0 + 4 * b;
+        const uint32_t x = __float_as_uint(col[min(max(q, 0), L - 1) * stride]);
+        v[b] = x & ((act && q >= 0 && q < L) ? 0xffffffffu : 0u);
+      }
+#pragma unroll
+      for (int b = 0; b < kStageBatch; ++b)
+        if (t0 + 4 * b < nrow) buf[(t0 + 4 * b) * kPsfLanes + lane] = __uint_as_float(v[b]);
     }
     __syncthreads();
     const float *wp = J.psf_w + kWPad;

@@ -51,6 +51,18 @@ __global__ __launch_bounds__(kSortThreads) void k_rotate(const Table *__restrict
 // ---------------------------------------------------------------------------------------------
 // radix sort: per-tile digit histograms
 // ---------------------------------------------------------------------------------------------
+// A buffer resource over the part of a 32-bit array that one sort tile covers: elements
+// [base, min(base + kSortTile, n)). Loads past its end return 0 instead of reading memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const uint32_t *p, int64_t base,
+                                                           int64_t n) {
+  const int64_t cnt = n - base < (int64_t)kSortTile ? n - base : (int64_t)kSortTile;
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(p + base), (short)0, (int)(cnt * 4), 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t ld_u32(__amdgpu_buffer_rsrc_t rs, int idx) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)idx * 4u, 0, 0);
+}
+
 __device__ __forceinline__ const uint32_t *sort_src_keys(const JobDev &J, int pass) {
   return pass == 0 ? reinterpret_cast<const uint32_t *>(J.key) : J.kbuf[(pass - 1) & 1];
 }
@@ -68,10 +80,17 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const Table *__restrict__
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)tile * kSortTile;
-#pragma unroll 4
+    // every key of the tile loaded first through the tile's buffer resource (no load behind a
+    // branch; entries past the end read 0 and are not counted), then counted
+    const __amdgpu_buffer_rsrc_t rk = tile_rsrc(src, base, J.n);
+    uint32_t dg[kSortItems];
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it)
+      dg[it] = (ld_u32(rk, it * kSortThreads + threadIdx.x) >> shift) & 255u;
+#pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
-      int64_t i = base + it * kSortThreads + threadIdx.x;
-      if (i < J.n) atomicAdd(&h[(src[i] >> shift) & 255u], 1u);
+      const int64_t i = base + it * kSortThreads + threadIdx.x;
+      if (i < J.n) atomicAdd(&h[dg[it]], 1u);
     }
     __syncthreads();
     J.hist[(int64_t)threadIdx.x * J.n_sort_tiles + tile] = h[threadIdx.x];
@@ -159,12 +178,21 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restric
 
     uint32_t keys[kSortItems], vals[kSortItems], rank[kSortItems];
     const int64_t base = (int64_t)tile * kSortTile + w * (64 * kSortItems);
+    // the wave's keys loaded first through the tile's buffer resource, so all of them are in
+    // flight together (entries past the end read 0 and are masked below); the values follow in
+    // one batch once the ranks are known
+    const int64_t tbase = (int64_t)tile * kSortTile;
+    const int woff = w * (64 * kSortItems);
+    {
+      const __amdgpu_buffer_rsrc_t rk = tile_rsrc(src_k, tbase, J.n);
+#pragma unroll
+      for (int r = 0; r < kSortItems; ++r) keys[r] = ld_u32(rk, woff + r * 64 + lane);
+    }
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
       const int64_t e = base + r * 64 + lane;
       const bool valid = e < J.n;
-      uint32_t k = valid ? src_k[e] : 0u;
-      uint32_t v = valid ? (pass == 0 ? (uint32_t)e : src_v[e]) : 0u;
+      const uint32_t k = keys[r];
       uint32_t d = (k >> shift) & 255u;
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -180,8 +208,6 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restric
       __builtin_amdgcn_wave_barrier();
       if (valid && below == 0) wcnt[w][d] = c0 + cnt;   // lowest lane of each digit group
       __builtin_amdgcn_wave_barrier();
-      keys[r] = k;
-      vals[r] = v;
       rank[r] = valid ? (c0 + below) : 0xffffffffu;
     }
     __syncthreads();
@@ -196,6 +222,14 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restric
       }
     }
     __syncthreads();
+    if (pass == 0) {
+#pragma unroll
+      for (int r = 0; r < kSortItems; ++r) vals[r] = (uint32_t)(base + r * 64 + lane);
+    } else {
+      const __amdgpu_buffer_rsrc_t rv = tile_rsrc(src_v, tbase, J.n);
+#pragma unroll
+      for (int r = 0; r < kSortItems; ++r) vals[r] = ld_u32(rv, woff + r * 64 + lane);
+    }
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
       if (rank[r] != 0xffffffffu) {
