@@ -5,8 +5,8 @@
 // in LDS with lane-contiguous (coalesced) loads and writes each output once; every lane computes
 // four outputs from one run of LDS values (register blocking), so an LDS value feeds four filter
 // taps instead of one:
-//   k_lsf    (spaxel, 1024-bin run): thread t owns bins 4t..4t+3 and reads the staged run with
-//            aligned 16-byte LDS loads;
+//   k_lsf    (spaxel, 2048-bin run): thread t owns bins 1024g + 4t .. +3 (g = 0, 1) and reads the
+//            staged run with aligned 16-byte LDS loads;
 //   k_psf<A> (line, 64-spaxel segment, 64-bin tile): 64 lanes span lambda (every load of a
 //            neighbouring spaxel is a contiguous 256-byte row segment); wave w owns 16 output
 //            positions of the segment, four at a time.
@@ -16,7 +16,10 @@
 
 namespace rubix {
 
-constexpr int kStageBatch = 8;   // staging loads per thread in flight together
+// staging loads per thread in flight together: the LSF's whole run with any radius in one
+// batch; the PSF's 64 + 2r + 4 rows in one batch for r <= 14
+constexpr int kLsfBatch = (kLsfOut + 2 * RUBIX_MAX_RADIUS + 4 + 255) / 256;
+constexpr int kPsfBatch = 24;
 
 __global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T) {
   __shared__ __attribute__((aligned(16))) float buf[kLsfOut + 2 * RUBIX_MAX_RADIUS + 8];
@@ -34,29 +37,32 @@ __global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T) {
     float *__restrict__ dst = J.pl_dst[0] + s * J.n_tel;
     const int j0 = t * kLsfOut;
     const int nload = kLsfOut + 2 * r + 4;       // + 4: the last float4 of a lane's window
-    // staging in batches of kStageBatch loads per thread, all in flight before the LDS writes:
+    // staging in batches of kLsfBatch loads per thread, all in flight before the LDS writes:
     // each load reads a clamped, always valid index and a bit mask zeroes what lies outside the
     // row (no load sits behind a branch)
-    for (int q0 = tid; q0 < nload; q0 += 256 * kStageBatch) {
-      uint32_t v[kStageBatch];
+    for (int q0 = tid; q0 < nload; q0 += 256 * kLsfBatch) {
+      uint32_t v[kLsfBatch];
 #pragma unroll
-      for (int b = 0; b < kStageBatch; ++b) {
+      for (int b = 0; b < kLsfBatch; ++b) {
         const int jj2 = j0 - r + q0 + 256 * b;
         const uint32_t x = __float_as_uint(src[min(max(jj2, 0), J.n_tel - 1)]);
         v[b] = x & ((jj2 >= 0 && jj2 < J.n_tel) ? 0xffffffffu : 0u);
       }
 #pragma unroll
-      for (int b = 0; b < kStageBatch; ++b)
+      for (int b = 0; b < kLsfBatch; ++b)
         if (q0 + 256 * b < nload) buf[q0 + 256 * b] = __uint_as_float(v[b]);
     }
     __syncthreads();
+    // thread t owns the runs of 4 bins at 1024 g + 4t, g = 0 .. kLsfOut/1024 - 1:
     // out[4t + i] = sum_{k=0..2r} w_k buf[4t + i + k] = sum_o wp[o - i] buf[4t + o], o = 0..2r+3,
     // wp[m] = weight of offset m (zero outside 0..2r)
+    for (int g = 0; g < kLsfOut / 1024; ++g) {
+    const int t4 = 1024 * g + 4 * tid;
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
     const float *wp = J.lsf_w + kWPad;            // wp[m], m in [-kWPad, 2r + kWPad]
     const int nq = (2 * r + 4 + 3) / 4;
     for (int m = 0; m < nq; ++m) {
-      const float4 x = *reinterpret_cast<const float4 *>(&buf[4 * tid + 4 * m]);
+      const float4 x = *reinterpret_cast<const float4 *>(&buf[t4 + 4 * m]);
       const int o = 4 * m;
       acc0 = fmaf(wp[o], x.x, acc0);
       acc1 = fmaf(wp[o - 1], x.x, acc1);
@@ -75,7 +81,7 @@ __global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T) {
       acc2 = fmaf(wp[o + 1], x.w, acc2);
       acc3 = fmaf(wp[o], x.w, acc3);
     }
-    const int jb = j0 + 4 * tid;
+    const int jb = j0 + t4;
     if (jb + 3 < J.n_tel && (((uintptr_t)(dst + jb)) & 15) == 0) {
       *reinterpret_cast<float4 *>(dst + jb) = make_float4(acc0, acc1, acc2, acc3);
     } else {
@@ -83,6 +89,7 @@ __global__ __launch_bounds__(256) void k_lsf(const Table *__restrict__ T) {
       if (jb + 1 < J.n_tel) dst[jb + 1] = acc1;
       if (jb + 2 < J.n_tel) dst[jb + 2] = acc2;
       if (jb + 3 < J.n_tel) dst[jb + 3] = acc3;
+    }
     }
     __syncthreads();
   }
@@ -120,21 +127,22 @@ __global__ __launch_bounds__(256) void k_psf(const Table *__restrict__ T) {
     };
     // rows q0 - r .. q0 + kPsfSeg + r + 3 (the last rows only feed masked blocked outputs)
     const int nrow = kPsfSeg + 2 * r + 4;
-    // staging in batches of kStageBatch rows per wave with every load in flight before the LDS
+    // staging in batches of kPsfBatch rows per wave with every load in flight before the LDS
     // writes: each load reads a clamped, always valid element of the line, and the zero padding
     // is a bit mask on the loaded value (no load sits behind a branch)
-    const float *col = src + spx(0) * J.n_tel + min(jb, J.n_tel - 1);
-    const int64_t stride = (AXIS == 0 ? (int64_t)J.nx : 1) * J.n_tel;
-    for (int t0 = w; t0 < nrow; t0 += 4 * kStageBatch) {
-      uint32_t v[kStageBatch];
+    // (the row of each load is wave-uniform: its base is scalar, the lane offset is shared)
+    const int jc = min(jb, J.n_tel - 1);
+    for (int t0 = __builtin_amdgcn_readfirstlane(w); t0 < nrow; t0 += 4 * kPsfBatch) {
+      uint32_t v[kPsfBatch];
 #pragma unroll
-      for (int b = 0; b < kStageBatch; ++b) {
+      for (int b = 0; b < kPsfBatch; ++b) {
         const int q = q0 - r + t0 + 4 * b;
-        const uint32_t x = __float_as_uint(col[min(max(q, 0), L - 1) * stride]);
+        const float *row = src + spx(min(max(q, 0), L - 1)) * J.n_tel;
+        const uint32_t x = __float_as_uint(row[jc]);
         v[b] = x & ((act && q >= 0 && q < L) ? 0xffffffffu : 0u);
       }
 #pragma unroll
-      for (int b = 0; b < kStageBatch; ++b)
+      for (int b = 0; b < kPsfBatch; ++b)
         if (t0 + 4 * b < nrow) buf[(t0 + 4 * b) * kPsfLanes + lane] = __uint_as_float(v[b]);
     }
     __syncthreads();

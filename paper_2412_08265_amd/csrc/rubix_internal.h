@@ -27,7 +27,7 @@ constexpr int kBinTL = 4 * kBinWaveBins;
 constexpr int kCubeSubsum = 256;    // particles per inner FP32 partial sum
 constexpr int kWPad = 4;            // zero weights before a padded filter
 constexpr int kWArray = 2 * RUBIX_MAX_RADIUS + 1 + 16;   // padded filter array (zeros after)
-constexpr int kLsfOut = 1024;       // bins per LSF work item (4 consecutive per thread)
+constexpr int kLsfOut = 2048;       // bins per LSF work item (two runs of 4 per thread)
 constexpr int kPsfLanes = 64;       // bins per PSF work item
 constexpr int kPsfSeg = 64;         // spaxels of a line per PSF work item (16 per wave)
 constexpr int kBwdParticles = 16;   // particles per backward work item (4 per wave)
