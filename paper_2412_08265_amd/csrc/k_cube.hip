@@ -433,53 +433,46 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
       int32_t orow = 0;
 #pragma unroll
       for (int u = 0; u < kCubeGroup; ++u) orow |= r[u].row;
-      const bool fast = !direct_job && orow >= 0;
-      bool done = false;
-      if (fast) {
+      if (!direct_job && orow >= 0) {
+        // every span fits a window: the group's 16 row loads in flight together, as in the
+        // interior, with each tap range-checked (a window may start before node 0 or reach past
+        // the last node; its out-of-grid nodes are only read by bins that the check zeroes)
         float tau[kCubeGroup];
-        int fi[kCubeGroup], fi0[kCubeGroup], n0[kCubeGroup];
-        bool inside = true;
+        int fi[kCubeGroup], fi0[kCubeGroup];
+        float v[kCubeGroup][4];
 #pragma unroll
         for (int u = 0; u < kCubeGroup; ++u) {
           const float t = fmaf(-lamf, r[u].g, qf);
           tau[u] = __builtin_amdgcn_fractf(t);
           fi[u] = floor_i32(t);
           fi0[u] = __builtin_amdgcn_readfirstlane(fi[u]);
-          n0[u] = qi0 + fi0[u];                           // window base: lane 0's node
-          inside = inside && (n0[u] >= 0) && (n0[u] + 63 <= nl - 1);
+          // window base: lane 0's node; the offset wraps modulo 2^32 with the lane part when the
+          // window starts before node 0 of the first row (past the grid's bytes: reads 0)
+          const uint32_t so = (uint32_t)(r[u].row + qi0 + fi0[u]) * 4u;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[u][c] = ldf(rs, lb[c], so);
         }
-        if (inside) {
-          float v[kCubeGroup][4];
 #pragma unroll
-          for (int u = 0; u < kCubeGroup; ++u) {
-            const uint32_t so = (uint32_t)(r[u].row + n0[u]) * 4u;
-            v[u][0] = ldf(rs, lb[0], so);
-            v[u][1] = ldf(rs, lb[1], so);
-            v[u][2] = ldf(rs, lb[2], so);
-            v[u][3] = ldf(rs, lb[3], so);
-          }
-#pragma unroll
-          for (int u = 0; u < kCubeGroup; ++u) {
-            float Sv = r[u].a[0] * v[u][0];
-            Sv = fmaf(r[u].a[1], v[u][1], Sv);
-            Sv = fmaf(r[u].a[2], v[u][2], Sv);
-            Sv = fmaf(r[u].a[3], v[u][3], Sv);
-            wslot[u * 64 + lane] = Sv;
-          }
-          __builtin_amdgcn_wave_barrier();
-#pragma unroll
-          for (int u = 0; u < kCubeGroup; ++u) {
-            // k - n0 = (qi - qi0) + (fi - fi0), in [0, 62] for every lane
-            const float *sp = (const float *)((const char *)wslot + abase +
-                                              (uint32_t)(fi[u] - fi0[u]) * 4u) + u * 64;
-            const float s0 = sp[0], s1 = sp[1];
-            acc += fmaf(tau[u], s1 - s0, s0);
-          }
-          __builtin_amdgcn_wave_barrier();
-          done = true;
+        for (int u = 0; u < kCubeGroup; ++u) {
+          float Sv = r[u].a[0] * v[u][0];
+          Sv = fmaf(r[u].a[1], v[u][1], Sv);
+          Sv = fmaf(r[u].a[2], v[u][2], Sv);
+          Sv = fmaf(r[u].a[3], v[u][3], Sv);
+          wslot[u * 64 + lane] = Sv;
         }
-      }
-      if (!done) {
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int u = 0; u < kCubeGroup; ++u) {
+          // k - n0 = (qi - qi0) + (fi - fi0), in [0, 62] for every lane (the clamp guards LDS)
+          const int idx = min(max((qi - qi0) + (fi[u] - fi0[u]), 0), 62);
+          const float s0 = wslot[u * 64 + idx], s1 = wslot[u * 64 + idx + 1];
+          const int k = qi + fi[u];
+          const bool ok = act && (k >= 0) && ((k < nl - 1) || (k == nl - 1 && tau[u] == 0.f));
+          const float val = (k == nl - 1) ? s0 : fmaf(tau[u], s1 - s0, s0);
+          acc += ok ? val : 0.f;
+        }
+        __builtin_amdgcn_wave_barrier();
+      } else {
 #pragma unroll
         for (int u = 0; u < kCubeGroup; ++u) {
           if (!direct_job && r[u].row >= 0)
