@@ -1,15 +1,15 @@
 // Steps 3-6 of the pipeline (arXiv:2412.08265, Sec. 3): SSP lookup, Doppler shift, resampling to
 // the telescope grid and the per-spaxel sum.
 //
-// Data flow (all on the caller's stream):
+// Data flow (all on the caller's stream, in this order):
+//   k_chunks  one block per job: splits every spaxel's particle range into chunks of at most
+//             kCubeChunk particles (load balance for dense central spaxels); chunks of a spaxel
+//             with several chunks get partial-sum slots.
 //   k_vbound  streams the particles in input order: the job's largest Doppler slope and window
 //             flag for the cube kernel, and a packed 16-byte (mass, age, [M/H], v_los) record each.
 //   k_prep    one thread per sorted in-field particle: gathers the packed record through perm,
 //             finds the SSP cell, and writes a 32-byte record {flux row, Doppler slope g,
 //             4 corner weights, window flag} in spaxel order.
-//   k_chunks  one block per job: splits every spaxel's particle range into chunks of at most
-//             kCubeChunk particles (load balance for dense central spaxels); chunks of a spaxel
-//             with several chunks get partial-sum slots.
 //   k_cube    one block per (lambda tile of kCubeTL bins, chunk); each wave owns 62 consecutive
 //             telescope bins and walks the chunk's particles, kCubeGroup at a time:
 //               stage    lane l computes the particle's bilinear spectrum at SSP node n0 + l,
@@ -20,6 +20,9 @@
 //                        accumulates the linear interpolant in registers (no atomics).
 //             Slots are private to a wave, so no block barrier is needed; particle records
 //             come through the scalar cache and a group's 16 row loads are in flight together.
+//             A wave whose windows stay inside the SSP grid for every slope of the job (most of
+//             them) runs without range checks; the others range-check each tap; a particle
+//             whose span does not fit a window gathers its taps directly.
 //             Blocks are ordered lambda-tile major, so the blocks resident on one XCD at a time
 //             share one tile's slice of the template grid in that XCD's L2.
 //   k_combine sums a multi-chunk spaxel's partial spectra in chunk order (deterministic).
