@@ -62,12 +62,12 @@ __device__ __forceinline__ void bwd_bin(float w0, float w1, float w2, float w3, 
   const float S = w0 * fmaf(t, d0, p0) + w1 * fmaf(t, d1, p1) + w2 * fmaf(t, d2, p2) +
                   w3 * fmaf(t, d3, p3);
   const float dS = w0 * d0 + w1 * d1 + w2 * d2 + w3 * d3;
-  // age direction: (1-tz)(Tlin_2 - Tlin_0) + tz (Tlin_3 - Tlin_1)
-  const float ea = p2 - p0, fa = q2 - q0, eb = p3 - p1, fb = q3 - q1;
-  const float Aa = (1.f - tz) * fmaf(t, fa - ea, ea) + tz * fmaf(t, fb - eb, eb);
+  // age direction: (1-tz)(Tlin_2 - Tlin_0) + tz (Tlin_3 - Tlin_1); the difference of two corners'
+  // linear interpolants is formed from the differences of their node values and of their slopes
+  // (d_c = q_c - p_c), both taken before they meet G
+  const float Aa = (1.f - tz) * fmaf(t, d2 - d0, p2 - p0) + tz * fmaf(t, d3 - d1, p3 - p1);
   // metallicity direction: (1-ta)(Tlin_1 - Tlin_0) + ta (Tlin_3 - Tlin_2)
-  const float ez = p1 - p0, fz = q1 - q0, ez2 = p3 - p2, fz2 = q3 - q2;
-  const float Az = (1.f - ta) * fmaf(t, fz - ez, ez) + ta * fmaf(t, fz2 - ez2, ez2);
+  const float Az = (1.f - ta) * fmaf(t, d1 - d0, p1 - p0) + ta * fmaf(t, d3 - d2, p3 - p2);
   sm = fmaf(g, S, sm);
   sa = fmaf(g, Aa, sa);
   sz = fmaf(g, Az, sz);
