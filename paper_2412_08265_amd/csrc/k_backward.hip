@@ -122,37 +122,39 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
         const float fl = floorf(tq);
         const float tau = tq - fl;
         const int k = __float_as_int(bt.x) + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
-        // bins whose node lies outside the SSP grid carry no gradient (a select, not a store
-        // under a branch)
-        const bool ok = (k >= 0) & ((k < nl - 1) | ((k == nl - 1) & (tau == 0.f)));
-        const float g = ok ? gj : 0.f;
-        const int kk = min(max(k, 0), nl - 2);
-        const float t = (k > kk) ? 1.f : tau;
         const int n0 = __builtin_amdgcn_readfirstlane(k);
         float pv[4], qv[4];
         if (fits && n0 >= 0 && n0 + 63 <= nl - 1) {
+          // every lane's node k lies in [n0, n0 + 62], inside [0, n - 2]: the bin is on the grid
+          // and its interval is k itself, so no mask or clamp is needed here
           const uint32_t so = (uint32_t)(row + n0) * 4u;
 #pragma unroll
           for (int c = 0; c < 4; ++c)
             wr[c * 64 + lane] = __builtin_bit_cast(
                 float, __builtin_amdgcn_raw_buffer_load_b32(rs, lb[c] + so, 0, 0));
           __builtin_amdgcn_wave_barrier();
-          // kk = k in [n0, n0 + 62] for every lane here; the clamp only guards the LDS rows
-          const int i = min(max(kk - n0, 0), 62);
+          const int i = min(max(k - n0, 0), 62);          // the clamp only guards the LDS rows
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             pv[c] = wr[c * 64 + i];
             qv[c] = wr[c * 64 + i + 1];
           }
           __builtin_amdgcn_wave_barrier();
+          bwd_bin(w0, w1, w2, w3, ta, tz, tau, gj, bt.z, pv, qv, sm, sa, sz, y);
         } else {
+          // bins whose node lies outside the SSP grid carry no gradient (a select, not a store
+          // under a branch); the last node takes the last interval with t = 1
+          const bool ok = (k >= 0) & ((k < nl - 1) | ((k == nl - 1) & (tau == 0.f)));
+          const float g = ok ? gj : 0.f;
+          const int kk = min(max(k, 0), nl - 2);
+          const float t = (k > kk) ? 1.f : tau;
           const float *b = flux + row + kk;
           pv[0] = b[0]; qv[0] = b[1];
           pv[1] = b[o1]; qv[1] = b[o1 + 1];
           pv[2] = b[o2]; qv[2] = b[o2 + 1];
           pv[3] = b[o3]; qv[3] = b[o3 + 1];
+          bwd_bin(w0, w1, w2, w3, ta, tz, t, g, bt.z, pv, qv, sm, sa, sz, y);
         }
-        bwd_bin(w0, w1, w2, w3, ta, tz, t, g, bt.z, pv, qv, sm, sa, sz, y);
       }
       const double Sm = wave_sum(sm), Sa = wave_sum(sa), Sz = wave_sum(sz), Y = wave_sum(y);
       if (lane == 0) {
