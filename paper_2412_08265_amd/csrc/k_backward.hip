@@ -59,9 +59,9 @@ __device__ __forceinline__ void bwd_bin(float w0, float w1, float w2, float w3, 
   const float p0 = pv[0], q0 = qv[0], p1 = pv[1], q1 = qv[1];
   const float p2 = pv[2], q2 = qv[2], p3 = pv[3], q3 = qv[3];
   const float d0 = q0 - p0, d1 = q1 - p1, d2 = q2 - p2, d3 = q3 - p3;
-  const float S = w0 * fmaf(t, d0, p0) + w1 * fmaf(t, d1, p1) + w2 * fmaf(t, d2, p2) +
-                  w3 * fmaf(t, d3, p3);
+  // S = sum_c w_c (p_c + t d_c) = P + t dS, with the slope sum dS needed for Y anyway
   const float dS = w0 * d0 + w1 * d1 + w2 * d2 + w3 * d3;
+  const float S = fmaf(t, dS, w0 * p0 + w1 * p1 + w2 * p2 + w3 * p3);
   // age direction: (1-tz)(Tlin_2 - Tlin_0) + tz (Tlin_3 - Tlin_1); the difference of two corners'
   // linear interpolants is formed from the differences of their node values and of their slopes
   // (d_c = q_c - p_c), both taken before they meet G
