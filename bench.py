@@ -25,6 +25,9 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 CUBE_FLOP_PER_UNIT = 16        # 4 SSP corners x 2 resampling taps x 1 multiply-add (2 FLOP)
+# bin mean: per corner the integral of a linear segment over the bin's node interval
+# (about 1.5 segments of ~4 FLOP each), 4 corners
+BIN_FLOP_PER_UNIT = 24
 # template bytes gathered per particle*bin: 4 corner rows x 4 B at 64 staged nodes per 62 bins
 CUBE_GATHER_BYTES_PER_UNIT = 16.0 * 64.0 / 62.0
 # aggregate L2 read rate: 8 XCDs x 16 channels x 128 B/clk x 2.4 GHz
@@ -250,7 +253,8 @@ def main():
     st = [sum(evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(K)) / K for i in range(3)]
     value = n_in * w.n_tel / (ms_step * 1e-3)
     units = n_in * w.n_tel
-    achieved = CUBE_FLOP_PER_UNIT * units / (cube_kernel_ms * 1e-3) / 1e12
+    flop_per_unit = BIN_FLOP_PER_UNIT if w.resample else CUBE_FLOP_PER_UNIT
+    achieved = flop_per_unit * units / (cube_kernel_ms * 1e-3) / 1e12
     gather_tbs = CUBE_GATHER_BYTES_PER_UNIT * units / (cube_kernel_ms * 1e-3) / 1e12
     digest = source_digest("k_cube.hip")
     traffic = traffic_from_profile(digest) if args.variant == "centre" else None
@@ -283,7 +287,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_cube_bin" if w.resample else "k_cube",
                      "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
-                     "flop_per_unit": CUBE_FLOP_PER_UNIT, "units_per_launch": units,
+                     "flop_per_unit": flop_per_unit, "units_per_launch": units,
                      "avg_ms": cube_kernel_ms, "source_digest": digest,
                      "timing": "HIP event pair around k_cube on its stream, every timed step"},
         "onchip": None if w.resample else {
