@@ -21,7 +21,11 @@
  *    workspaces.
  *  - Return value: RUBIX_OK (0) or a negative status; rubix_last_error() then returns a message
  *    (thread-local, valid until the next call on the same thread). Host-visible arguments are
- *    validated before any launch; device data is not inspected (NaN in gives NaN out).
+ *    validated before any launch. Device data is not inspected, and no value of it makes a
+ *    kernel access memory out of range: a particle whose rotated position is not finite falls
+ *    outside the field (key nx*ny); one whose line-of-sight velocity is not finite contributes
+ *    nothing to the cube; a NaN age or [M/H] takes the first node of its axis (infinities clamp
+ *    to the matching end); a non-finite mass makes the voxels its spectrum reaches non-finite.
  *  - Sizes: particle counts up to 2^31-1 per job; int32 spaxel keys and offsets.
  */
 #ifndef RUBIX_H

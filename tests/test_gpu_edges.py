@@ -136,3 +136,64 @@ def test_wave_and_tile_tails(n_tel):
                        psf_sigma_spx=0.9, lsf_sigma_A=4.0)
     log(f"wave/tile tails: n_tel={n_tel}")
     _run(w)
+
+
+def test_non_finite_particle_values():
+    """Non-finite particle values never reach memory out of range, and each has a fixed meaning:
+    a position that is not finite leaves the field (keys, perm and seg_off exact against the
+    oracle on the same input); a velocity that is not finite contributes nothing; a NaN age or
+    [M/H] takes the first node (the cube equals the oracle's with those particles massless or
+    below the first node); a NaN mass spoils only its own spaxel."""
+    import torch
+    n = 3000
+    p = _particles(n, 5, r=0.9)
+    x, y, vx, vz = p.x.copy(), p.y.copy(), p.vx.copy(), p.vz.copy()
+    age, met, mass = p.age.copy(), p.met.copy(), p.mass.copy()
+    rng = np.random.default_rng(9)
+    idx = rng.permutation(n)
+    x[idx[0:10]] = np.nan
+    y[idx[10:20]] = np.inf
+    vx[idx[20:30]] = np.nan
+    vz[idx[30:40]] = -np.inf
+    age[idx[40:50]] = np.nan
+    met[idx[50:60]] = np.nan
+    age[idx[60:65]] = np.inf
+    met[idx[65:70]] = -np.inf
+    bad = synth.Particles(x, y, p.z, vx, p.vy, vz, mass, age, met)
+    ssp = synth.cached_ssp(8, 5, 3600.0, 7.615230460921844, 500)
+    w = synth.Workload("non-finite", bad, (30.0, 20.0, 10.0), 8, 7, 0.3, 3650.3, 5.1, 611, ssp,
+                       psf_sigma_spx=1.0, lsf_sigma_A=6.0)
+    log("non-finite particle values")
+    _, g = gpu_forward(w)
+    cfg = O.config_from_workload(w)
+    fo = O.forward(bad, cfg, with_cube=False)
+    np.testing.assert_array_equal(g["key"], fo["key"])
+    np.testing.assert_array_equal(g["perm"], fo["perm"])
+    np.testing.assert_array_equal(g["seg_off"], fo["seg_off"])
+    assert np.all(g["key"][idx[0:20]] == w.nx * w.ny)
+    # the same cube from finite inputs: massless particles for non-finite velocities, ages and
+    # metallicities below (or above) the grid for NaN (infinite) ones
+    moving = np.isfinite(vx) & np.isfinite(vz)
+    f32 = lambda a: np.asarray(a, dtype=np.float32)
+    fin = synth.Particles(x, y, p.z, f32(np.where(moving, vx, 0.0)), p.vy,
+                          f32(np.where(moving, vz, 0.0)), f32(np.where(moving, mass, 0.0)),
+                          f32(np.where(np.isnan(age), 1e-6, np.where(np.isinf(age), 1e3, age))),
+                          f32(np.where(np.isfinite(met), met, -50.0)))
+    ref = O.forward(fin, cfg)
+    assert np.all(np.isfinite(g["cube_raw"]))
+    assert_cube_close(g["cube_raw"], ref["cube_raw"], what="non-finite cube_raw")
+    assert_cube_close(g["cube"], ref["cube"], what="non-finite cube")
+    # a NaN mass: its spaxel's voxels reached by the spectrum are NaN, every other spaxel finite
+    i0 = int(np.flatnonzero(fo["key"] < w.nx * w.ny)[0])
+    mass2 = mass.copy()
+    mass2[i0] = np.nan
+    w2 = synth.Workload("nan-mass", synth.Particles(x, y, p.z, vx, p.vy, vz, mass2, age, met),
+                        w.angles_deg, w.nx, w.ny, w.spaxel_kpc, w.tel_start, w.tel_step, w.n_tel,
+                        ssp)
+    _, g2 = gpu_forward(w2)
+    raw = g2["cube_raw"].reshape(w.ny * w.nx, w.n_tel)
+    s0 = int(fo["key"][i0])
+    assert np.isnan(raw[s0]).any()
+    others = np.delete(raw, s0, axis=0)
+    assert np.all(np.isfinite(others))
+    np.testing.assert_array_equal(others, np.delete(g["cube_raw"].reshape(w.ny * w.nx, w.n_tel), s0, axis=0))
