@@ -197,3 +197,17 @@ def test_non_finite_particle_values():
     others = np.delete(raw, s0, axis=0)
     assert np.all(np.isfinite(others))
     np.testing.assert_array_equal(others, np.delete(g["cube_raw"].reshape(w.ny * w.nx, w.n_tel), s0, axis=0))
+
+
+@pytest.mark.parametrize("ratio", [1.6, 3.0])
+def test_telescope_bins_coarser_than_the_ssp_nodes(ratio):
+    """Telescope bins wider than the SSP node spacing: no particle's span fits a wave window, so
+    every bin gathers its taps directly; the grid runs past both ends of the SSP grid."""
+    p = _particles(4000, 70, r=0.9, v=400.0)
+    ssp = synth.cached_ssp(8, 5, 3600.0, 7.615230460921844, 500)
+    step = ratio * ssp.lam_step
+    n_tel = int((ssp.lam_start + ssp.lam_step * (ssp.n_lam - 1) + 40.0 - 3560.0) / step)
+    w = synth.Workload(f"coarse-{ratio}", p, (40.0, 15.0, 5.0), 9, 8, 0.25, 3560.0, step, n_tel,
+                       ssp, psf_sigma_spx=0.8, lsf_sigma_A=1.5 * step)
+    log(f"coarse telescope grid: step {step:.3f} A, {n_tel} bins")
+    _run(w)
