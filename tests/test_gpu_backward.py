@@ -109,6 +109,24 @@ def test_seeded_gradient_with_bins_past_both_ends_of_the_ssp_grid():
     _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False)
 
 
+def test_seeded_gradient_on_a_coarse_telescope_grid():
+    """Telescope bins 1.7 times the SSP node spacing: no particle's span fits a wave window, so
+    the adjoint gathers every tap directly. Oracle on every particle and FP64 finite
+    differences."""
+    p = synth.make_galaxy(3000, 41)
+    ssp = synth.cached_ssp(12, 6, 3600.0, 3.8, 1000)
+    w = synth.Workload("grad-coarse", p, (55.0, 12.0, 20.0), 14, 12, 2.0, 3700.0, 1.7 * 3.8, 520,
+                       ssp, psf_sigma_spx=1.2, lsf_sigma_A=9.0)
+    cfg = O.config_from_workload(w)
+    fo = O.forward(w.particles, cfg)
+    rng = np.random.default_rng(13)
+    G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
+    _, g = _gpu_grads(w, G)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo)
+    _compare(g, ref, 2e-5, "coarse seeded-G")
+    _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False)
+
+
 def _fd_delta_L(cfg, G, s, dplus, dminus, quadratic=True):
     """L(+) - L(-) when one particle of spaxel s changes its spectrum by d+/d- (FP64).
     For the loss L = |A C - T|^2 / 2 with G = A(A C - T):
