@@ -301,6 +301,25 @@ def main():
                        "psf_lsf_GBs": psf_gbs, "psf_lsf_frac": psf_gbs / PEAK_HBM_GBS},
     }
     err(f"step {ms_step:.3f} ms, stages {st}")
+    # the noise step beside the step: one read and one write of the cube per call (8 B per voxel)
+    noisy = torch.empty_like(fw.buf.cube)
+    noisy.copy_(fw.buf.cube)
+    spec = [dict(seed=2024, stream=0, gain=1.0, sigma_floor=1e-3)]
+    ops.rubix_add_noise([fw.job], spec, [noisy])
+    torch.cuda.synchronize()
+    n0, n1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n0.record()
+    for _ in range(5):
+        ops.rubix_add_noise([fw.job], spec, [noisy])
+    n1.record()
+    torch.cuda.synchronize()
+    noise_ms = n0.elapsed_time(n1) / 5
+    noise_gbs = 8.0 * w.n_spaxels * w.n_tel / (noise_ms * 1e-3) / 1e9
+    out["stages_ms"]["noise"] = noise_ms
+    out["stages_hbm"]["noise_GBs"] = noise_gbs
+    out["stages_hbm"]["noise_frac"] = noise_gbs / PEAK_HBM_GBS
+    del noisy
+    err(f"noise {noise_ms:.3f} ms ({noise_gbs:.0f} GB/s)")
     if not args.no_backward and not w.resample:     # (the bin mean has no adjoint)
         # gradient pass beside the forward: adjoint PSF/LSF of a seeded dL/dcube, then the
         # per-particle adjoint (mass, age, [M/H], v_los, velocities, angles)

@@ -38,7 +38,7 @@ __all__ = [
     "C_KMS", "rotation_matrix", "rotation_matrix_derivs", "rotate_positions", "los_velocity",
     "spaxel_keys", "sort_by_key", "ssp_cell", "ssp_weights", "interp_templates",
     "rest_index", "doppler_index", "doppler_index_dbeta", "node_decision", "resample_linear",
-    "integral_linear", "bin_edge_indices", "particle_spectra", "cube_raw", "gaussian_weights",
+    "integral_linear", "linear_at", "bin_edge_indices", "particle_spectra", "cube_raw", "gaussian_weights",
     "convolve_axis", "psf_lsf", "forward", "loss", "loss_grad_cube", "adjoint",
     "OracleConfig", "config_from_workload",
 ]
@@ -517,8 +517,8 @@ def loss_grad_cube(cube: np.ndarray, target: np.ndarray, cfg: OracleConfig) -> n
 def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
             idx: Optional[np.ndarray] = None, chunk: int = 512,
             workers: int = 1) -> Dict[str, np.ndarray]:
-    """Analytic gradients of L given G = dL/dC_raw, for particles `idx` (default: all); the
-    resampling of reading 0 only.
+    """Analytic gradients of L given G = dL/dC_raw, for particles `idx` (default: all). For the
+    bin-mean resampling see _adjoint_bin_mean; the bin-centre form is below.
 
     Per particle i in the field (spaxel s), with a_ic = flux_scale m_i J_i w_ic and
     X_ic = sum_j G[s, j] Tlin_c(q_ij):
@@ -532,8 +532,6 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
       dL/dphi_k = sum_i dL/dvlos_i (dR/dphi_k v_i)_z,   dL/dv_i = dL/dvlos_i R[2, :].
     Particles outside the field get zero. Positions get no gradient (binning is piecewise
     constant)."""
-    if cfg.resample != 0:
-        raise NotImplementedError("the adjoint covers the bin-centre resampling only")
     if fw is None:
         fw = forward(p, cfg, with_cube=False)
     R, key, vlos = fw["R"], fw["key"], fw["vlos"]
@@ -567,6 +565,10 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
         v = vlos[ii]
         beta = v / C_KMS
         ja, jz, ta, tz, w, ina, inz = ssp_weights(age, met, la_nodes, mz_nodes)
+        if cfg.resample == 1:
+            _adjoint_bin_mean(cfg, G, key[ii], age, mass, v, ja, jz, ta, tz, w, ina, inz,
+                              out, sel)
+            continue
         q = doppler_index(cfg, v)
         k, valid = node_decision(cfg, v, nl)
         k = np.where(valid, np.minimum(k, nl - 2), 0)
@@ -600,6 +602,60 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
         dbeta = fs * mass * np.sum(g * (dJ[:, None] * Sl + J[:, None] * dS * dq), axis=1)
         out["vlos"][sel] = dbeta / C_KMS
     return _adjoint_angles(p, cfg, R, idx, out)
+
+
+def linear_at(S: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Value of the piecewise-linear interpolant of row i of S at q[i, j], for q in [0, n-1]
+    (clipped there; callers mask what lies outside)."""
+    n = S.shape[1]
+    q = np.clip(q, 0.0, n - 1.0)
+    k = np.minimum(np.floor(q), n - 2).astype(np.int64)
+    t = q - k
+    s0 = np.take_along_axis(S, k, axis=1)
+    s1 = np.take_along_axis(S, k + 1, axis=1)
+    return s0 + t * (s1 - s0)
+
+
+def _adjoint_bin_mean(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, inz, out, sel):
+    """Gradients for the bin-mean resampling (reading 1), particles `sel` of the chunk.
+
+    f_i(j) = B m_i sum_c w_ic I_c(j), B = flux_scale dlam_ssp/dlam, I_c(j) the integral of the
+    linear interpolant of corner c over [q_lo,ij, q_hi,ij] clipped to [0, n-1]. With
+    X_ic = sum_j G[s, j] I_c(j):
+      dL/dm_i    = B sum_c w_ic X_ic,
+      dL/dage_i  = B m_i sum_c (dw_c/dt_a) X_ic / du_a / (age_i ln 10), dL/dmet_i likewise;
+    the integrand does not depend on beta, the limits do (Leibniz rule): with Slin_i the
+    bilinear spectrum's interpolant,
+      dL/dbeta_i = B m_i sum_j G[s, j] (Slin_i(q_hi) dq_hi/dbeta - Slin_i(q_lo) dq_lo/dbeta),
+    an edge outside (0, n-1) being clipped and contributing nothing, and
+    dq/dbeta = -lam_edge / ((1+z)(1+beta)^2 dlam_ssp) at the bin edge lam_edge = lam_j -/+ dlam/2."""
+    T = cfg.ssp_flux
+    nl = T.shape[2]
+    la_nodes, mz_nodes = cfg.log_age_nodes, cfg.met_nodes
+    g = G[keys]                                            # [m, n_tel]
+    q_lo, q_hi = bin_edge_indices(cfg, v)
+    corners = [(ja, jz), (ja, jz + 1), (ja + 1, jz), (ja + 1, jz + 1)]
+    X = np.zeros((keys.shape[0], 4))
+    for c, (a_, z_) in enumerate(corners):
+        X[:, c] = np.sum(g * integral_linear(T[a_, z_], q_lo, q_hi), axis=1)
+    B = cfg.flux_scale * cfg.ssp_lam_step / cfg.tel_step
+    out["mass"][sel] = B * np.sum(w * X, axis=1)
+    dwa = np.stack([-(1 - tz), -tz, (1 - tz), tz], axis=-1)
+    dwz = np.stack([-(1 - ta), (1 - ta), -ta, ta], axis=-1)
+    du_a = la_nodes[ja + 1] - la_nodes[ja]
+    du_z = mz_nodes[jz + 1] - mz_nodes[jz]
+    out["age"][sel] = np.where(ina, B * mass * np.sum(dwa * X, axis=1) / du_a
+                               / (age * math.log(10.0)), 0.0)
+    out["met"][sel] = np.where(inz, B * mass * np.sum(dwz * X, axis=1) / du_z, 0.0)
+    S = interp_templates(T, ja, jz, w)
+    beta = np.asarray(v, dtype=np.float64) / C_KMS
+    lam = cfg.tel_lambda()[None, :]
+    f2 = (1.0 + cfg.z_sys) * (1.0 + beta[:, None]) ** 2 * cfg.ssp_lam_step
+    term = np.zeros_like(q_lo)
+    for q, edge, sgn in ((q_hi, lam + 0.5 * cfg.tel_step, 1.0), (q_lo, lam - 0.5 * cfg.tel_step, -1.0)):
+        inside = (q > 0.0) & (q < nl - 1.0)
+        term += sgn * np.where(inside, linear_at(S, q) * (-edge / f2), 0.0)
+    out["vlos"][sel] = B * mass * np.sum(g * term, axis=1) / C_KMS
 
 
 def _adjoint_part(part):

@@ -596,3 +596,86 @@ def test_adjoint_identities():
     assert np.all(gq["age"][np.arange(p.n) % 3 == 0] == 0)
     assert np.all(gq["met"][np.arange(p.n) % 4 == 0] == 0)
     np.testing.assert_allclose(g["vel"], g["vlos"][None, :] * fw["R"][2][:, None])
+
+
+# ------------------------------------------------------------------ adjoint of the bin mean
+def _bin_mean_setup(seed=31, n=220):
+    ssp = synth.make_ssp(7, 5, 4000.0, 2.0, 220)
+    # bins of 2.7 A (coarser than the 2 A nodes) reaching the red end of the SSP grid, so that
+    # bin edges cross nodes and some intervals are clipped
+    cfg = _cfg(nx=9, ny=8, s=1.0, angles=(math.radians(55), 0.2, 0.3), ssp=ssp,
+               tel=(4010.3, 2.7, 158), resample=1)
+    p = _parts(n, seed, r=4.5)
+    fw = O.forward(p, cfg)
+    G = np.random.default_rng(seed).normal(size=fw["cube_raw"].shape)
+    return p, cfg, fw, G
+
+
+def test_bin_mean_adjoint_matches_central_differences():
+    """The bin-mean value is C1 in the velocity (the integral of a continuous piecewise-linear
+    spectrum), so central differences of the oracle's own forward under the linear functional
+    L = <G, C_raw> pin every gradient, the Leibniz term for the velocity included."""
+    p, cfg, fw, G = _bin_mean_setup()
+    g = O.adjoint(p, cfg, G, fw)
+    key, vlos = fw["key"], fw["vlos"]
+    rng = np.random.default_rng(1)
+    cand = np.flatnonzero(key < cfg.n_spaxels)
+    checked = 0
+    for i in rng.permutation(cand)[:40]:
+        def spec(**kw):
+            q = p.subset(np.array([i]))
+            vv = np.array([vlos[i]])
+            if "vlos" in kw:
+                vv = np.array([kw.pop("vlos")])
+            q = synth.Particles(*[np.asarray(kw.get(f, getattr(q, f)), dtype=np.float64)
+                                  if f in kw else getattr(q, f).astype(np.float64)
+                                  for f in synth.Particles.FIELDS])
+            return O.particle_spectra(q, np.array([0]), vv, cfg)[0]
+
+        m, a, z, v = float(p.mass[i]), float(p.age[i]), float(p.met[i]), float(vlos[i])
+        la, mz = cfg.log_age_nodes, cfg.met_nodes
+        if np.min(np.abs(la - math.log10(a))) < 1e-4 or np.min(np.abs(mz - z)) < 1e-4:
+            continue
+        for name, h, kw_p, kw_m in (
+                ("mass", 1e-6 * m, dict(mass=[m + 1e-6 * m]), dict(mass=[m - 1e-6 * m])),
+                ("age", 1e-6, dict(age=[a + 1e-6]), dict(age=[a - 1e-6])),
+                ("met", 1e-6, dict(met=[z + 1e-6]), dict(met=[z - 1e-6])),
+                ("vlos", 1e-3, dict(vlos=v + 1e-3), dict(vlos=v - 1e-3))):
+            fd = float(np.dot(G[key[i]], spec(**kw_p) - spec(**kw_m))) / (2 * h)
+            an = g[name][i]
+            scale = max(abs(fd), 1e-3 * np.abs(g[name]).max())
+            assert abs(an - fd) <= 2e-5 * scale, (name, i, an, fd)
+        checked += 1
+    assert checked >= 25
+
+
+def test_bin_mean_adjoint_identities():
+    """Euler: the raw cube is homogeneous of degree 1 in the masses, so sum m dL/dm = <G, C_raw>;
+    the velocity gradient of a particle whose bins all lie inside the grid is the Leibniz sum
+    over its bin edges, which telescopes: shifting a spectrum inside the band moves no flux out of
+    it, so sum_j dL/dbeta with G = 1 on its spaxel only counts the two ends of the band."""
+    p, cfg, fw, G = _bin_mean_setup(seed=7)
+    g = O.adjoint(p, cfg, G, fw)
+    lhs = np.sum(p.mass.astype(float) * g["mass"])
+    rhs = np.vdot(G, fw["cube_raw"])
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+    # G = 1 everywhere: L is the band-integrated flux (times dlam); interior edges cancel in pairs
+    ones = np.ones_like(G)
+    g1 = O.adjoint(p, cfg, ones, fw)
+    key, vlos = fw["key"], fw["vlos"]
+    i = int(np.flatnonzero(key < cfg.n_spaxels)[0])
+    ssp_w = O.ssp_weights(p.age[i:i + 1].astype(float), p.met[i:i + 1].astype(float),
+                          cfg.log_age_nodes, cfg.met_nodes)
+    S = O.interp_templates(cfg.ssp_flux, ssp_w[0], ssp_w[1], ssp_w[4])
+    q_lo, q_hi = O.bin_edge_indices(cfg, vlos[i:i + 1])
+    beta = vlos[i] / O.C_KMS
+    f2 = (1.0 + cfg.z_sys) * (1.0 + beta) ** 2 * cfg.ssp_lam_step
+    B = cfg.flux_scale * cfg.ssp_lam_step / cfg.tel_step
+    ends = 0.0
+    nl = cfg.ssp_flux.shape[2]
+    for q, lam_e, sgn in ((q_hi[0, -1], cfg.tel_lambda()[-1] + 0.5 * cfg.tel_step, 1.0),
+                          (q_lo[0, 0], cfg.tel_lambda()[0] - 0.5 * cfg.tel_step, -1.0)):
+        if 0.0 < q < nl - 1:
+            ends += sgn * float(O.linear_at(S, np.array([[q]]))[0, 0]) * (-lam_e / f2)
+    expect = B * float(p.mass[i]) * ends / O.C_KMS
+    assert abs(g1["vlos"][i] - expect) <= 1e-9 * max(abs(expect), 1e-30) + 1e-12 * abs(g1["vlos"]).max()
