@@ -256,7 +256,7 @@ def main():
     flop_per_unit = BIN_FLOP_PER_UNIT if w.resample else CUBE_FLOP_PER_UNIT
     achieved = flop_per_unit * units / (cube_kernel_ms * 1e-3) / 1e12
     gather_tbs = CUBE_GATHER_BYTES_PER_UNIT * units / (cube_kernel_ms * 1e-3) / 1e12
-    digest = source_digest("k_cube.hip")
+    digest = source_digest("k_cube.hip", "rubix_internal.h")
     traffic = traffic_from_profile(digest) if args.variant == "centre" else None
     rot_gbs = ROTBIN_BYTES_PER_PARTICLE * w.particles.n / (st[0] * 1e-3) / 1e9
     psf_gbs = PSF_BYTES_PER_VOXEL * w.n_spaxels * w.n_tel / (st[2] * 1e-3) / 1e9
@@ -320,7 +320,7 @@ def main():
     out["stages_hbm"]["noise_frac"] = noise_gbs / PEAK_HBM_GBS
     del noisy
     err(f"noise {noise_ms:.3f} ms ({noise_gbs:.0f} GB/s)")
-    if not args.no_backward and not w.resample:     # (the bin mean has no adjoint)
+    if not args.no_backward:
         # gradient pass beside the forward: adjoint PSF/LSF of a seeded dL/dcube, then the
         # per-particle adjoint (mass, age, [M/H], v_los, velocities, angles)
         gen = torch.Generator(device=dev).manual_seed(7)

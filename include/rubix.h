@@ -111,7 +111,7 @@ typedef struct {
   float      *cube_raw;         /* [ny][nx][tel.n] written by rubix_cube                       */
   float      *cube;             /* [ny][nx][tel.n] optional; rubix_psf_lsf may write it        */
   int32_t     resample;         /* 0: bin-centre sampling (below); 1: bin mean (flux conserving,
-                                   linear grids only; no adjoint)                               */
+                                   linear grids only)                                           */
   int32_t     reserved;         /* 0                                                            */
 } rubix_job;
 
@@ -170,6 +170,9 @@ int rubix_psf_lsf(const rubix_job *jobs, int n_jobs, const float *const *in, flo
  *   spaxel assignment held fixed (binning is piecewise constant).
  * Particles outside the field get 0. Derivatives at SSP nodes / wavelength nodes take the
  * right-hand cell; clamped age or metallicity gives 0 along that axis. Positions get no gradient.
+ * Bin-mean jobs (resample = 1): the integrand does not depend on beta, the bin's limits do, so
+ * d_vlos is the Leibniz sum over the bin edges of Slin at the edge times its d q/d beta; an edge
+ * clipped to the SSP grid's end (q <= 0 or q >= n-1) contributes nothing.
  * Reads key, perm, seg_off, vlos from rubix_rotate_bin. Per-particle dot products are reduced in
  * FP64 in a fixed order (deterministic). */
 int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,

@@ -26,6 +26,16 @@ __global__ __launch_bounds__(256) void k_bintab(const Table *__restrict__ T) {
     const JobDev &J = jobs[jj];
     const int jb = (int)((vb - J.vb_start[K_BINTAB]) * 256 + threadIdx.x);
     if (jb >= J.n_tel) continue;
+    if (J.resample) {
+      // the bin's two edges, as the forward bin-mean kernel computes them
+      int qlo, qhi;
+      float flo, fhi, llo, lhi;
+      bin_edge(J, S, jb, 0, qlo, flo, llo);
+      bin_edge(J, S, jb, 1, qhi, fhi, lhi);
+      J.bintab[jb] = make_float4(__int_as_float(qlo), flo, llo, 0.f);
+      J.bintab[J.n_tel + jb] = make_float4(__int_as_float(qhi), fhi, lhi, 0.f);
+      continue;
+    }
     // as the forward kernel's split index: Q and the factor of the Doppler term (lambda or 1)
     double Q;
     float lamf;
@@ -165,6 +175,87 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
   }
 }
 
+// Bin-mean jobs. A bin's value is the integral of the particle's linear interpolants over the
+// bin's rest-frame node interval [q_lo, q_hi] clipped to [0, n-1], so the dots become
+//   s_m, s_a, s_z = sum_j G[s,j] x (integral over bin j of Slin, of its age direction, of its
+//                   metallicity direction),
+//   Y = sum_j G[s,j] (lam_hi Slin(q_hi) [q_hi inside] - lam_lo Slin(q_lo) [q_lo inside]),
+// Y holding the Leibniz terms of the moving limits (an edge clipped to the grid's end does not
+// move, so it contributes nothing; "inside" is 0 < q < n-1). One wave per particle; lane l takes
+// bins l, l+64, ... and walks each bin's node segments with direct gathers of the four corner
+// rows (any number of segments per bin). Where both edges are inside, lam_hi S_hi - lam_lo S_lo
+// is formed as lam_lo (S_hi - S_lo) + dlam S_hi, with S_hi - S_lo summed from the segments'
+// slopes, so a bin's term is not a difference of two nearly equal products.
+__global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ T) {
+  const SspDev &S = T->h.ssp;
+  const JobDev *jobs = table_jobs(T);
+  const float *__restrict__ flux = S.flux;
+  const int nl = S.n_lam;
+  const int o1 = nl, o2 = S.n_met * nl, o3 = o2 + nl;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_BWDB]; vb += gridDim.x) {
+    const int jj = find_job(T, K_BWDB, vb);
+    const JobDev &J = jobs[jj];
+    const int64_t pbase = (vb - J.vb_start[K_BWDB]) * kBwdParticles;
+    const int n_in = J.seg_off[J.n_s];
+    const float dlam = (float)J.tel_step;
+    for (int q = w; q < kBwdParticles; q += 4) {
+      const int64_t p = pbase + q;
+      if (p >= n_in) break;
+      const PrepRec r = J.prep[p];
+      const float *__restrict__ G = J.grad_raw + (int64_t)r.spaxel * J.n_tel;
+      const float w0 = r.a[0], w1 = r.a[1], w2 = r.a[2], w3 = r.a[3];
+      const float ta = w2 + w3, tz = w1 + w3;
+      const int row = prep_row(r.row);
+      float sm = 0.f, sa = 0.f, sz = 0.f, y = 0.f;
+      for (int jb = lane; jb < J.n_tel; jb += 64) {
+        const float4 lo = J.bintab[jb], hi = J.bintab[J.n_tel + jb];
+        const float gj = G[jb];
+        const float tl = fmaf(-lo.z, r.g, lo.y), th = fmaf(-hi.z, r.g, hi.y);
+        int klo = __float_as_int(lo.x) + floor_i32(tl), khi = __float_as_int(hi.x) + floor_i32(th);
+        float a = __builtin_amdgcn_fractf(tl), b = __builtin_amdgcn_fractf(th);
+        const bool in_lo = (klo > 0 || (klo == 0 && a > 0.f)) && klo < nl - 1;
+        const bool in_hi = (khi > 0 || (khi == 0 && b > 0.f)) && khi < nl - 1;
+        clip_node(klo, a, nl);
+        clip_node(khi, b, nl);
+        if (klo > khi || (klo == khi && !(a < b))) continue;   // empty: both edges clipped together
+        float Is = 0.f, Ia = 0.f, Iz = 0.f, D = 0.f, s_lo = 0.f, s_hi = 0.f;
+        for (int k = klo; k <= khi; ++k) {
+          const float *f = flux + row + k;
+          const float p0 = f[0], q0 = f[1], p1 = f[o1], q1 = f[o1 + 1];
+          const float p2 = f[o2], q2 = f[o2 + 1], p3 = f[o3], q3 = f[o3 + 1];
+          const float x = k == klo ? a : 0.f, xe = k == khi ? b : 1.f;
+          const float P = w0 * p0 + w1 * p1 + w2 * p2 + w3 * p3;
+          const float dS = w0 * (q0 - p0) + w1 * (q1 - p1) + w2 * (q2 - p2) + w3 * (q3 - p3);
+          // age and metallicity directions at the two nodes, differences taken before the sums
+          const float ap = (1.f - tz) * (p2 - p0) + tz * (p3 - p1);
+          const float aq = (1.f - tz) * (q2 - q0) + tz * (q3 - q1);
+          const float zp = (1.f - ta) * (p1 - p0) + ta * (p3 - p2);
+          const float zq = (1.f - ta) * (q1 - q0) + ta * (q3 - q2);
+          Is += seg_integral(P, P + dS, x, xe);
+          Ia += seg_integral(ap, aq, x, xe);
+          Iz += seg_integral(zp, zq, x, xe);
+          D = fmaf(dS, xe - x, D);
+          s_lo = k == klo ? fmaf(a, dS, P) : s_lo;
+          s_hi = k == khi ? fmaf(b, dS, P) : s_hi;
+        }
+        float e;
+        if (in_lo && in_hi) e = fmaf(lo.z, D, dlam * s_hi);
+        else e = (in_hi ? hi.z * s_hi : 0.f) - (in_lo ? lo.z * s_lo : 0.f);
+        sm = fmaf(gj, Is, sm);
+        sa = fmaf(gj, Ia, sa);
+        sz = fmaf(gj, Iz, sz);
+        y = fmaf(gj, e, y);
+      }
+      const double Sm = wave_sum(sm), Sa = wave_sum(sa), Sz = wave_sum(sz), Y = wave_sum(y);
+      if (lane == 0) {
+        double *d = J.dots + p * 4;
+        d[0] = Sm; d[1] = Sa; d[2] = Sz; d[3] = Y;
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ int cell_of_b(const double *thr, int n, double x) {
   if (!(x > thr[0])) return 0;
   if (x >= thr[n - 1]) return n - 2;
@@ -202,15 +293,17 @@ __global__ __launch_bounds__(kFinThreads) void k_bwd_final(const Table *__restri
         const double sm = X[0], sa = X[1], sz = X[2], Y = X[3];
         const double beta = v / kCkmsB;
         const double opz = 1.0 + J.z_sys;
-        const double jac = 1.0 / (opz * (1.0 + beta));
+        // bin-centre sampling: the Jacobian 1/((1+z)(1+beta)) scales the sample and moves with
+        // beta; the bin mean carries the constant dlam_ssp/dlam_tel instead
+        const double jac = J.resample ? J.bin_scale : 1.0 / (opz * (1.0 + beta));
         const double fs = J.flux_scale;
         const double A = fs * m * jac;
         gm = (float)(fs * jac * sm);
         if (in_a) ga = (float)(A * sa / (S.log_age[ja + 1] - S.log_age[ja]) / (age * 2.302585092994046));
         if (in_z) gz = (float)(A * sz / (S.met[jz + 1] - S.met[jz]));
-        const double dJ = -jac / (1.0 + beta);
+        const double dJ = J.resample ? 0.0 : -jac / (1.0 + beta);
         // dq/dbeta per unit of the bin factor accumulated in Y (lambda on linear grids, 1 on
-        // log grids, where q = Q - ln(1+beta)/dln)
+        // log grids, where q = Q - ln(1+beta)/dln; the edge wavelength for the bin mean)
         const double dq = J.log_lambda ? -1.0 / ((1.0 + beta) * S.lam_step)
                                        : -1.0 / (opz * (1.0 + beta) * (1.0 + beta) * S.lam_step);
         const double dbeta = fs * m * (dJ * sm + jac * dq * Y);
@@ -291,6 +384,7 @@ hipError_t launch_backward(const Table *dt, const TableHeader &h, int cap, hipSt
   int g;
   if ((g = grid_for(h.total[K_BINTAB], cap))) hipLaunchKernelGGL(k_bintab, dim3(g), dim3(256), 0, s, dt);
   if ((g = grid_for(h.total[K_BWD], cap))) hipLaunchKernelGGL(k_bwd_dots, dim3(g), dim3(256), 0, s, dt);
+  if ((g = grid_for(h.total[K_BWDB], cap))) hipLaunchKernelGGL(k_bwd_dots_bin, dim3(g), dim3(256), 0, s, dt);
   if ((g = grid_for(h.total[K_FIN], cap))) hipLaunchKernelGGL(k_bwd_final, dim3(g), dim3(kFinThreads), 0, s, dt);
   if ((g = grid_for(h.total[K_ANG], cap))) hipLaunchKernelGGL(k_bwd_angles, dim3(g), dim3(256), 0, s, dt);
   return hipGetLastError();

@@ -230,14 +230,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t flux_rsrc(const SspDev &S) {
   return __builtin_amdgcn_make_buffer_rsrc((void *)S.flux, (short)0, (int)bytes, 0x00020000);
 }
 
-// floor(t) as an integer in one instruction (floor-and-convert); t is finite and far inside the
-// int range here.
-__device__ __forceinline__ int floor_i32(float t) {
-  int r;
-  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(t));
-  return r;
-}
-
 __device__ __forceinline__ float ldf(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + off, 0, 0));
 }
@@ -515,25 +507,6 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
 // and no bin spans more than two segments; otherwise the particle's segments are gathered from
 // the template grid directly (both cases give the same sum of the same terms).
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ float seg_integral(float s0, float s1, float x, float y) {
-  return fmaf(s0, y - x, 0.5f * (s1 - s0) * (y * y - x * x));
-}
-
-// Node interval and fraction of an edge, clipped to [0, n-1] as (k, t) with k in [0, n-2].
-__device__ __forceinline__ void clip_node(int &k, float &t, int nl) {
-  if (k < 0) { k = 0; t = 0.f; }
-  else if (k > nl - 2) { k = nl - 2; t = 1.f; }
-}
-
-__device__ __forceinline__ void edge_index(const JobDev &J, const SspDev &S, double lam, int &qi,
-                                           float &qf, float &lamf) {
-  const double Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
-  const double Qfl = floor(Q);
-  qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
-  qf = (float)(Q - Qfl);
-  lamf = (float)lam;
-}
-
 __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restrict__ T) {
   __shared__ float slots[kCubeThreads / 64][64];
   const SspDev &S = T->h.ssp;
@@ -560,11 +533,10 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restri
     const bool act = (lane < kBinWaveBins) && (jb < J.n_tel);
     // lanes past the wave's bins take its last bin, so the node span stays that of the bins
     const int jc = min(jw + min(lane, kBinWaveBins - 1), J.n_tel - 1);
-    const double lam = J.tel_start + (double)jc * J.tel_step;
     int qlo, qhi;
     float flo, fhi, llo, lhi;
-    edge_index(J, S, lam - 0.5 * J.tel_step, qlo, flo, llo);
-    edge_index(J, S, lam + 0.5 * J.tel_step, qhi, fhi, lhi);
+    bin_edge(J, S, jc, 0, qlo, flo, llo);
+    bin_edge(J, S, jc, 1, qhi, fhi, lhi);
     const PrepRec *prep = J.prep;
     float acc = 0.f, tot = 0.f;
     int since = 0;

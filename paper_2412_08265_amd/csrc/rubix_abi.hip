@@ -139,7 +139,7 @@ static JobSizes sizes_of(const rubix_job &j) {
   size_t psf_end = al(4ull * z.cube_elems);
   // backward region (prep at the same offset as in the cube region)
   o = al(sizeof(PrepRec) * (size_t)z.n);
-  z.o_bintab = o; o += al(16ull * z.n_tel);
+  z.o_bintab = o; o += al(32ull * z.n_tel);       // two edges per bin for bin-mean jobs
   z.o_dots = o; o += al(32ull * z.n);
   z.o_ang = o; o += al(24ull * std::max(1, z.n_fin_blocks));
   size_t bwd_end = o;
@@ -201,8 +201,6 @@ static int validate_jobs(const rubix_job *jobs, int n_jobs, Call call) {
       return fail(RUBIX_EINVAL, "job %d: resample must be 0 or 1", k);
     if (j.resample == 1 && j.tel.log_spaced)
       return fail(RUBIX_EINVAL, "job %d: bin-mean resampling needs linear grids", k);
-    if (j.resample == 1 && call == CALL_BWD)
-      return fail(RUBIX_EINVAL, "job %d: no adjoint for bin-mean resampling", k);
     if (!(j.z_sys > -1.0) || !isfinite(j.z_sys)) return fail(RUBIX_EINVAL, "job %d: z_sys must be > -1", k);
     if (!isfinite(j.flux_scale)) return fail(RUBIX_EINVAL, "job %d: flux_scale not finite", k);
     for (int a = 0; a < 3; ++a)
@@ -434,11 +432,12 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
         /*K_PSFX*/ n_psfx,
         /*K_COPY*/ n_copy,
         /*K_BINTAB*/ cdiv(z.n_tel, 256),
-        /*K_BWD*/ cdiv(z.n, kBwdParticles),
+        /*K_BWD*/ j.resample ? 0 : cdiv(z.n, kBwdParticles),
         /*K_FIN*/ z.n_fin_blocks,
         /*K_ANG*/ 1,
         /*K_VB*/ cdiv(z.n, kVbParticles),
         /*K_CUBEB*/ j.resample ? (int64_t)z.n_tiles_b * z.n_chunk_ub : 0,
+        /*K_BWDB*/ j.resample ? cdiv(z.n, kBwdParticles) : 0,
     };
     for (int q = 0; q < NK; ++q) {
       d.vb_start[q] = start[q];

@@ -52,6 +52,7 @@ enum Kind : int {
   K_ANG,       // one per job
   K_VB,        // per kVbParticles particles (Doppler bounds for the cube kernel)
   K_CUBEB,     // per (lambda tile of kBinTL bins, chunk slot): bin-mean resampling jobs
+  K_BWDB,      // per kBwdParticles sorted particles of a bin-mean job (K_BWD covers the others)
   NK
 };
 
@@ -135,7 +136,8 @@ struct JobDev {
                         // slope| of the job, [3] nonzero if some particle's span does not fit
   float *partial;       // [n_comb_slots_ub][n_tel]
   float *tmp_cube;      // [cube_elems]
-  float4 *bintab;       // [n_tel]: (node index integer part as int bits, frac, lambda, 0)
+  float4 *bintab;       // [n_tel]: (node index integer part as int bits, frac, lambda, 0) of
+                        // each bin centre; bin-mean jobs: [2][n_tel], lower then upper edges
   double *dots;         // [n][4]: s_m, s_a, s_z, Y per sorted particle
   double *ang_part;     // [n_fin_blocks][3]
   int64_t vb_start[NK];
@@ -171,6 +173,40 @@ __device__ inline int find_job(const Table *t, int kind, int64_t vb) {
     if (jobs[mid].vb_start[kind] <= vb) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+// floor(t) as an integer in one instruction (floor-and-convert); t is finite and far inside the
+// int range here.
+__device__ __forceinline__ int floor_i32(float t) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(t));
+  return r;
+}
+
+// Bin-mean resampling helpers, shared by the forward sum and its adjoint so both see the same
+// bin edges. Integral over a node segment of the linear interpolant between s0 and s1, from
+// fraction x to fraction y.
+__device__ __forceinline__ float seg_integral(float s0, float s1, float x, float y) {
+  return fmaf(s0, y - x, 0.5f * (s1 - s0) * (y * y - x * x));
+}
+
+// Node interval and fraction of an edge, clipped to [0, n-1] as (k, t) with k in [0, n-2].
+__device__ __forceinline__ void clip_node(int &k, float &t, int nl) {
+  if (k < 0) { k = 0; t = 0.f; }
+  else if (k > nl - 2) { k = nl - 2; t = 1.f; }
+}
+
+// Rest-frame node index of telescope bin jb's lower (hi = 0) or upper (hi = 1) edge at zero
+// velocity, split into its integer part qi and FP32 fraction qf, and the edge wavelength lamf
+// (the factor of the Doppler term: a particle's index is qi + qf - lamf * g). Linear grids.
+__device__ __forceinline__ void bin_edge(const JobDev &J, const SspDev &S, int jb, int hi, int &qi,
+                                         float &qf, float &lamf) {
+  const double lam = J.tel_start + (double)jb * J.tel_step + (hi ? 0.5 : -0.5) * J.tel_step;
+  const double Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
+  const double Qfl = floor(Q);
+  qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
+  qf = (float)(Q - Qfl);
+  lamf = (float)lam;
 }
 
 // Launchers (one per translation unit); grid = number of blocks (persistent if < total).

@@ -202,10 +202,11 @@ def test_resample_mode_is_validated(lib):
     j.tel.log_spaced = 0
     ssp, keep = _ssp_c([-1, 0, 1], [-2, 0])
     ptrs = (ctypes.c_void_p * 1)(0x1000)
-    # the adjoint refuses bin-mean jobs before any device work
+    # the adjoint validates the mode before any device work
+    j.resample = 2
     rc = lib.rubix_cube_backward(_arr(j), 1, ctypes.byref(ssp), ptrs, ptrs, ptrs, ptrs, ptrs,
                                  None, 0x1000, 0x1000, 1 << 40, None)
-    assert rc == _lib.RUBIX_EINVAL and b"bin-mean" in lib.rubix_last_error()
+    assert rc == _lib.RUBIX_EINVAL and b"resample" in lib.rubix_last_error()
 
 
 def test_product_path_never_touches_the_oracle():

@@ -127,6 +127,31 @@ def test_seeded_gradient_on_a_coarse_telescope_grid():
     _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False)
 
 
+@pytest.mark.parametrize("ratio,n_tel,seed", [(1.0, 1010, 43), (2.3, 440, 47), (0.45, 2200, 53)])
+def test_bin_mean_seeded_gradient(ratio, n_tel, seed):
+    """Adjoint of the bin-mean resampling: the integrals of the corner interpolants over each
+    bin's node interval, and for the velocity the Leibniz terms of the moving bin edges (an edge
+    clipped to the grid's end gives none). Telescope bins of 1.0, 2.3 (several node segments per
+    bin) and 0.45 (bins inside one segment) SSP node spacings, with the band running 5 bins past
+    both ends of the SSP grid, so clipped edges of both kinds occur. Oracle on every particle
+    and FP64 finite differences."""
+    p = synth.make_galaxy(3000, seed)
+    ssp = synth.cached_ssp(12, 6, 3600.0, 3.8, 1000)
+    step = ratio * 3.8
+    w = synth.Workload(f"grad-binmean-{ratio}", p, (55.0, 12.0, 20.0), 14, 12, 2.0,
+                       3600.0 - 5 * step, step, n_tel, ssp, psf_sigma_spx=1.2,
+                       lsf_sigma_A=6.0, z_sys=0.001, resample=1)
+    cfg = O.config_from_workload(w)
+    assert cfg.resample == 1
+    fo = O.forward(w.particles, cfg)
+    rng = np.random.default_rng(seed)
+    G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
+    _, g = _gpu_grads(w, G)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo)
+    _compare(g, ref, 2e-5, f"bin-mean x{ratio} seeded-G")
+    _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False, h_vlos=1e-2)
+
+
 def _fd_delta_L(cfg, G, s, dplus, dminus, quadratic=True):
     """L(+) - L(-) when one particle of spaxel s changes its spectrum by d+/d- (FP64).
     For the loss L = |A C - T|^2 / 2 with G = A(A C - T):
@@ -146,7 +171,11 @@ def _fd_delta_L(cfg, G, s, dplus, dminus, quadratic=True):
     return float(np.dot(dplus - dminus, G[s])) + 0.5 * P2 * (np.dot(Lp, Lp) - np.dot(Lm, Lm))
 
 
-def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True):
+def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-4):
+    """FP64 central differences of the oracle's particle spectra against the GPU gradient, on up
+    to n_check in-field particles away from SSP nodes. h_vlos is the velocity step in km/s: the
+    oracle's bin mean is a difference of prefix sums over the node grid, whose rounding needs a
+    larger step than bin-centre sampling does."""
     p = w.particles
     key, vlos = fo["key"], fo["vlos"]
     la, mz = cfg.log_age_nodes, cfg.met_nodes
@@ -178,7 +207,7 @@ def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True):
         for k, h, mk in (("mass", 1e-6 * m, lambda d: spec("mass", m + d)),
                          ("age", 1e-6, lambda d: spec("age", a + d)),
                          ("met", 1e-6, lambda d: spec("met", z + d)),
-                         ("vlos", 1e-4, lambda d: spec(vv=v + d))):
+                         ("vlos", h_vlos, lambda d: spec(vv=v + d))):
             dl = _fd_delta_L(cfg, G, int(key[i]), mk(h) - base, mk(-h) - base, quadratic)
             fd = dl / (2 * h)
             rel = abs(gpu[k][i] - fd) / abs(fd)
