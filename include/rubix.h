@@ -183,10 +183,12 @@ int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
 
 /* Noise (Sec. 3 ends with realistic noise; the paper gives no model). Reading taken: every voxel
  * v of the cube gets independent Gaussian noise of variance gain * max(C_v, 0) + sigma_floor^2.
- * The deviate of voxel v (C order in [ny][nx][tel.n]) is eps = sqrt(-2 ln u0) cos(2 pi u1) with
- * u = (x + 1/2) 2^-32 from the first two outputs x0, x1 of Philox-4x32-10 (Salmon et al., SC
- * 2011) keyed by `seed` (low word first) with counter (v_lo, v_hi, stream, 0), in FP64; the
- * noisy value is rounded to FP32 once. It depends only on (seed, stream, v, C_v). */
+ * Voxels v = 4b .. 4b+3 (C order in [ny][nx][tel.n]) take their deviates from one block of
+ * Philox-4x32-10 (Salmon et al., SC 2011) keyed by `seed` (low word first) with counter
+ * (b_lo, b_hi, stream, 0): its outputs x0..x3 give u = (x + 1/2) 2^-32 and, by Box-Muller in
+ * FP64, eps(4b) = r0 cos(2 pi u1), eps(4b+1) = r0 sin(2 pi u1), eps(4b+2) = r1 cos(2 pi u3),
+ * eps(4b+3) = r1 sin(2 pi u3), r0 = sqrt(-2 ln u0), r1 = sqrt(-2 ln u2); the noisy value is
+ * rounded to FP32 once. It depends only on (seed, stream, v, C_v). */
 typedef struct {
   uint64_t seed;
   uint32_t stream;        /* independent sequences for one seed (e.g. one per observation)     */

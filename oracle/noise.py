@@ -6,9 +6,12 @@ variance  gain * max(C, 0) + sigma_floor^2  (a photon term in the Gaussian limit
 
 The normal deviates come from a counter-based generator so that any implementation draws the
 same numbers: Philox-4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
-as easy as 1, 2, 3", SC 2011), key (seed_lo, seed_hi), counter (voxel_lo, voxel_hi, stream, 0).
-Of its four 32-bit outputs x0, x1 the first two give u = (x + 1/2) 2^-32 in (0, 1), and the
-Box-Muller transform eps = sqrt(-2 ln u0) cos(2 pi u1) (FP64) a standard normal deviate.
+as easy as 1, 2, 3", SC 2011), key (seed_lo, seed_hi), counter (b_lo, b_hi, stream, 0) for the
+block b of voxels 4b .. 4b+3. Its four 32-bit outputs x0..x3 give u_k = (x_k + 1/2) 2^-32 in
+(0, 1), and the Box-Muller transform (Box and Muller 1958) turns each pair (u0, u1), (u2, u3)
+into two independent standard normal deviates, in FP64:
+  eps(4b)   = r0 cos(2 pi u1),  eps(4b+1) = r0 sin(2 pi u1),  r0 = sqrt(-2 ln u0),
+  eps(4b+2) = r1 cos(2 pi u3),  eps(4b+3) = r1 sin(2 pi u3),  r1 = sqrt(-2 ln u2).
 """
 from __future__ import annotations
 
@@ -41,14 +44,22 @@ def philox4x32_10(ctr, key):
 
 
 def normals(n: int, seed: int, stream: int) -> np.ndarray:
-    """Standard normal deviates for voxels 0..n-1 of one stream, FP64."""
-    i = np.arange(n, dtype=np.uint64)
-    x0, x1, _, _ = philox4x32_10((i & MASK32, i >> np.uint64(32), np.full(n, stream, np.uint64),
-                                  np.zeros(n, np.uint64)),
-                                 (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
-    u0 = (x0.astype(np.float64) + 0.5) * 2.0 ** -32
-    u1 = (x1.astype(np.float64) + 0.5) * 2.0 ** -32
-    return np.sqrt(-2.0 * np.log(u0)) * np.cos(2.0 * np.pi * u1)
+    """Standard normal deviates for voxels 0..n-1 of one stream, FP64 (one Philox block per
+    four voxels; the last block's unused deviates are dropped)."""
+    nb = (n + 3) // 4
+    b = np.arange(nb, dtype=np.uint64)
+    x = philox4x32_10((b & MASK32, b >> np.uint64(32), np.full(nb, stream, np.uint64),
+                       np.zeros(nb, np.uint64)),
+                      (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+    u = [(xk.astype(np.float64) + 0.5) * 2.0 ** -32 for xk in x]
+    r0 = np.sqrt(-2.0 * np.log(u[0]))
+    r1 = np.sqrt(-2.0 * np.log(u[2]))
+    eps = np.empty((nb, 4))
+    eps[:, 0] = r0 * np.cos(2.0 * np.pi * u[1])
+    eps[:, 1] = r0 * np.sin(2.0 * np.pi * u[1])
+    eps[:, 2] = r1 * np.cos(2.0 * np.pi * u[3])
+    eps[:, 3] = r1 * np.sin(2.0 * np.pi * u[3])
+    return eps.ravel()[:n]
 
 
 def add_noise(cube: np.ndarray, seed: int, stream: int, gain: float,

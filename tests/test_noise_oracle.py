@@ -38,6 +38,25 @@ def test_normals_are_standard_normal():
     assert np.array_equal(e[:1000], N.normals(1000, seed=2024, stream=3))
 
 
+def test_normals_of_one_block_are_independent_and_prefix_stable():
+    """The four deviates of a Philox block (two Box-Muller pairs) are uncorrelated with each
+    other and with the next block's; their squares sum to -2 ln u per pair (the pair's radius).
+    Drawing fewer voxels returns a prefix of the same sequence."""
+    e = N.normals(400_000, seed=11, stream=0).reshape(-1, 4)
+    c = np.corrcoef(np.concatenate([e[:-1], e[1:]], axis=1).T)
+    off = c[~np.eye(8, dtype=bool)]
+    assert np.abs(off).max() < 0.01
+    # the pair (cos, sin) of one radius: e0^2 + e1^2 = r0^2 = -2 ln u0 is Exp(1/2) distributed
+    r2 = e[:, 0] ** 2 + e[:, 1] ** 2
+    assert scipy.stats.kstest(r2[:50_000], "expon", args=(0, 2)).pvalue > 1e-4
+    x = N.philox4x32_10((np.arange(5, dtype=np.uint64), np.zeros(5, np.uint64),
+                         np.zeros(5, np.uint64), np.zeros(5, np.uint64)), (11, 0))
+    u0 = (x[0].astype(np.float64) + 0.5) * 2.0 ** -32
+    np.testing.assert_allclose(r2[:5], -2.0 * np.log(u0), rtol=1e-13)
+    for n in (1, 2, 3, 5, 7, 4001):
+        assert np.array_equal(N.normals(n, 11, 0), e.ravel()[:n])
+
+
 def test_noise_model_moments():
     rng = np.random.default_rng(0)
     cube = np.where(rng.uniform(size=(40, 50, 200)) < 0.5, 0.0, 37.0)
