@@ -84,6 +84,14 @@ __device__ __forceinline__ void bwd_bin(float w0, float w1, float w2, float w3, 
   y = fmaf(g * lamf, dS, y);
 }
 
+__device__ __forceinline__ float4 ld_bintab(__amdgpu_buffer_rsrc_t rt, int j) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rt, j * 16, 0, 0));
+}
+
+__device__ __forceinline__ float ld_grad(__amdgpu_buffer_rsrc_t rg, int j) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, j * 4, 0, 0));
+}
+
 // One wave per particle, walking the telescope grid in windows of kCubeWaveBins bins (lane l
 // takes bin jw + l; lanes 62 and 63 only stage). Where the particle's span fits a window (the
 // forward kernel's decision, carried in the record's sign) and the window's 64 nodes n0 .. n0+63
@@ -98,7 +106,8 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
   const float *__restrict__ flux = S.flux;
   const int nl = S.n_lam;
   const int o1 = nl, o2 = S.n_met * nl, o3 = o2 + nl;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is wave-uniform: say so, so that per-particle values live in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const uint32_t fbytes = (uint32_t)S.n_age * (uint32_t)S.n_met * (uint32_t)nl * 4u;
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void *)flux, (short)0, (int)fbytes, 0x00020000);
@@ -115,19 +124,34 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
       const int64_t p = pbase + q;
       if (p >= n_in) break;
       const PrepRec r = J.prep[p];
-      const float *__restrict__ G = J.grad_raw + (int64_t)r.spaxel * J.n_tel;
+      // the record is the wave's (a vector load of one address): its integers in scalar registers
+      const int spx = __builtin_amdgcn_readfirstlane(r.spaxel);
+      const int rrow = __builtin_amdgcn_readfirstlane(r.row);
+      const float *__restrict__ G = J.grad_raw + (int64_t)spx * J.n_tel;
       const float w0 = r.a[0], w1 = r.a[1], w2 = r.a[2], w3 = r.a[3];
       const float ta = w2 + w3, tz = w1 + w3;   // bilinear fractions recovered from the weights
-      const bool fits = r.row >= 0;
-      const int row = prep_row(r.row);
+      const bool fits = rrow >= 0;
+      const int row = prep_row(rrow);
       float sm = 0.f, sa = 0.f, sz = 0.f, y = 0.f;
+      // lanes past a window's bins take its last bin, so their nodes stay in the window; the bin
+      // table entry and gradient of the next window are loaded while this window's template rows
+      // are (the index is clamped, so the load past the last window re-reads the last bin)
+      // (buffer loads, which complete in order with the row loads, so waiting for the rows does
+      // not wait for them)
+      const __amdgpu_buffer_rsrc_t rt =
+          __builtin_amdgcn_make_buffer_rsrc((void *)J.bintab, (short)0, J.n_tel * 16, 0x00020000);
+      const __amdgpu_buffer_rsrc_t rg =
+          __builtin_amdgcn_make_buffer_rsrc((void *)G, (short)0, J.n_tel * 4, 0x00020000);
+      const int lb_lane = min(lane, kCubeWaveBins - 1);
+      int jc = min(lb_lane, J.n_tel - 1);
+      float4 bt_next = ld_bintab(rt, jc);
+      float g_next = ld_grad(rg, jc);
       for (int jw = 0; jw < J.n_tel; jw += kCubeWaveBins) {
         const int jb = jw + lane;
         const bool act = (lane < kCubeWaveBins) && (jb < J.n_tel);
-        // lanes past the window's bins take its last bin, so their nodes stay in the window
-        const int jc = min(jw + min(lane, kCubeWaveBins - 1), J.n_tel - 1);
-        const float4 bt = J.bintab[jc];
-        const float gj = act ? G[jc] : 0.f;
+        const float4 bt = bt_next;
+        const float gj = act ? g_next : 0.f;
+        jc = min(jw + kCubeWaveBins + lb_lane, J.n_tel - 1);
         const float tq = fmaf(-bt.z, r.g, bt.y);
         const float fl = floorf(tq);
         const float tau = tq - fl;
@@ -138,10 +162,14 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
           // every lane's node k lies in [n0, n0 + 62], inside [0, n - 2]: the bin is on the grid
           // and its interval is k itself, so no mask or clamp is needed here
           const uint32_t so = (uint32_t)(row + n0) * 4u;
+          float st[4];
 #pragma unroll
           for (int c = 0; c < 4; ++c)
-            wr[c * 64 + lane] = __builtin_bit_cast(
-                float, __builtin_amdgcn_raw_buffer_load_b32(rs, lb[c] + so, 0, 0));
+            st[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lb[c] + so, 0, 0));
+          bt_next = ld_bintab(rt, jc);
+          g_next = ld_grad(rg, jc);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) wr[c * 64 + lane] = st[c];
           __builtin_amdgcn_wave_barrier();
           const int i = min(max(k - n0, 0), 62);          // the clamp only guards the LDS rows
 #pragma unroll
@@ -158,11 +186,15 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
           const float g = ok ? gj : 0.f;
           const int kk = min(max(k, 0), nl - 2);
           const float t = (k > kk) ? 1.f : tau;
-          const float *b = flux + row + kk;
-          pv[0] = b[0]; qv[0] = b[1];
-          pv[1] = b[o1]; qv[1] = b[o1 + 1];
-          pv[2] = b[o2]; qv[2] = b[o2 + 1];
-          pv[3] = b[o3]; qv[3] = b[o3 + 1];
+          const uint32_t b = (uint32_t)(row + kk) * 4u;
+          const uint32_t oc[4] = {0u, (uint32_t)o1 * 4u, (uint32_t)o2 * 4u, (uint32_t)o3 * 4u};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            pv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, b + oc[c], 0, 0));
+            qv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, b + oc[c] + 4u, 0, 0));
+          }
+          bt_next = ld_bintab(rt, jc);
+          g_next = ld_grad(rg, jc);
           bwd_bin(w0, w1, w2, w3, ta, tz, t, g, bt.z, pv, qv, sm, sa, sz, y);
         }
       }
