@@ -213,36 +213,80 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
 //                   metallicity direction),
 //   Y = sum_j G[s,j] (lam_hi Slin(q_hi) [q_hi inside] - lam_lo Slin(q_lo) [q_lo inside]),
 // Y holding the Leibniz terms of the moving limits (an edge clipped to the grid's end does not
-// move, so it contributes nothing; "inside" is 0 < q < n-1). One wave per particle; lane l takes
-// bins l, l+64, ... and walks each bin's node segments with direct gathers of the four corner
-// rows (any number of segments per bin). Where both edges are inside, lam_hi S_hi - lam_lo S_lo
-// is formed as lam_lo (S_hi - S_lo) + dlam S_hi, with S_hi - S_lo summed from the segments'
-// slopes, so a bin's term is not a difference of two nearly equal products.
+// move, so it contributes nothing; "inside" is 0 < q < n-1). Where both edges are inside,
+// lam_hi S_hi - lam_lo S_lo is formed as lam_lo (S_hi - S_lo) + dlam S_hi, with S_hi - S_lo
+// summed from the segments' slopes, so a bin's term is not a difference of two nearly equal
+// products.
+
+// Terms of one node segment [x, xe] (fractions) between node values p_c and q_c of the corner
+// rows: the integrals of Slin and of its two directions, and Slin's slope dS (per node).
+struct SegTerms {
+  float is, ia, iz, ds, p;
+};
+__device__ __forceinline__ SegTerms seg_terms(float w0, float w1, float w2, float w3, float ta,
+                                              float tz, const float (&pv)[4], const float (&qv)[4],
+                                              float x, float xe) {
+  SegTerms o;
+  o.p = w0 * pv[0] + w1 * pv[1] + w2 * pv[2] + w3 * pv[3];
+  o.ds = w0 * (qv[0] - pv[0]) + w1 * (qv[1] - pv[1]) + w2 * (qv[2] - pv[2]) + w3 * (qv[3] - pv[3]);
+  // age and metallicity directions at the two nodes, differences taken before the sums
+  const float ap = (1.f - tz) * (pv[2] - pv[0]) + tz * (pv[3] - pv[1]);
+  const float aq = (1.f - tz) * (qv[2] - qv[0]) + tz * (qv[3] - qv[1]);
+  const float zp = (1.f - ta) * (pv[1] - pv[0]) + ta * (pv[3] - pv[2]);
+  const float zq = (1.f - ta) * (qv[1] - qv[0]) + ta * (qv[3] - qv[2]);
+  o.is = seg_integral(o.p, o.p + o.ds, x, xe);
+  o.ia = seg_integral(ap, aq, x, xe);
+  o.iz = seg_integral(zp, zq, x, xe);
+  return o;
+}
+
+// One wave per particle, walking the telescope grid in windows of kBinWaveBins bins (lane l takes
+// bin jw + l; the last lanes only stage). Where every bin of the window spans at most two node
+// segments and the window's bins span at most 63 nodes, the four corner rows at nodes
+// n0 .. n0+63 (n0 = lane 0's lower node) are staged in the wave's LDS rows with one coalesced
+// load each, and each bin reads its (at most three) nodes per row from there; otherwise each lane
+// walks its bin's segments with direct gathers. Each lane accumulates its bins in increasing
+// order; the wave's sums are reduced in FP64.
 __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ T) {
+  __shared__ float rows[4][4][64];     // [wave][corner][node - n0]
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
-  const float *__restrict__ flux = S.flux;
   const int nl = S.n_lam;
   const int o1 = nl, o2 = S.n_met * nl, o3 = o2 + nl;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const uint32_t fbytes = (uint32_t)S.n_age * (uint32_t)S.n_met * (uint32_t)nl * 4u;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)S.flux, (short)0, (int)fbytes, 0x00020000);
+  const uint32_t lb[4] = {(uint32_t)lane * 4u, (uint32_t)(lane + o1) * 4u,
+                          (uint32_t)(lane + o2) * 4u, (uint32_t)(lane + o3) * 4u};
+  const uint32_t oc[4] = {0u, (uint32_t)o1 * 4u, (uint32_t)o2 * 4u, (uint32_t)o3 * 4u};
+  float *wr = &rows[w][0][0];
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_BWDB]; vb += gridDim.x) {
     const int jj = find_job(T, K_BWDB, vb);
     const JobDev &J = jobs[jj];
     const int64_t pbase = (vb - J.vb_start[K_BWDB]) * kBwdParticles;
     const int n_in = J.seg_off[J.n_s];
     const float dlam = (float)J.tel_step;
+    const __amdgpu_buffer_rsrc_t rt =
+        __builtin_amdgcn_make_buffer_rsrc((void *)J.bintab, (short)0, J.n_tel * 32, 0x00020000);
     for (int q = w; q < kBwdParticles; q += 4) {
       const int64_t p = pbase + q;
       if (p >= n_in) break;
       const PrepRec r = J.prep[p];
-      const float *__restrict__ G = J.grad_raw + (int64_t)r.spaxel * J.n_tel;
+      const int spx = __builtin_amdgcn_readfirstlane(r.spaxel);
+      const int row = prep_row(__builtin_amdgcn_readfirstlane(r.row));
+      const float *__restrict__ G = J.grad_raw + (int64_t)spx * J.n_tel;
+      const __amdgpu_buffer_rsrc_t rg =
+          __builtin_amdgcn_make_buffer_rsrc((void *)G, (short)0, J.n_tel * 4, 0x00020000);
       const float w0 = r.a[0], w1 = r.a[1], w2 = r.a[2], w3 = r.a[3];
       const float ta = w2 + w3, tz = w1 + w3;
-      const int row = prep_row(r.row);
       float sm = 0.f, sa = 0.f, sz = 0.f, y = 0.f;
-      for (int jb = lane; jb < J.n_tel; jb += 64) {
-        const float4 lo = J.bintab[jb], hi = J.bintab[J.n_tel + jb];
-        const float gj = G[jb];
+      for (int jw = 0; jw < J.n_tel; jw += kBinWaveBins) {
+        const bool act = (lane < kBinWaveBins) && (jw + lane < J.n_tel);
+        // lanes past the window's bins take its last bin, so the node span stays the bins'
+        const int jc = min(jw + min(lane, kBinWaveBins - 1), J.n_tel - 1);
+        const float4 lo = ld_bintab(rt, jc), hi = ld_bintab(rt, J.n_tel + jc);
+        const float graw = ld_grad(rg, jc);
         const float tl = fmaf(-lo.z, r.g, lo.y), th = fmaf(-hi.z, r.g, hi.y);
         int klo = __float_as_int(lo.x) + floor_i32(tl), khi = __float_as_int(hi.x) + floor_i32(th);
         float a = __builtin_amdgcn_fractf(tl), b = __builtin_amdgcn_fractf(th);
@@ -250,34 +294,72 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
         const bool in_hi = (khi > 0 || (khi == 0 && b > 0.f)) && khi < nl - 1;
         clip_node(klo, a, nl);
         clip_node(khi, b, nl);
-        if (klo > khi || (klo == khi && !(a < b))) continue;   // empty: both edges clipped together
+        // empty: both edges clipped to the same point of the grid
+        const bool empty = klo > khi || (klo == khi && !(a < b));
+        const int n0 = __builtin_amdgcn_readfirstlane(klo);
+        const int nmax = __builtin_amdgcn_readlane(khi, 63) + 1;
+        const bool multi = !empty && (khi - klo > 1);
         float Is = 0.f, Ia = 0.f, Iz = 0.f, D = 0.f, s_lo = 0.f, s_hi = 0.f;
-        for (int k = klo; k <= khi; ++k) {
-          const float *f = flux + row + k;
-          const float p0 = f[0], q0 = f[1], p1 = f[o1], q1 = f[o1 + 1];
-          const float p2 = f[o2], q2 = f[o2 + 1], p3 = f[o3], q3 = f[o3 + 1];
-          const float x = k == klo ? a : 0.f, xe = k == khi ? b : 1.f;
-          const float P = w0 * p0 + w1 * p1 + w2 * p2 + w3 * p3;
-          const float dS = w0 * (q0 - p0) + w1 * (q1 - p1) + w2 * (q2 - p2) + w3 * (q3 - p3);
-          // age and metallicity directions at the two nodes, differences taken before the sums
-          const float ap = (1.f - tz) * (p2 - p0) + tz * (p3 - p1);
-          const float aq = (1.f - tz) * (q2 - q0) + tz * (q3 - q1);
-          const float zp = (1.f - ta) * (p1 - p0) + ta * (p3 - p2);
-          const float zq = (1.f - ta) * (q1 - q0) + ta * (q3 - q2);
-          Is += seg_integral(P, P + dS, x, xe);
-          Ia += seg_integral(ap, aq, x, xe);
-          Iz += seg_integral(zp, zq, x, xe);
-          D = fmaf(dS, xe - x, D);
-          s_lo = k == klo ? fmaf(a, dS, P) : s_lo;
-          s_hi = k == khi ? fmaf(b, dS, P) : s_hi;
+        if (nmax - n0 <= 63 && !__builtin_amdgcn_ballot_w64(multi)) {
+          // every lane's nodes klo .. khi+1 lie in n0 .. n0+63; rows read past the end of a row
+          // (or of the grid, as zeros) only feed lanes that do not use them
+          const uint32_t so = (uint32_t)(row + n0) * 4u;
+          float st[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            st[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lb[c] + so, 0, 0));
+#pragma unroll
+          for (int c = 0; c < 4; ++c) wr[c * 64 + lane] = st[c];
+          __builtin_amdgcn_wave_barrier();
+          const int i = min(max(klo - n0, 0), 61);
+          float pv[4], qv[4], rv[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            pv[c] = wr[c * 64 + i];
+            qv[c] = wr[c * 64 + i + 1];
+            rv[c] = wr[c * 64 + i + 2];
+          }
+          __builtin_amdgcn_wave_barrier();
+          // first segment [a, b or 1]; second [0, b] when the bin reaches the next segment
+          const bool two = khi > klo;
+          const float e1 = two ? 1.f : b, e2 = two ? b : 0.f;
+          const SegTerms t1 = seg_terms(w0, w1, w2, w3, ta, tz, pv, qv, a, e1);
+          const SegTerms t2 = seg_terms(w0, w1, w2, w3, ta, tz, qv, rv, 0.f, e2);
+          Is = t1.is + t2.is;
+          Ia = t1.ia + t2.ia;
+          Iz = t1.iz + t2.iz;
+          D = fmaf(t2.ds, e2, t1.ds * (e1 - a));
+          s_lo = fmaf(a, t1.ds, t1.p);
+          s_hi = two ? fmaf(b, t2.ds, t2.p) : fmaf(b, t1.ds, t1.p);
+        } else if (!empty) {
+          // any number of segments, gathered from the template grid
+          for (int k = klo; k <= khi; ++k) {
+            const uint32_t e = (uint32_t)(row + k) * 4u;
+            float pv[4], qv[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              pv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, e + oc[c], 0, 0));
+              qv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, e + oc[c] + 4u, 0, 0));
+            }
+            const float x = k == klo ? a : 0.f, xe = k == khi ? b : 1.f;
+            const SegTerms t = seg_terms(w0, w1, w2, w3, ta, tz, pv, qv, x, xe);
+            Is += t.is;
+            Ia += t.ia;
+            Iz += t.iz;
+            D = fmaf(t.ds, xe - x, D);
+            s_lo = k == klo ? fmaf(a, t.ds, t.p) : s_lo;
+            s_hi = k == khi ? fmaf(b, t.ds, t.p) : s_hi;
+          }
         }
         float e;
         if (in_lo && in_hi) e = fmaf(lo.z, D, dlam * s_hi);
         else e = (in_hi ? hi.z * s_hi : 0.f) - (in_lo ? lo.z * s_lo : 0.f);
-        sm = fmaf(gj, Is, sm);
-        sa = fmaf(gj, Ia, sa);
-        sz = fmaf(gj, Iz, sz);
-        y = fmaf(gj, e, y);
+        // an empty bin, or a lane past the window's bins, adds nothing
+        const float g = (act && !empty) ? graw : 0.f;
+        sm = fmaf(g, Is, sm);
+        sa = fmaf(g, Ia, sa);
+        sz = fmaf(g, Iz, sz);
+        y = fmaf(g, e, y);
       }
       const double Sm = wave_sum(sm), Sa = wave_sum(sa), Sz = wave_sum(sz), Y = wave_sum(y);
       if (lane == 0) {
