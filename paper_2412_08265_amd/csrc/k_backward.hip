@@ -25,17 +25,16 @@ __global__ __launch_bounds__(256) void k_bintab(const Table *__restrict__ T) {
     const int jj = find_job(T, K_BINTAB, vb);
     const JobDev &J = jobs[jj];
     const int jb = (int)((vb - J.vb_start[K_BINTAB]) * 256 + threadIdx.x);
-    if (jb >= J.n_tel) continue;
     if (J.resample) {
-      // the bin's two edges, as the forward bin-mean kernel computes them
-      int qlo, qhi;
-      float flo, fhi, llo, lhi;
-      bin_edge(J, S, jb, 0, qlo, flo, llo);
-      bin_edge(J, S, jb, 1, qhi, fhi, lhi);
-      J.bintab[jb] = make_float4(__int_as_float(qlo), flo, llo, 0.f);
-      J.bintab[J.n_tel + jb] = make_float4(__int_as_float(qhi), fhi, lhi, 0.f);
+      // the bin edges 0 .. n_tel, as the forward bin-mean kernel computes them
+      if (jb > J.n_tel) continue;
+      int qe;
+      float fe, le;
+      bin_edge(J, S, jb, qe, fe, le);
+      J.bintab[jb] = make_float4(__int_as_float(qe), fe, le, 0.f);
       continue;
     }
+    if (jb >= J.n_tel) continue;
     // as the forward kernel's split index: Q and the factor of the Doppler term (lambda or 1)
     double Q;
     float lamf;
@@ -268,7 +267,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
     const int n_in = J.seg_off[J.n_s];
     const float dlam = (float)J.tel_step;
     const __amdgpu_buffer_rsrc_t rt =
-        __builtin_amdgcn_make_buffer_rsrc((void *)J.bintab, (short)0, J.n_tel * 32, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void *)J.bintab, (short)0, (J.n_tel + 1) * 16, 0x00020000);
     for (int q = w; q < kBwdParticles; q += 4) {
       const int64_t p = pbase + q;
       if (p >= n_in) break;
@@ -285,7 +284,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
         const bool act = (lane < kBinWaveBins) && (jw + lane < J.n_tel);
         // lanes past the window's bins take its last bin, so the node span stays the bins'
         const int jc = min(jw + min(lane, kBinWaveBins - 1), J.n_tel - 1);
-        const float4 lo = ld_bintab(rt, jc), hi = ld_bintab(rt, J.n_tel + jc);
+        const float4 lo = ld_bintab(rt, jc), hi = ld_bintab(rt, jc + 1);
         const float graw = ld_grad(rg, jc);
         const float tl = fmaf(-lo.z, r.g, lo.y), th = fmaf(-hi.z, r.g, hi.y);
         int klo = __float_as_int(lo.x) + floor_i32(tl), khi = __float_as_int(hi.x) + floor_i32(th);

@@ -505,7 +505,9 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
 // the particle's spectrum at 64 consecutive nodes n0 .. n0+63 in its LDS slot (n0 = lane 0's
 // clipped lower node), which covers every lane's interval when the bins span at most 63 nodes
 // and no bin spans more than two segments; otherwise the particle's segments are gathered from
-// the template grid directly (both cases give the same sum of the same terms).
+// the template grid directly (both cases give the same sum of the same terms). Per particle a lane
+// splits one bin edge (its own, edge jw + l) and takes its bin's upper edge from the next lane,
+// so neighbouring bins see the same edge.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restrict__ T) {
   __shared__ float slots[kCubeThreads / 64][64];
@@ -532,22 +534,28 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restri
     const int jb = jw + lane;
     const bool act = (lane < kBinWaveBins) && (jb < J.n_tel);
     // lanes past the wave's bins take its last bin, so the node span stays that of the bins
-    const int jc = min(jw + min(lane, kBinWaveBins - 1), J.n_tel - 1);
-    int qlo, qhi;
-    float flo, fhi, llo, lhi;
-    bin_edge(J, S, jc, 0, qlo, flo, llo);
-    bin_edge(J, S, jc, 1, qhi, fhi, lhi);
+    // lane l holds edge jw + l (the lower edge of bin jw + l, the upper edge of bin jw + l - 1);
+    // lanes past the wave's last edge take it, so the node span stays that of the bins
+    int qe;
+    float fe, le;
+    bin_edge(J, S, min(jw + min(lane, kBinWaveBins), J.n_tel), qe, fe, le);
     const PrepRec *prep = J.prep;
     float acc = 0.f, tot = 0.f;
     int since = 0;
+    // the next particle's record is loaded while this one is summed
+    PrepRec rn;
+    if (ch.p0 < ch.p1) rn = load_rec(prep + ch.p0);
     for (int p = ch.p0; p < ch.p1; ++p) {
-      const PrepRec r = load_rec(prep + p);
+      const PrepRec r = rn;
+      rn = load_rec(prep + min(p + 1, ch.p1 - 1));
       const int row = prep_row(r.row);
-      const float tl = fmaf(-llo, r.g, flo), th = fmaf(-lhi, r.g, fhi);
-      int klo = qlo + floor_i32(tl), khi = qhi + floor_i32(th);
-      float a = __builtin_amdgcn_fractf(tl), b = __builtin_amdgcn_fractf(th);
+      const float tl = fmaf(-le, r.g, fe);
+      int klo = qe + floor_i32(tl);
+      float a = __builtin_amdgcn_fractf(tl);
       clip_node(klo, a, nl);
-      clip_node(khi, b, nl);
+      // the bin's upper edge is the next lane's edge
+      const int khi = __shfl_down(klo, 1, 64);
+      const float b = __shfl_down(a, 1, 64);
       const bool empty = (klo > khi) || (klo == khi && !(a < b));
       const int n0 = __builtin_amdgcn_readfirstlane(klo);
       const int nmax = __builtin_amdgcn_readlane(khi, 63) + 1;    // last bin's upper node
@@ -565,9 +573,12 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restri
         const int i0 = min(max(klo - n0, 0), 62);
         const float s0 = wslot[i0], s1 = wslot[i0 + 1], s2 = wslot[min(i0 + 2, 63)];
         __builtin_amdgcn_wave_barrier();
-        if (!empty)
-          v = (khi == klo) ? seg_integral(s0, s1, a, b)
-                           : seg_integral(s0, s1, a, 1.f) + seg_integral(s1, s2, 0.f, b);
+        // first segment [a, b or 1], second [0, b] when the bin reaches the next segment (a
+        // zero-width second segment adds exactly 0)
+        const bool next = khi > klo;
+        const float vv = seg_integral(s0, s1, a, next ? 1.f : b) +
+                         seg_integral(s1, s2, 0.f, next ? b : 0.f);
+        v = empty ? 0.f : vv;
       } else if (!empty) {
         // any number of segments, gathered from the template grid
         for (int k = klo; k <= khi; ++k) {

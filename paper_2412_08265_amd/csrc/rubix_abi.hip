@@ -139,7 +139,7 @@ static JobSizes sizes_of(const rubix_job &j) {
   size_t psf_end = al(4ull * z.cube_elems);
   // backward region (prep at the same offset as in the cube region)
   o = al(sizeof(PrepRec) * (size_t)z.n);
-  z.o_bintab = o; o += al(32ull * z.n_tel);       // two edges per bin for bin-mean jobs
+  z.o_bintab = o; o += al(16ull * (z.n_tel + 1));  // n_tel + 1 bin edges for bin-mean jobs
   z.o_dots = o; o += al(32ull * z.n);
   z.o_ang = o; o += al(24ull * std::max(1, z.n_fin_blocks));
   size_t bwd_end = o;
@@ -431,7 +431,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
         /*K_PSFY*/ n_psfy,
         /*K_PSFX*/ n_psfx,
         /*K_COPY*/ n_copy,
-        /*K_BINTAB*/ cdiv(z.n_tel, 256),
+        /*K_BINTAB*/ cdiv(z.n_tel + (j.resample ? 1 : 0), 256),
         /*K_BWD*/ j.resample ? 0 : cdiv(z.n, kBwdParticles),
         /*K_FIN*/ z.n_fin_blocks,
         /*K_ANG*/ 1,

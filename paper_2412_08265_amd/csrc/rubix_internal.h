@@ -46,7 +46,7 @@ enum Kind : int {
   K_PSFY,      // per (x column, y segment, lambda tile)
   K_PSFX,      // per (y row, x segment, lambda tile)
   K_COPY,      // per 64k floats of a cube (identity PSF/LSF)
-  K_BINTAB,    // per 256 telescope bins
+  K_BINTAB,    // per 256 telescope bins (bin edges for bin-mean jobs)
   K_BWD,       // per kBwdParticles sorted particles
   K_FIN,       // per kFinThreads sorted particles
   K_ANG,       // one per job
@@ -137,7 +137,7 @@ struct JobDev {
   float *partial;       // [n_comb_slots_ub][n_tel]
   float *tmp_cube;      // [cube_elems]
   float4 *bintab;       // [n_tel]: (node index integer part as int bits, frac, lambda, 0) of
-                        // each bin centre; bin-mean jobs: [2][n_tel], lower then upper edges
+                        // each bin centre; bin-mean jobs: [n_tel + 1] bin edges
   double *dots;         // [n][4]: s_m, s_a, s_z, Y per sorted particle
   double *ang_part;     // [n_fin_blocks][3]
   int64_t vb_start[NK];
@@ -196,12 +196,14 @@ __device__ __forceinline__ void clip_node(int &k, float &t, int nl) {
   else if (k > nl - 2) { k = nl - 2; t = 1.f; }
 }
 
-// Rest-frame node index of telescope bin jb's lower (hi = 0) or upper (hi = 1) edge at zero
-// velocity, split into its integer part qi and FP32 fraction qf, and the edge wavelength lamf
-// (the factor of the Doppler term: a particle's index is qi + qf - lamf * g). Linear grids.
-__device__ __forceinline__ void bin_edge(const JobDev &J, const SspDev &S, int jb, int hi, int &qi,
+// Rest-frame node index at zero velocity of telescope bin edge e (the lower edge of bin e, the
+// upper edge of bin e - 1: wavelength start + (e - 1/2) step), split into its integer part qi
+// and FP32 fraction qf, and the edge wavelength lamf (the factor of the Doppler term: a
+// particle's index is qi + qf - lamf * g). Linear grids. The forward sum and the adjoint's edge
+// table both take their edges from here, so two bins that share an edge see the same value.
+__device__ __forceinline__ void bin_edge(const JobDev &J, const SspDev &S, int e, int &qi,
                                          float &qf, float &lamf) {
-  const double lam = J.tel_start + (double)jb * J.tel_step + (hi ? 0.5 : -0.5) * J.tel_step;
+  const double lam = J.tel_start + ((double)e - 0.5) * J.tel_step;
   const double Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
   const double Qfl = floor(Q);
   qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
