@@ -149,7 +149,8 @@ def test_bin_mean_seeded_gradient(ratio, n_tel, seed):
     _, g = _gpu_grads(w, G)
     ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo)
     _compare(g, ref, 2e-5, f"bin-mean x{ratio} seeded-G")
-    _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False, h_vlos=1e-2)
+    _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False, h_vlos=1e-2,
+              h_met=5e-5)
 
 
 def _fd_delta_L(cfg, G, s, dplus, dminus, quadratic=True):
@@ -171,11 +172,12 @@ def _fd_delta_L(cfg, G, s, dplus, dminus, quadratic=True):
     return float(np.dot(dplus - dminus, G[s])) + 0.5 * P2 * (np.dot(Lp, Lp) - np.dot(Lm, Lm))
 
 
-def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-4):
+def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-4, h_met=1e-6):
     """FP64 central differences of the oracle's particle spectra against the GPU gradient, on up
-    to n_check in-field particles away from SSP nodes. h_vlos is the velocity step in km/s: the
-    oracle's bin mean is a difference of prefix sums over the node grid, whose rounding needs a
-    larger step than bin-centre sampling does."""
+    to n_check in-field particles at least 1e-4 away from SSP nodes. h_vlos (km/s) and h_met
+    (dex) are the velocity and metallicity steps: the oracle's bin mean is a difference of prefix
+    sums over the node grid, whose rounding needs larger steps than bin-centre sampling does (the
+    spectrum is linear in [M/H] inside a cell, so any step below the node distance is exact)."""
     p = w.particles
     key, vlos = fo["key"], fo["vlos"]
     la, mz = cfg.log_age_nodes, cfg.met_nodes
@@ -206,7 +208,7 @@ def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-
         base = spec()
         for k, h, mk in (("mass", 1e-6 * m, lambda d: spec("mass", m + d)),
                          ("age", 1e-6, lambda d: spec("age", a + d)),
-                         ("met", 1e-6, lambda d: spec("met", z + d)),
+                         ("met", h_met, lambda d: spec("met", z + d)),
                          ("vlos", h_vlos, lambda d: spec(vv=v + d))):
             dl = _fd_delta_L(cfg, G, int(key[i]), mk(h) - base, mk(-h) - base, quadratic)
             fd = dl / (2 * h)
@@ -323,3 +325,30 @@ def test_differentiation_workload_full_size():
         log(f"C5 full-vector d{k}: max-norm rel err {e:.3e}")
         assert e <= 1e-4
     _fd_check(w, cfg, fo, G, g, n_check=64, seed=2)
+
+
+def test_bin_mean_adjoint_on_the_differentiation_workload():
+    """The bin-mean adjoint at the differentiation workload's size (1e6 particles, 50x50x3000
+    cube) with a seeded dL/dC_raw: GPU gradients vs the oracle's on 4000 sampled particles
+    (max-norm per parameter) and vs FP64 central differences on 32 of them."""
+    import dataclasses
+    w = dataclasses.replace(synth.medium_workload(), resample=1)
+    cfg = O.config_from_workload(w)
+    assert cfg.resample == 1
+    log(f"bin-mean C5: oracle keys and velocities ({WORKERS} workers)")
+    fo = O.forward(w.particles, cfg, workers=WORKERS, with_cube=False)
+    rng = np.random.default_rng(17)
+    G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
+    log("bin-mean C5: GPU forward + backward")
+    _, g = _gpu_grads(w, G)
+    sub = rng.choice(w.particles.n, 4000, replace=False)
+    log("bin-mean C5: oracle adjoint on 4000 sampled particles")
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, idx=sub)
+    for k in GRAD_KEYS:
+        a = np.asarray(g[k][sub], dtype=np.float64)
+        b = np.asarray(ref[k], dtype=np.float64)
+        err = np.abs(a - b).max() / np.abs(b).max()
+        log(f"bin-mean C5 d{k}: max-norm rel err {err:.3e}")
+        assert err <= 1e-4, (k, err)
+    _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=32, seed=3, quadratic=False,
+              h_vlos=1e-2, h_met=5e-5)
