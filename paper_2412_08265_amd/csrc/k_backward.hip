@@ -18,38 +18,43 @@ constexpr double kCkmsB = 299792.458;
 
 hipError_t launch_prep_backward(const Table *dt, const TableHeader &h, int cap, hipStream_t s);
 
+// Bin-edge table of the bin-mean jobs: edges 0 .. n_tel as the forward bin-mean kernel computes
+// them (the node index split into integer part and fraction, and the edge wavelength).
 __global__ __launch_bounds__(256) void k_bintab(const Table *__restrict__ T) {
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_BINTAB]; vb += gridDim.x) {
     const int jj = find_job(T, K_BINTAB, vb);
     const JobDev &J = jobs[jj];
-    const int jb = (int)((vb - J.vb_start[K_BINTAB]) * 256 + threadIdx.x);
-    if (J.resample) {
-      // the bin edges 0 .. n_tel, as the forward bin-mean kernel computes them
-      if (jb > J.n_tel) continue;
-      int qe;
-      float fe, le;
-      bin_edge(J, S, jb, qe, fe, le);
-      J.bintab[jb] = make_float4(__int_as_float(qe), fe, le, 0.f);
-      continue;
-    }
-    if (jb >= J.n_tel) continue;
-    // as the forward kernel's split index: Q and the factor of the Doppler term (lambda or 1)
-    double Q;
-    float lamf;
-    if (J.log_lambda) {
-      Q = J.q_off + (double)jb * J.q_ratio;
-      lamf = 1.0f;
-    } else {
-      const double lam = J.tel_start + (double)jb * J.tel_step;
-      Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
-      lamf = (float)lam;
-    }
-    const double Qfl = floor(Q);
-    const int qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
-    J.bintab[jb] = make_float4(__int_as_float(qi), (float)(Q - Qfl), lamf, 0.f);
+    const int e = (int)((vb - J.vb_start[K_BINTAB]) * 256 + threadIdx.x);
+    if (e > J.n_tel) continue;
+    int qe;
+    float fe, le;
+    bin_edge(J, S, e, qe, fe, le);
+    J.bintab[e] = make_float4(__int_as_float(qe), fe, le, 0.f);
   }
+}
+
+// Rest-frame node index of bin j's centre at zero velocity, split into its integer part qi and
+// FP32 fraction qf, and the factor lamf of the Doppler term (the particle's index is
+// qi + qf - lamf g): on log grids Q = q_off + j q_ratio and lamf = 1; on linear grids
+// Q = (lam_j / (1+z) - lam0_ssp) / dlam_ssp, its two divisions taken as multiplications by the
+// reciprocals inv_opz and inv_ds (a few FP64 operations per bin instead of a table read).
+__device__ __forceinline__ void centre_index(const JobDev &J, const SspDev &S, double inv_opz,
+                                             double inv_ds, int j, int &qi, float &qf,
+                                             float &lamf) {
+  double Q;
+  if (J.log_lambda) {
+    Q = J.q_off + (double)j * J.q_ratio;
+    lamf = 1.0f;
+  } else {
+    const double lam = J.tel_start + (double)j * J.tel_step;
+    Q = (lam * inv_opz - S.lam_start) * inv_ds;
+    lamf = (float)lam;
+  }
+  const double Qfl = floor(Q);
+  qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
+  qf = (float)(Q - Qfl);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -119,6 +124,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
     const JobDev &J = jobs[jj];
     const int64_t pbase = (vb - J.vb_start[K_BWD]) * kBwdParticles;
     const int n_in = J.seg_off[J.n_s];
+    const double inv_opz = 1.0 / (1.0 + J.z_sys), inv_ds = 1.0 / S.lam_step;
     for (int q = w; q < kBwdParticles; q += 4) {
       const int64_t p = pbase + q;
       if (p >= n_in) break;
@@ -132,29 +138,27 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
       const bool fits = rrow >= 0;
       const int row = prep_row(rrow);
       float sm = 0.f, sa = 0.f, sz = 0.f, y = 0.f;
-      // lanes past a window's bins take its last bin, so their nodes stay in the window; the bin
-      // table entry and gradient of the next window are loaded while this window's template rows
-      // are (the index is clamped, so the load past the last window re-reads the last bin)
-      // (buffer loads, which complete in order with the row loads, so waiting for the rows does
-      // not wait for them)
-      const __amdgpu_buffer_rsrc_t rt =
-          __builtin_amdgcn_make_buffer_rsrc((void *)J.bintab, (short)0, J.n_tel * 16, 0x00020000);
+      // lanes past a window's bins take its last bin, so their nodes stay in the window; the
+      // gradient of the next window is loaded while this window's template rows are (a buffer
+      // load, which completes in order with the row loads, so waiting for the rows does not wait
+      // for it; the index is clamped, so the load past the last window re-reads the last bin)
       const __amdgpu_buffer_rsrc_t rg =
           __builtin_amdgcn_make_buffer_rsrc((void *)G, (short)0, J.n_tel * 4, 0x00020000);
       const int lb_lane = min(lane, kCubeWaveBins - 1);
       int jc = min(lb_lane, J.n_tel - 1);
-      float4 bt_next = ld_bintab(rt, jc);
       float g_next = ld_grad(rg, jc);
       for (int jw = 0; jw < J.n_tel; jw += kCubeWaveBins) {
         const int jb = jw + lane;
         const bool act = (lane < kCubeWaveBins) && (jb < J.n_tel);
-        const float4 bt = bt_next;
+        int qi;
+        float qf, lamf;
+        centre_index(J, S, inv_opz, inv_ds, jc, qi, qf, lamf);
         const float gj = act ? g_next : 0.f;
         jc = min(jw + kCubeWaveBins + lb_lane, J.n_tel - 1);
-        const float tq = fmaf(-bt.z, r.g, bt.y);
+        const float tq = fmaf(-lamf, r.g, qf);
         const float fl = floorf(tq);
         const float tau = tq - fl;
-        const int k = __float_as_int(bt.x) + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
+        const int k = qi + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
         const int n0 = __builtin_amdgcn_readfirstlane(k);
         float pv[4], qv[4];
         if (fits && n0 >= 0 && n0 + 63 <= nl - 1) {
@@ -165,7 +169,6 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
 #pragma unroll
           for (int c = 0; c < 4; ++c)
             st[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lb[c] + so, 0, 0));
-          bt_next = ld_bintab(rt, jc);
           g_next = ld_grad(rg, jc);
 #pragma unroll
           for (int c = 0; c < 4; ++c) wr[c * 64 + lane] = st[c];
@@ -177,7 +180,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
             qv[c] = wr[c * 64 + i + 1];
           }
           __builtin_amdgcn_wave_barrier();
-          bwd_bin(w0, w1, w2, w3, ta, tz, tau, gj, bt.z, pv, qv, sm, sa, sz, y);
+          bwd_bin(w0, w1, w2, w3, ta, tz, tau, gj, lamf, pv, qv, sm, sa, sz, y);
         } else {
           // bins whose node lies outside the SSP grid carry no gradient (a select, not a store
           // under a branch); the last node takes the last interval with t = 1
@@ -192,9 +195,8 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
             pv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, b + oc[c], 0, 0));
             qv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, b + oc[c] + 4u, 0, 0));
           }
-          bt_next = ld_bintab(rt, jc);
           g_next = ld_grad(rg, jc);
-          bwd_bin(w0, w1, w2, w3, ta, tz, t, g, bt.z, pv, qv, sm, sa, sz, y);
+          bwd_bin(w0, w1, w2, w3, ta, tz, t, g, lamf, pv, qv, sm, sa, sz, y);
         }
       }
       const double Sm = wave_sum(sm), Sa = wave_sum(sa), Sz = wave_sum(sz), Y = wave_sum(y);

@@ -431,7 +431,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
         /*K_PSFY*/ n_psfy,
         /*K_PSFX*/ n_psfx,
         /*K_COPY*/ n_copy,
-        /*K_BINTAB*/ cdiv(z.n_tel + (j.resample ? 1 : 0), 256),
+        /*K_BINTAB*/ j.resample ? cdiv(z.n_tel + 1, 256) : 0,
         /*K_BWD*/ j.resample ? 0 : cdiv(z.n, kBwdParticles),
         /*K_FIN*/ z.n_fin_blocks,
         /*K_ANG*/ 1,

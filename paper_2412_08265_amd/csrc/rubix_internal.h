@@ -46,7 +46,7 @@ enum Kind : int {
   K_PSFY,      // per (x column, y segment, lambda tile)
   K_PSFX,      // per (y row, x segment, lambda tile)
   K_COPY,      // per 64k floats of a cube (identity PSF/LSF)
-  K_BINTAB,    // per 256 telescope bins (bin edges for bin-mean jobs)
+  K_BINTAB,    // per 256 bin edges of a bin-mean job
   K_BWD,       // per kBwdParticles sorted particles
   K_FIN,       // per kFinThreads sorted particles
   K_ANG,       // one per job
@@ -136,8 +136,8 @@ struct JobDev {
                         // slope| of the job, [3] nonzero if some particle's span does not fit
   float *partial;       // [n_comb_slots_ub][n_tel]
   float *tmp_cube;      // [cube_elems]
-  float4 *bintab;       // [n_tel]: (node index integer part as int bits, frac, lambda, 0) of
-                        // each bin centre; bin-mean jobs: [n_tel + 1] bin edges
+  float4 *bintab;       // [n_tel + 1] bin edges of a bin-mean job: (node index integer part
+                        // as int bits, frac, lambda, 0)
   double *dots;         // [n][4]: s_m, s_a, s_z, Y per sorted particle
   double *ang_part;     // [n_fin_blocks][3]
   int64_t vb_start[NK];
