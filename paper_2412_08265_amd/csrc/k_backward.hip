@@ -35,28 +35,6 @@ __global__ __launch_bounds__(256) void k_bintab(const Table *__restrict__ T) {
   }
 }
 
-// Rest-frame node index of bin j's centre at zero velocity, split into its integer part qi and
-// FP32 fraction qf, and the factor lamf of the Doppler term (the particle's index is
-// qi + qf - lamf g): on log grids Q = q_off + j q_ratio and lamf = 1; on linear grids
-// Q = (lam_j / (1+z) - lam0_ssp) / dlam_ssp, its two divisions taken as multiplications by the
-// reciprocals inv_opz and inv_ds (a few FP64 operations per bin instead of a table read).
-__device__ __forceinline__ void centre_index(const JobDev &J, const SspDev &S, double inv_opz,
-                                             double inv_ds, int j, int &qi, float &qf,
-                                             float &lamf) {
-  double Q;
-  if (J.log_lambda) {
-    Q = J.q_off + (double)j * J.q_ratio;
-    lamf = 1.0f;
-  } else {
-    const double lam = J.tel_start + (double)j * J.tel_step;
-    Q = (lam * inv_opz - S.lam_start) * inv_ds;
-    lamf = (float)lam;
-  }
-  const double Qfl = floor(Q);
-  qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
-  qf = (float)(Q - Qfl);
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -124,7 +102,6 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
     const JobDev &J = jobs[jj];
     const int64_t pbase = (vb - J.vb_start[K_BWD]) * kBwdParticles;
     const int n_in = J.seg_off[J.n_s];
-    const double inv_opz = 1.0 / (1.0 + J.z_sys), inv_ds = 1.0 / S.lam_step;
     for (int q = w; q < kBwdParticles; q += 4) {
       const int64_t p = pbase + q;
       if (p >= n_in) break;
@@ -152,7 +129,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
         const bool act = (lane < kCubeWaveBins) && (jb < J.n_tel);
         int qi;
         float qf, lamf;
-        centre_index(J, S, inv_opz, inv_ds, jc, qi, qf, lamf);
+        split_index(J, S, jc, qi, qf, lamf);
         const float gj = act ? g_next : 0.f;
         jc = min(jw + kCubeWaveBins + lb_lane, J.n_tel - 1);
         const float tq = fmaf(-lamf, r.g, qf);

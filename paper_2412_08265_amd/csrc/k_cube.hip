@@ -304,25 +304,6 @@ __device__ __forceinline__ float slot_contrib(const PrepRec &r, __amdgpu_buffer_
   return (k == nl - 1) ? s0 : fmaf(tau, s1 - s0, s0);
 }
 
-// Rest-frame node index Q of bin jb split into an integer and an FP32 fraction, and the factor
-// that multiplies the particle's Doppler term g: the bin wavelength on linear grids, 1 on log
-// grids (where q = Q - g).
-__device__ __forceinline__ void split_index(const JobDev &J, const SspDev &S, int jb, int &qi,
-                                            float &qf, float &lamf) {
-  double Q;
-  if (J.log_lambda) {
-    Q = J.q_off + (double)jb * J.q_ratio;
-    lamf = 1.0f;
-  } else {
-    const double lam = J.tel_start + (double)jb * J.tel_step;
-    Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
-    lamf = (float)lam;
-  }
-  const double Qfl = floor(Q);
-  qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
-  qf = (float)(Q - Qfl);
-}
-
 __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__ T) {
   __shared__ float slots[kCubeThreads / 64][kCubeGroup][64];
   const SspDev &S = T->h.ssp;

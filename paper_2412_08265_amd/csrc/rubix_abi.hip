@@ -357,6 +357,8 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
     } else {
       d.bin_slope = ssp ? j.tel.step / ((1.0 + j.z_sys) * ssp->lam.step) : 1.0;
     }
+    d.inv_opz = 1.0 / (1.0 + j.z_sys);
+    d.inv_ds = ssp ? 1.0 / ssp->lam.step : 1.0;
     // a telescope grid coarser than the SSP grid needs node windows wider than a wave; such jobs
     // gather their two taps per corner directly from the template grid
     d.cube_direct = d.bin_slope > 1.0 ? 1 : 0;

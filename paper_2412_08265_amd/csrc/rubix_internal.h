@@ -108,6 +108,7 @@ struct JobDev {
   int32_t resample, n_tiles_b;  // 1 = bin-mean resampling; its tiles of kBinTL bins
   double bin_scale;             // bin mean: dlam_ssp / dlam_tel
   double bin_slope;                                  // d(node index)/d(bin) at rest
+  double inv_opz, inv_ds;  // 1/(1+z_sys) and 1/dlam_ssp (linear grids: the rest-frame index)
   int32_t n_chunk_ub, n_comb_ub, lsf_r, psf_r;
   int32_t n_psf_tiles, n_psf_seg_y, n_psf_seg_x, n_fin_blocks;
   // outputs
@@ -196,18 +197,41 @@ __device__ __forceinline__ void clip_node(int &k, float &t, int nl) {
   else if (k > nl - 2) { k = nl - 2; t = 1.f; }
 }
 
-// Rest-frame node index at zero velocity of telescope bin edge e (the lower edge of bin e, the
-// upper edge of bin e - 1: wavelength start + (e - 1/2) step), split into its integer part qi
-// and FP32 fraction qf, and the edge wavelength lamf (the factor of the Doppler term: a
-// particle's index is qi + qf - lamf * g). Linear grids. The forward sum and the adjoint's edge
-// table both take their edges from here, so two bins that share an edge see the same value.
-__device__ __forceinline__ void bin_edge(const JobDev &J, const SspDev &S, int e, int &qi,
-                                         float &qf, float &lamf) {
-  const double lam = J.tel_start + ((double)e - 0.5) * J.tel_step;
-  const double Q = (lam / (1.0 + J.z_sys) - S.lam_start) / S.lam_step;
+// Rest-frame node index at zero velocity of wavelength lam on a linear grid,
+// Q = (lam/(1+z) - lam0_ssp)/dlam_ssp with the two divisions taken as multiplications by the
+// job's reciprocals, split into its integer part qi and FP32 fraction qf.
+__device__ __forceinline__ void split_q(double Q, int &qi, float &qf) {
   const double Qfl = floor(Q);
   qi = (int)fmin(fmax(Qfl, -1.0e9), 1.0e9);
   qf = (float)(Q - Qfl);
+}
+__device__ __forceinline__ double rest_q(const JobDev &J, const SspDev &S, double lam) {
+  return (lam * J.inv_opz - S.lam_start) * J.inv_ds;
+}
+
+// Rest-frame node index of telescope bin jb's centre, split into an integer and an FP32
+// fraction, and the factor lamf that multiplies the particle's Doppler term g (the particle's
+// index is qi + qf - lamf g): the bin wavelength on linear grids; 1 on log grids, where
+// Q = q_off + jb q_ratio. The forward sum and the adjoint both take it from here, so they put
+// every bin in the same node interval.
+__device__ __forceinline__ void split_index(const JobDev &J, const SspDev &S, int jb, int &qi,
+                                            float &qf, float &lamf) {
+  if (J.log_lambda) {
+    split_q(J.q_off + (double)jb * J.q_ratio, qi, qf);
+    lamf = 1.0f;
+  } else {
+    const double lam = J.tel_start + (double)jb * J.tel_step;
+    split_q(rest_q(J, S, lam), qi, qf);
+    lamf = (float)lam;
+  }
+}
+
+// The same for telescope bin edge e (the lower edge of bin e, the upper edge of bin e - 1, at
+// wavelength start + (e - 1/2) step). Linear grids (bin-mean resampling).
+__device__ __forceinline__ void bin_edge(const JobDev &J, const SspDev &S, int e, int &qi,
+                                         float &qf, float &lamf) {
+  const double lam = J.tel_start + ((double)e - 0.5) * J.tel_step;
+  split_q(rest_q(J, S, lam), qi, qf);
   lamf = (float)lam;
 }
 
