@@ -109,6 +109,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
       // the record is the wave's (a vector load of one address): its integers in scalar registers
       const int spx = __builtin_amdgcn_readfirstlane(r.spaxel);
       const int rrow = __builtin_amdgcn_readfirstlane(r.row);
+      const int jo = __builtin_amdgcn_readfirstlane(r.pad);     // input index: where the dots go
       const float *__restrict__ G = J.grad_raw + (int64_t)spx * J.n_tel;
       const float w0 = r.a[0], w1 = r.a[1], w2 = r.a[2], w3 = r.a[3];
       const float ta = w2 + w3, tz = w1 + w3;   // bilinear fractions recovered from the weights
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
       }
       const double Sm = wave_sum(sm), Sa = wave_sum(sa), Sz = wave_sum(sz), Y = wave_sum(y);
       if (lane == 0) {
-        double *d = J.dots + p * 4;
+        double *d = J.dots + (int64_t)jo * 4;
         d[0] = Sm; d[1] = Sa; d[2] = Sz; d[3] = Y;
       }
     }
@@ -253,6 +254,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
       const PrepRec r = J.prep[p];
       const int spx = __builtin_amdgcn_readfirstlane(r.spaxel);
       const int row = prep_row(__builtin_amdgcn_readfirstlane(r.row));
+      const int jo = __builtin_amdgcn_readfirstlane(r.pad);
       const float *__restrict__ G = J.grad_raw + (int64_t)spx * J.n_tel;
       const __amdgpu_buffer_rsrc_t rg =
           __builtin_amdgcn_make_buffer_rsrc((void *)G, (short)0, J.n_tel * 4, 0x00020000);
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
       }
       const double Sm = wave_sum(sm), Sa = wave_sum(sa), Sz = wave_sum(sz), Y = wave_sum(y);
       if (lane == 0) {
-        double *d = J.dots + p * 4;
+        double *d = J.dots + (int64_t)jo * 4;
         d[0] = Sm; d[1] = Sa; d[2] = Sz; d[3] = Y;
       }
     }
@@ -368,20 +370,21 @@ __global__ __launch_bounds__(kFinThreads) void k_bwd_final(const Table *__restri
     const int jj = find_job(T, K_FIN, vb);
     const JobDev &J = jobs[jj];
     const int64_t blk = vb - J.vb_start[K_FIN];
+    // in input order: the particle arrays, its dots and its gradients are read and written
+    // coalesced; particles outside the field (key n_s) get zeros
     const int64_t i = blk * kFinThreads + t;
-    const int n_in = J.seg_off[J.n_s];
     double c0 = 0.0, c1 = 0.0, c2 = 0.0;
     if (i < J.n) {
-      const int j = J.perm[i];
+      const int64_t j = i;
       float gm = 0.f, ga = 0.f, gz = 0.f, gv = 0.f;
-      if (i < n_in) {
+      if (J.key[j] < J.n_s) {
         const double age = J.age[j], m = J.mass[j], met = J.met[j], v = J.vlos[j];
         const int na = S.n_age, nz = S.n_met;
         const bool in_a = (age >= S.age_thr[0]) && (age <= S.age_thr[na - 1]);
         const bool in_z = (met >= S.met[0]) && (met <= S.met[nz - 1]);
         const int ja = cell_of_b(S.age_thr, na, age);
         const int jz = cell_of_b(S.met, nz, met);
-        const double *X = J.dots + i * 4;
+        const double *X = J.dots + j * 4;
         const double sm = X[0], sa = X[1], sz = X[2], Y = X[3];
         const double beta = v / kCkmsB;
         const double opz = 1.0 + J.z_sys;

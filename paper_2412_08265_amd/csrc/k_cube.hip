@@ -86,15 +86,10 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__
     const int n_in = J.seg_off[J.n_s];
     if (i >= n_in) continue;
     const int j = J.perm[i];
-    // forward: one 16-byte gather of the particle's (mass, age, [M/H], vlos), packed in input
-    // order by k_vbound; backward: the particle arrays (and its key) directly
-    double age, m, met, v;
-    if (mode == 0) {
-      const float4 pr = J.pay[j];
-      m = pr.x; age = pr.y; met = pr.z; v = pr.w;
-    } else {
-      age = J.age[j]; m = J.mass[j]; met = J.met[j]; v = J.vlos[j];
-    }
+    // one 16-byte gather of the particle's (mass, age, [M/H], vlos), packed in input order by
+    // k_vbound (forward) or k_pack (backward)
+    const float4 pr = J.pay[j];
+    const double m = pr.x, age = pr.y, met = pr.z, v = pr.w;
     const int ja = cell_of(S.age_thr, S.n_age, age);
     double ta;
     if (!(age > S.age_thr[0])) ta = 0.0;
@@ -122,7 +117,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__
     r.a[3] = (float)(scale * ta * tz);
     r.spaxel = mode == 0 ? -1 : J.key[j];
     if (!fits) r.row = ~r.row;
-    r.pad = 0;
+    r.pad = mode == 0 ? 0 : j;     // backward: the particle's input index (where its dots go)
     J.prep[i] = r;
   }
 }
@@ -165,6 +160,21 @@ __global__ __launch_bounds__(256) void k_vbound(const Table *__restrict__ T) {
       if (s_f[0] | s_f[1] | s_f[2] | s_f[3]) atomicOr(&J.counts[3], 1);
     }
     __syncthreads();
+  }
+}
+
+// The backward pass's packing of (mass, age, [M/H], vlos) in input order (k_vbound's packing
+// without its Doppler bounds, which only the forward sum uses).
+__global__ __launch_bounds__(256) void k_pack(const Table *__restrict__ T) {
+  const JobDev *jobs = table_jobs(T);
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_VB]; vb += gridDim.x) {
+    const int jj = find_job(T, K_VB, vb);
+    const JobDev &J = jobs[jj];
+    const int64_t base = (vb - J.vb_start[K_VB]) * kVbParticles;
+    for (int q = threadIdx.x; q < kVbParticles; q += 256) {
+      const int64_t i = base + q;
+      if (i < J.n) J.pay[i] = make_float4(J.mass[i], J.age[i], J.met[i], J.vlos[i]);
+    }
   }
 }
 
@@ -640,6 +650,8 @@ hipError_t launch_cube(const Table *dt, const TableHeader &h, int cap, hipStream
 // Backward needs the same per-particle records with plain bilinear weights.
 hipError_t launch_prep_backward(const Table *dt, const TableHeader &h, int cap, hipStream_t s) {
   int g;
+  if ((g = grid_for(h.total[K_VB], cap)))
+    hipLaunchKernelGGL(k_pack, dim3(g), dim3(256), 0, s, dt);
   if ((g = grid_for(h.total[K_PREP], cap)))
     hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, 1);
   return hipGetLastError();

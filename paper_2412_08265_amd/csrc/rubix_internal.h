@@ -65,7 +65,7 @@ struct PrepRec {
                     // per Angstrom of bin wavelength, or ln(1+beta)/dln_ssp on log grids
   float a[4];       // corner weights (forward: flux_scale m J w_c; backward: w_c)
   int32_t spaxel;   // key of the particle (backward records; -1 in forward records)
-  int32_t pad;
+  int32_t pad;      // backward records: the particle's input index; 0 in forward records
 };
 
 // Flux offset of a record's corner (ja, jz) whatever its window flag.
@@ -130,7 +130,7 @@ struct JobDev {
   uint32_t *hist;       // [256][n_sort_tiles], digit major
   uint32_t *dtot;       // [256]
   PrepRec *prep;        // [n]
-  float4 *pay;          // [n]: (mass, age, [M/H], vlos) in input order (forward cube call)
+  float4 *pay;          // [n]: (mass, age, [M/H], vlos) in input order
   ChunkRec *chunks;     // [n_chunk_ub]
   CombRec *combs;       // [n_comb_ub]
   int32_t *counts;      // [0] chunks, [1] combine entries, [2] bits of the largest |Doppler
@@ -139,7 +139,7 @@ struct JobDev {
   float *tmp_cube;      // [cube_elems]
   float4 *bintab;       // [n_tel + 1] bin edges of a bin-mean job: (node index integer part
                         // as int bits, frac, lambda, 0)
-  double *dots;         // [n][4]: s_m, s_a, s_z, Y per sorted particle
+  double *dots;         // [n][4]: s_m, s_a, s_z, Y per in-field particle, in input order
   double *ang_part;     // [n_fin_blocks][3]
   int64_t vb_start[NK];
 };
