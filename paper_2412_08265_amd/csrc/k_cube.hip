@@ -25,15 +25,19 @@
 //             whose span does not fit a window gathers its taps directly.
 //             Blocks are ordered lambda-tile major, so the blocks resident on one XCD at a time
 //             share one tile's slice of the template grid in that XCD's L2.
+//   k_cube_bin  bin-mean jobs in place of k_cube: the same work items on tiles of kBinTL bins,
+//             each bin's value the integral of the shifted spectrum over the bin.
 //   k_combine sums a multi-chunk spaxel's partial spectra in chunk order (deterministic).
+// The adjoint's records come from k_pack (the packing half of k_vbound) and k_prep in mode 1.
 //
 // Resampling index: for bin centre lam_j the node index of the rest-frame wavelength is
 //   q = (lam_j/((1+z)(1+beta)) - lam0)/dlam = Q_j - lam_j * g,
 //   Q_j = (lam_j/(1+z) - lam0)/dlam,  g = beta/(1+beta) / ((1+z) dlam).
-// Q_j is formed in FP64 per lane and split into an integer and an FP32 fraction; only the small
-// Doppler term lam_j*g is FP32, so q carries an absolute error of ~1e-6 nodes instead of the
-// ~1e-3 that an FP32 lam/(1+beta) would give at 9000 A. The integer part k = floor(q) is the
-// same FP32 decision in every kernel (forward and adjoint).
+// Q_j is formed in FP64 per lane (split_index, with the job's reciprocals of 1+z and dlam) and
+// split into an integer and an FP32 fraction; only the small Doppler term lam_j*g is FP32, so q
+// carries an absolute error of ~1e-6 nodes instead of the ~1e-3 that an FP32 lam/(1+beta) would
+// give at 9000 A. The integer part k = floor(q) is the same FP32 decision in every kernel
+// (forward and adjoint).
 #include "rubix_internal.h"
 
 namespace rubix {
@@ -524,7 +528,6 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restri
     const ChunkRec ch{chp[0], chp[1], chp[2], chp[3]};
     const int jb = jw + lane;
     const bool act = (lane < kBinWaveBins) && (jb < J.n_tel);
-    // lanes past the wave's bins take its last bin, so the node span stays that of the bins
     // lane l holds edge jw + l (the lower edge of bin jw + l, the upper edge of bin jw + l - 1);
     // lanes past the wave's last edge take it, so the node span stays that of the bins
     int qe;
@@ -562,13 +565,15 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restri
         wslot[lane] = Sv;
         __builtin_amdgcn_wave_barrier();
         const int i0 = min(max(klo - n0, 0), 62);
-        const float s0 = wslot[i0], s1 = wslot[i0 + 1], s2 = wslot[min(i0 + 2, 63)];
+        const float s0 = wslot[i0], s1 = wslot[i0 + 1];
         __builtin_amdgcn_wave_barrier();
-        // first segment [a, b or 1], second [0, b] when the bin reaches the next segment (a
-        // zero-width second segment adds exactly 0)
-        const bool next = khi > klo;
-        const float vv = seg_integral(s0, s1, a, next ? 1.f : b) +
-                         seg_integral(s1, s2, 0.f, next ? b : 0.f);
+        // the integral over the lane's edge segment from its node to the edge (P) and over the
+        // whole segment (Tn); a bin's value is P(upper edge) - P(lower edge), plus the lower
+        // segment's Tn when the upper edge lies in the next segment
+        const float P = a * fmaf(0.5f * a, s1 - s0, s0);
+        const float Tn = 0.5f * (s0 + s1);
+        const float Ph = __shfl_down(P, 1, 64);
+        const float vv = (Ph - P) + (khi > klo ? Tn : 0.f);
         v = empty ? 0.f : vv;
       } else if (!empty) {
         // any number of segments, gathered from the template grid
