@@ -220,12 +220,13 @@ __device__ __forceinline__ SegTerms seg_terms(float w0, float w1, float w2, floa
 }
 
 // One wave per particle, walking the telescope grid in windows of kBinWaveBins bins (lane l takes
-// bin jw + l; the last lanes only stage). Where every bin of the window spans at most two node
-// segments and the window's bins span at most 63 nodes, the four corner rows at nodes
-// n0 .. n0+63 (n0 = lane 0's lower node) are staged in the wave's LDS rows with one coalesced
-// load each, and each bin reads its (at most three) nodes per row from there; otherwise each lane
-// walks its bin's segments with direct gathers. Each lane accumulates its bins in increasing
-// order; the wave's sums are reduced in FP64.
+// bin jw + l and splits its lower edge; the upper edge is the next lane's; the last lanes only
+// stage). Where every bin of the window spans at most two node segments and the window's bins
+// span at most 63 nodes, the four corner rows at nodes n0 .. n0+63 (n0 = lane 0's lower node)
+// are staged in the wave's LDS rows with one coalesced load each; each lane reads the two nodes
+// of its edge's segment and integrates that segment, and a bin combines its two edges' partial
+// integrals. Otherwise each lane walks its bin's segments with direct gathers. Each lane
+// accumulates its bins in increasing order; the wave's sums are reduced in FP64.
 __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ T) {
   __shared__ float rows[4][4][64];     // [wave][corner][node - n0]
   const SspDev &S = T->h.ssp;
@@ -263,17 +264,20 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
       float sm = 0.f, sa = 0.f, sz = 0.f, y = 0.f;
       for (int jw = 0; jw < J.n_tel; jw += kBinWaveBins) {
         const bool act = (lane < kBinWaveBins) && (jw + lane < J.n_tel);
-        // lanes past the window's bins take its last bin, so the node span stays the bins'
         const int jc = min(jw + min(lane, kBinWaveBins - 1), J.n_tel - 1);
-        const float4 lo = ld_bintab(rt, jc), hi = ld_bintab(rt, jc + 1);
         const float graw = ld_grad(rg, jc);
-        const float tl = fmaf(-lo.z, r.g, lo.y), th = fmaf(-hi.z, r.g, hi.y);
-        int klo = __float_as_int(lo.x) + floor_i32(tl), khi = __float_as_int(hi.x) + floor_i32(th);
-        float a = __builtin_amdgcn_fractf(tl), b = __builtin_amdgcn_fractf(th);
+        // lane l splits edge jw + l, the lower edge of its bin; the upper edge is the next lane's
+        // (lanes past the window's last edge take it, so the node span stays the bins')
+        const float4 lo = ld_bintab(rt, min(jw + min(lane, kBinWaveBins), J.n_tel));
+        const float tl = fmaf(-lo.z, r.g, lo.y);
+        int klo = __float_as_int(lo.x) + floor_i32(tl);
+        float a = __builtin_amdgcn_fractf(tl);
         const bool in_lo = (klo > 0 || (klo == 0 && a > 0.f)) && klo < nl - 1;
-        const bool in_hi = (khi > 0 || (khi == 0 && b > 0.f)) && khi < nl - 1;
         clip_node(klo, a, nl);
-        clip_node(khi, b, nl);
+        const int khi = __shfl_down(klo, 1, 64);
+        const float b = __shfl_down(a, 1, 64);
+        const bool in_hi = __shfl_down((int)in_lo, 1, 64) != 0;
+        const float lhi = __shfl_down(lo.z, 1, 64);
         // empty: both edges clipped to the same point of the grid
         const bool empty = klo > khi || (klo == khi && !(a < b));
         const int n0 = __builtin_amdgcn_readfirstlane(klo);
@@ -291,26 +295,35 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
 #pragma unroll
           for (int c = 0; c < 4; ++c) wr[c * 64 + lane] = st[c];
           __builtin_amdgcn_wave_barrier();
-          const int i = min(max(klo - n0, 0), 61);
-          float pv[4], qv[4], rv[4];
+          const int i = min(max(klo - n0, 0), 62);
+          float pv[4], qv[4];
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             pv[c] = wr[c * 64 + i];
             qv[c] = wr[c * 64 + i + 1];
-            rv[c] = wr[c * 64 + i + 2];
           }
           __builtin_amdgcn_wave_barrier();
-          // first segment [a, b or 1]; second [0, b] when the bin reaches the next segment
+          // each lane integrates its own edge's segment, from the node to the edge (P) and whole
+          // (T); a bin's integrals are P(upper edge) - P(lower edge), plus the lower segment's T
+          // when the upper edge lies in the next segment, the upper values coming from the next
+          // lane
+          const SegTerms te = seg_terms(w0, w1, w2, w3, ta, tz, pv, qv, 0.f, a);
+          const float ap = (1.f - tz) * (pv[2] - pv[0]) + tz * (pv[3] - pv[1]);
+          const float aq = (1.f - tz) * (qv[2] - qv[0]) + tz * (qv[3] - qv[1]);
+          const float zp = (1.f - ta) * (pv[1] - pv[0]) + ta * (pv[3] - pv[2]);
+          const float zq = (1.f - ta) * (qv[1] - qv[0]) + ta * (qv[3] - qv[2]);
+          const float TS = fmaf(0.5f, te.ds, te.p), TA = 0.5f * (ap + aq), TZ = 0.5f * (zp + zq);
+          const float Se = fmaf(a, te.ds, te.p);
+          const float PSn = __shfl_down(te.is, 1, 64), PAn = __shfl_down(te.ia, 1, 64);
+          const float PZn = __shfl_down(te.iz, 1, 64), dSn = __shfl_down(te.ds, 1, 64);
+          const float Sn = __shfl_down(Se, 1, 64);
           const bool two = khi > klo;
-          const float e1 = two ? 1.f : b, e2 = two ? b : 0.f;
-          const SegTerms t1 = seg_terms(w0, w1, w2, w3, ta, tz, pv, qv, a, e1);
-          const SegTerms t2 = seg_terms(w0, w1, w2, w3, ta, tz, qv, rv, 0.f, e2);
-          Is = t1.is + t2.is;
-          Ia = t1.ia + t2.ia;
-          Iz = t1.iz + t2.iz;
-          D = fmaf(t2.ds, e2, t1.ds * (e1 - a));
-          s_lo = fmaf(a, t1.ds, t1.p);
-          s_hi = two ? fmaf(b, t2.ds, t2.p) : fmaf(b, t1.ds, t1.p);
+          Is = (PSn - te.is) + (two ? TS : 0.f);
+          Ia = (PAn - te.ia) + (two ? TA : 0.f);
+          Iz = (PZn - te.iz) + (two ? TZ : 0.f);
+          D = two ? fmaf(dSn, b, te.ds * (1.f - a)) : te.ds * (b - a);
+          s_lo = Se;
+          s_hi = Sn;
         } else if (!empty) {
           // any number of segments, gathered from the template grid
           for (int k = klo; k <= khi; ++k) {
@@ -333,7 +346,7 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
         }
         float e;
         if (in_lo && in_hi) e = fmaf(lo.z, D, dlam * s_hi);
-        else e = (in_hi ? hi.z * s_hi : 0.f) - (in_lo ? lo.z * s_lo : 0.f);
+        else e = (in_hi ? lhi * s_hi : 0.f) - (in_lo ? lo.z * s_lo : 0.f);
         // an empty bin, or a lane past the window's bins, adds nothing
         const float g = (act && !empty) ? graw : 0.f;
         sm = fmaf(g, Is, sm);
