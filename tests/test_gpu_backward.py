@@ -153,6 +153,37 @@ def test_bin_mean_seeded_gradient(ratio, n_tel, seed):
               h_met=5e-5)
 
 
+@pytest.mark.parametrize("n", [0, 1, 255, 256, 257, 4097])
+def test_ragged_particle_counts_backward(n):
+    """Particle counts around the final pass's 256-particle blocks and the adjoint's 16-particle
+    work items, and the empty galaxy: gradients against the oracle (all zero for n = 0)."""
+    import torch
+    from paper_2412_08265_amd import ops
+    p = synth.make_galaxy(max(n, 1), seed=300 + n).subset(slice(0, n))
+    ssp = synth.cached_ssp(12, 6, 3600.0, 3.8, 1000)
+    w = synth.Workload(f"grad-n{n}", p, (55.0, 12.0, 20.0), 14, 12, 2.0, 3640.0, 3.1, 1100, ssp,
+                       psf_sigma_spx=1.2, lsf_sigma_A=6.0)
+    rng = np.random.default_rng(n)
+    G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
+    _, g = _gpu_grads(w, G)
+    if n == 0:
+        for k in GRAD_KEYS:
+            assert g[k].size == 0
+        assert np.all(np.asarray(g["angles"]) == 0.0)
+        return
+    cfg = O.config_from_workload(w)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64))
+    for k in GRAD_KEYS:
+        a = np.asarray(g[k], dtype=np.float64)
+        b = np.asarray(ref[k], dtype=np.float64)
+        scale = np.abs(b).max()
+        err = np.abs(a - b).max() / scale if scale > 0 else np.abs(a).max()
+        log(f"n={n} d{k}: max-norm rel err {err:.3e}")
+        assert err <= 2e-5, (k, err)
+    a, b = np.asarray(g["angles"]), np.asarray(ref["angles"])
+    assert np.abs(a[:2] - b[:2]).max() <= 2e-5 * max(np.abs(b[:2]).max(), 1e-300) and a[2] == 0.0
+
+
 def _fd_delta_L(cfg, G, s, dplus, dminus, quadratic=True):
     """L(+) - L(-) when one particle of spaxel s changes its spectrum by d+/d- (FP64).
     For the loss L = |A C - T|^2 / 2 with G = A(A C - T):
