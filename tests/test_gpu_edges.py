@@ -138,12 +138,13 @@ def test_wave_and_tile_tails(n_tel):
     _run(w)
 
 
-@pytest.mark.parametrize("n_tel", [59, 60, 61, 239, 240, 241, 993])
+@pytest.mark.parametrize("n_tel", [1, 2, 59, 60, 61, 239, 240, 241, 993])
 def test_bin_mean_wave_and_tile_tails(n_tel):
-    """Bin-mean resampling on telescope grids whose last wave ends one bin short of, at and one
-    past a wave's 60 bins, at a tile edge (240 bins) and past it: the lanes share bin edges with
-    their neighbours, and the last wave's edges are clamped to the band's end. Forward cube and
-    the adjoint's gradients (seeded dL/dC_raw) against the oracle."""
+    """Bin-mean resampling on telescope grids of one and two bins, and on grids whose last wave
+    ends one bin short of, at and one past a wave's 60 bins, at a tile edge (240 bins) and past
+    it: the lanes share bin edges with their neighbours, and the last wave's edges are clamped
+    to the band's end. Forward cube and the adjoint's gradients (seeded dL/dC_raw) against the
+    oracle."""
     import torch
     from paper_2412_08265_amd import ops
     p = _particles(4000, 70 + n_tel, r=0.9)
