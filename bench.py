@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true",
                     help="skip timing the gradient pass (reported beside the forward step)")
-    ap.add_argument("--cpu-sample", type=int, default=300_000)
+    ap.add_argument("--cpu-sample", type=int, default=800_000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 1 GiB device to device once (a known-size kernel "
                          "for calibrating profiler byte counters)")
