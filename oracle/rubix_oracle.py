@@ -69,10 +69,10 @@ class OracleConfig:
         # both wavelength grids uniform in ln(lambda): value k is start * exp(k * step)
         self.log_lambda = bool(log_lambda)
         # resampling reading: 0 = the shifted spectrum sampled at bin centres (linear
-        # interpolation); 1 = its average over each telescope bin (flux conserving; linear grids)
+        # interpolation); 1 = its average over each telescope bin (flux conserving)
         self.resample = int(resample)
-        if self.resample not in (0, 1) or (self.resample == 1 and self.log_lambda):
-            raise ValueError("resample must be 0, or 1 on linear grids")
+        if self.resample not in (0, 1):
+            raise ValueError("resample must be 0 or 1")
 
     @property
     def n_spaxels(self):
@@ -363,6 +363,53 @@ def bin_edge_indices(cfg: OracleConfig, vlos: np.ndarray):
     return lo, hi
 
 
+def bin_edge_indices_log(cfg: OracleConfig, vlos: np.ndarray):
+    """Log grids: rest-frame SSP node index of the lower and upper edge of every telescope bin,
+    shape [n, n_tel] each. Bin j spans ln lam in [ln lam_j - dln/2, ln lam_j + dln/2] (uniform in
+    ln lam, centred on lam_j); an edge's rest index is
+    (ln lam_edge - ln(1+z) - ln(1+beta) - ln lam0_ssp) / dln_ssp."""
+    beta = np.asarray(vlos, dtype=np.float64) / C_KMS
+    j = np.arange(cfg.n_tel, dtype=np.float64)[None, :]
+    base = (math.log(cfg.tel_start) - math.log1p(cfg.z_sys) - math.log(cfg.ssp_lam_start))
+    shift = np.log1p(beta)[:, None]
+    lo = (base + (j - 0.5) * cfg.tel_step - shift) / cfg.ssp_lam_step
+    hi = (base + (j + 0.5) * cfg.tel_step - shift) / cfg.ssp_lam_step
+    return lo, hi
+
+
+def integral_log_weighted(S: np.ndarray, q_lo: np.ndarray, q_hi: np.ndarray, lam0: float,
+                          dln: float) -> np.ndarray:
+    """Log grids: integral over rest wavelength of the spectrum whose value is linear in the node
+    index between nodes (row i of S), over the rest-frame index interval [q_lo, q_hi] clipped to
+    [0, n-1] (zero outside), FP64. With lam(q) = lam0 exp(q dln), dlam = lam dln dq, and on segment
+    k (t = q - k) the integrand (S_k + t d_k) lam0 e^{k dln} e^{t dln} dln, whose antiderivative in
+    t is lam0 e^{k dln} (S_k + t d_k - d_k/dln) e^{t dln}."""
+    n = S.shape[1]
+    k_all = np.arange(n - 1, dtype=np.float64)
+    d = S[:, 1:] - S[:, :-1]
+    lamk = lam0 * np.exp(k_all * dln)                     # rest wavelength of node k
+
+    def G(k, t):
+        # antiderivative on segment k at fraction t, per row (k, t arrays of the row's shape)
+        sk = np.take_along_axis(S, k, axis=1)
+        dk = np.take_along_axis(d, k, axis=1)
+        return lamk[k] * (sk + t * dk - dk / dln) * np.exp(t * dln)
+
+    # whole segments: G_k(1) - G_k(0), summed from node 0
+    full = lamk[None, :] * ((S[:, :-1] + d - d / dln) * math.exp(dln) - (S[:, :-1] - d / dln))
+    C = np.zeros((S.shape[0], n))
+    C[:, 1:] = np.cumsum(full, axis=1)
+
+    def F(q):
+        q = np.clip(q, 0.0, n - 1.0)
+        k = np.minimum(np.floor(q), n - 2).astype(np.int64)
+        t = q - k
+        zero = np.zeros_like(t)
+        return np.take_along_axis(C, k, axis=1) + G(k, t) - G(k, zero)
+
+    return F(q_hi) - F(q_lo)
+
+
 def particle_spectra(p, idx: np.ndarray, vlos: np.ndarray, cfg: OracleConfig) -> np.ndarray:
     """Observed spectrum of each particle in `idx` on the telescope grid, shape [len(idx), n_tel].
 
@@ -370,13 +417,24 @@ def particle_spectra(p, idx: np.ndarray, vlos: np.ndarray, cfg: OracleConfig) ->
     resample 1: the mean of the observed flux density over bin j,
       f_i(j) = (1/dlam) int_{bin j} flux_scale m_i J_i Slin_i(q(lam)) dlam
              = flux_scale m_i (dlam_ssp / dlam) int_{q_lo}^{q_hi} Slin_i(q) dq
-    (the substitution lam -> q cancels J); summed over bins this conserves the flux exactly."""
+    (the substitution lam -> q cancels J); summed over bins this conserves the flux exactly.
+    On log grids the same mean, with the spectrum linear in the log-grid index: f_i(j) =
+    (flux_scale m_i / dlam_j) x the integral of Slin_i over the rest wavelength between the bin's
+    edges (integral_log_weighted), dlam_j the bin's width in wavelength."""
     age = _p64(p, "age")[idx]
     met = _p64(p, "met")[idx]
     mass = _p64(p, "mass")[idx]
     v = vlos[idx]
     ja, jz, ta, tz, w, _, _ = ssp_weights(age, met, cfg.log_age_nodes, cfg.met_nodes)
     S = interp_templates(cfg.ssp_flux, ja, jz, w)
+    if cfg.resample == 1 and cfg.log_lambda:
+        # the mean of the observed flux density over bin j, of width
+        # dlam_j = lam_j (e^{dln/2} - e^{-dln/2}): the substitution of the rest wavelength cancels
+        # J, leaving (flux_scale m / dlam_j) x the integral of Slin over the rest wavelength
+        q_lo, q_hi = bin_edge_indices_log(cfg, v)
+        width = cfg.tel_lambda() * (2.0 * math.sinh(0.5 * cfg.tel_step))
+        return ((cfg.flux_scale * mass)[:, None] / width[None, :]) * integral_log_weighted(
+            S, q_lo, q_hi, cfg.ssp_lam_start, cfg.ssp_lam_step)
     if cfg.resample == 1:
         q_lo, q_hi = bin_edge_indices(cfg, v)
         scale = cfg.flux_scale * mass * (cfg.ssp_lam_step / cfg.tel_step)
@@ -532,6 +590,8 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
       dL/dphi_k = sum_i dL/dvlos_i (dR/dphi_k v_i)_z,   dL/dv_i = dL/dvlos_i R[2, :].
     Particles outside the field get zero. Positions get no gradient (binning is piecewise
     constant)."""
+    if cfg.resample == 1 and cfg.log_lambda:
+        raise NotImplementedError("no adjoint for bin-mean resampling on log grids")
     if fw is None:
         fw = forward(p, cfg, with_cube=False)
     R, key, vlos = fw["R"], fw["key"], fw["vlos"]

@@ -391,16 +391,73 @@ def test_bin_average_conserves_flux_exactly():
 
 
 def test_bin_average_of_a_constant_and_reading_check():
-    """A constant spectrum c gives J c in every bin inside the band; the bin-average reading is
-    refused on log grids."""
+    """A constant spectrum c gives J c in every bin inside the band; a resampling mode other than
+    0 and 1 is refused."""
     ssp = synth.make_line_ssp(5000.0, 1.0, 400, 5200.0, 3.0)
     ssp.flux = np.full_like(ssp.flux, 2.0)
     v = 500.0
     cfg, f = _bin_avg(ssp, (5050.3, 1.7, 150), v, mass=3.0)
     np.testing.assert_allclose(f, 3.0 * 2.0 / (1 + v / O.C_KMS), rtol=1e-12)
-    log_ssp = synth.make_ssp(3, 3, 4000.0, 1e-4, 50, log_lambda=True)
     with pytest.raises(ValueError):
-        _cfg(ssp=log_ssp, resample=1)
+        _cfg(ssp=ssp, resample=2)
+
+
+def _log_obs_density(ssp, S, lam, v, z, m, fs):
+    """Observed flux density fs m J Slin at wavelengths lam, Slin linear in the log-grid index
+    between nodes and zero outside them (np.interp on the index)."""
+    fac = (1 + z) * (1 + v / O.C_KMS)
+    q = np.log(lam / fac / ssp.lam_start) / ssp.lam_step
+    return fs * m / fac * np.interp(q, np.arange(ssp.n_lam), S, left=0.0, right=0.0)
+
+
+def test_log_bin_average_matches_midpoint_quadrature():
+    """Log grids, brute force: the mean of the observed flux density over each bin (uniform in
+    ln lam, centred on lam_j) by a 20000-point midpoint rule in lam."""
+    ssp = synth.make_ssp(5, 3, 4000.0, 4.0e-4, 400, log_lambda=True)
+    tel = (4013.1, 5.3e-4, 280)
+    v, z, m, fs = -287.0, 0.003, 2.5, 0.7
+    cfg, f = _bin_avg(ssp, tel, v, z, m, fs)
+    p = _single(mass=m, vlos=v)
+    ja, jz, ta, tz, w, _, _ = O.ssp_weights(p.age, p.met, cfg.log_age_nodes, cfg.met_nodes)
+    S = O.interp_templates(cfg.ssp_flux, ja, jz, w)[0]
+    lam_c = cfg.tel_lambda()
+    u = (np.arange(20000) + 0.5) / 20000.0
+    for j in (0, 1, 57, 140, 279):
+        lo, hi = lam_c[j] * math.exp(-0.5 * tel[1]), lam_c[j] * math.exp(0.5 * tel[1])
+        ref = _log_obs_density(ssp, S, lo + u * (hi - lo), v, z, m, fs).mean()
+        assert abs(f[j] - ref) <= 2e-7 * abs(ref), (j, f[j], ref)
+
+
+def test_log_bin_average_conserves_flux_and_a_constant():
+    """Log grids: for a line inside the band, sum_j f_j dlam_j is the same for every shift (the
+    bins tile the band); a constant spectrum c gives J c in every bin inside the band."""
+    ssp = synth.make_line_ssp(5000.0, 2.0e-4, 2000, 5600.0, 3.0, log_lambda=True)
+    S = ssp.flux[0, 0].astype(np.float64)
+    lam_s = ssp.lam()
+    total = np.sum(0.5 * (S[:-1] + S[1:]) * np.diff(lam_s))        # close to the exact integral
+    for tel in (None, (5003.7, 2.6e-4, 1500), (4990.2, 1.5e-4, 2700)):
+        for v in (-600.0, -150.0, 0.0, 40.0, 600.0):
+            cfg, f = _bin_avg(ssp, tel, v)
+            width = cfg.tel_lambda() * 2.0 * math.sinh(0.5 * cfg.tel_step)
+            flux = np.sum(f * width)
+            if v == -600.0:
+                ref = flux
+            assert abs(flux - ref) <= 1e-12 * ref, (tel, v)
+            assert abs(flux - total) <= 1e-6 * total, (tel, v)
+    const = synth.make_line_ssp(5000.0, 2.0e-4, 900, 5200.0, 3.0, log_lambda=True)
+    const.flux = np.full_like(const.flux, 2.0)
+    v = 500.0
+    cfg, f = _bin_avg(const, (5050.3, 3.1e-4, 300), v, mass=3.0)
+    # (the oracle differences prefix sums over up to 900 weighted segments: 1e-11)
+    np.testing.assert_allclose(f, 3.0 * 2.0 / (1 + v / O.C_KMS), rtol=1e-11)
+
+
+def test_log_bin_average_refuses_the_adjoint():
+    ssp = synth.make_ssp(3, 3, 4000.0, 1e-4, 50, log_lambda=True)
+    cfg = _cfg(ssp=ssp, resample=1)
+    p = _single()
+    with pytest.raises(NotImplementedError):
+        O.adjoint(p, cfg, np.zeros((cfg.n_spaxels, cfg.n_tel)))
 
 
 def test_out_of_band_is_zero_and_last_node_is_included():
