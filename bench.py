@@ -182,10 +182,12 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 1 GiB device to device once (a known-size kernel "
                          "for calibrating profiler byte counters)")
-    ap.add_argument("--variant", choices=("centre", "binmean", "loglam"), default="centre",
+    ap.add_argument("--variant", choices=("centre", "binmean", "loglam", "binmeanlog"),
+                    default="centre",
                     help="resampling reading / grid kind of the forward step: bin-centre sampling "
                          "on linear grids (default, the headline), bin mean (flux conserving), "
-                         "or grids uniform in ln(lambda)")
+                         "grids uniform in ln(lambda), or the bin mean on those grids (forward "
+                         "only: no adjoint there)")
     ap.add_argument("--serve", action="store_true",
                     help="print the serving report (request stream, batched graph path vs "
                          "one-at-a-time plain launches) instead of the forward-step line")
@@ -210,8 +212,11 @@ def main():
     from paper_2412_08265_amd import ops, synth
 
     err(f"generating the 1e7-particle workload ({args.variant})")
-    if args.variant == "loglam":
+    if args.variant in ("loglam", "binmeanlog"):
         w = synth.large_log_workload(n=args.n)
+        if args.variant == "binmeanlog":
+            w.resample = 1
+            args.no_backward = True          # the bin mean on log grids has no adjoint
     else:
         w = synth.large_workload(n=args.n)
         if args.variant == "binmean":

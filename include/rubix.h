@@ -110,8 +110,8 @@ typedef struct {
   float      *vlos;             /* [n]           written by rubix_rotate_bin                   */
   float      *cube_raw;         /* [ny][nx][tel.n] written by rubix_cube                       */
   float      *cube;             /* [ny][nx][tel.n] optional; rubix_psf_lsf may write it        */
-  int32_t     resample;         /* 0: bin-centre sampling (below); 1: bin mean (flux conserving,
-                                   linear grids only)                                           */
+  int32_t     resample;         /* 0: bin-centre sampling (below); 1: bin mean (flux conserving;
+                                   on log grids forward only, SSP step <= 0.05)                 */
   int32_t     reserved;         /* 0                                                            */
 } rubix_job;
 
@@ -148,6 +148,11 @@ int rubix_rotate_bin(const rubix_job *jobs, int n_jobs, void *ws, size_t ws_byte
  *    f_i(j) = flux_scale m_i (dlam_ssp / tel.step) * integral of Slin_i over the rest-frame node
  *    interval [q_ij(lam_j - step/2), q_ij(lam_j + step/2)] (exact for the piecewise-linear
  *    spectrum; the sum over bins conserves the flux of any shift inside the band).
+ *    resample = 1 (log grids): the same mean over bin j = [ln lam_j - step/2, ln lam_j + step/2],
+ *    f_i(j) = flux_scale m_i / dlam_j * integral of Slin_i over rest wavelength between the bin's
+ *    rest-frame edges, Slin linear in the log-grid index, dlam_j = 2 lam_j sinh(step/2) (each
+ *    segment's exponential weight evaluated by a four-term series, so the SSP step must be at
+ *    most 0.05; no adjoint).
  *  - cube_raw[s][j] = sum of f_i(lam_j) over the particles of spaxel s, FP32, accumulated per
  *    work item in a fixed order (deterministic; independent of the other jobs in the batch). */
 int rubix_cube(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, void *ws,

@@ -38,7 +38,8 @@ __all__ = [
     "C_KMS", "rotation_matrix", "rotation_matrix_derivs", "rotate_positions", "los_velocity",
     "spaxel_keys", "sort_by_key", "ssp_cell", "ssp_weights", "interp_templates",
     "rest_index", "doppler_index", "doppler_index_dbeta", "node_decision", "resample_linear",
-    "integral_linear", "linear_at", "bin_edge_indices", "particle_spectra", "cube_raw", "gaussian_weights",
+    "integral_linear", "linear_at", "bin_edge_indices", "bin_edge_indices_log",
+    "integral_log_weighted", "particle_spectra", "cube_raw", "gaussian_weights",
     "convolve_axis", "psf_lsf", "forward", "loss", "loss_grad_cube", "adjoint",
     "OracleConfig", "config_from_workload",
 ]

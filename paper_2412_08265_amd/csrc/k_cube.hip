@@ -503,7 +503,32 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
 // the template grid directly (both cases give the same sum of the same terms). Per particle a lane
 // splits one bin edge (its own, edge jw + l) and takes its bin's upper edge from the next lane,
 // so neighbouring bins see the same edge.
+// Log grids: the spectrum is linear in the log-grid index and the bin's integral runs over rest
+// wavelength, lambda(q) = lambda_0 e^{q dln}, so a segment's integral from its node k to fraction
+// a carries the weight e^{t dln} dln: lambda_k (S_k E1(a dln) + (S_{k+1} - S_k) a Phi(a dln)) with
+// E1(h) = e^h - 1 and Phi(h) = e^h - (e^h - 1)/h, both by their Taylor series (four terms; the
+// ABI admits steps up to 0.05, where the next terms are below 1e-7), and each bin's sum is divided
+// by its width in wavelength.
 // ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ float expm1_small(float h) {
+  return h * fmaf(h, fmaf(h, fmaf(h, 1.f / 24.f, 1.f / 6.f), 0.5f), 1.f);
+}
+__device__ __forceinline__ float phi_small(float h) {
+  return h * fmaf(h, fmaf(h, fmaf(h, 1.f / 30.f, 0.125f), 1.f / 3.f), 0.5f);
+}
+// wavelength of node k from the lane's reference node qe (wavelength lam_e): a short series in
+// the small exponent (k - qe) dln, or the exponential itself where the exponent is not small
+__device__ __forceinline__ float node_lambda(int k, int qe, float lam_e, float lam0, float dln) {
+  const float x = (float)(k - qe) * dln;
+  if (fabsf(x) <= 0.05f) return fmaf(lam_e, expm1_small(x), lam_e);
+  return lam0 * expf((float)k * dln);
+}
+// integral over rest wavelength of the segment from node k (value s0, slope d) to fraction a
+__device__ __forceinline__ float log_partial(float lamk, float s0, float d, float a, float dln) {
+  const float h = a * dln;
+  return lamk * fmaf(s0, expm1_small(h), d * a * phi_small(h));
+}
+
 __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restrict__ T) {
   __shared__ float slots[kCubeThreads / 64][64];
   const SspDev &S = T->h.ssp;
@@ -533,6 +558,16 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restri
     int qe;
     float fe, le;
     bin_edge(J, S, min(jw + min(lane, kBinWaveBins), J.n_tel), qe, fe, le);
+    // log grids: the node wavelengths' base and step, the wavelength of the lane's edge node at
+    // rest (a node k's is lam_e e^{(k - qe) dln}, the exponent small), the whole-segment series,
+    // and 1 / the bin's width in wavelength
+    const bool lg = J.log_lambda != 0;
+    const float lam0 = (float)S.lam_start, dln = (float)S.lam_step;
+    const float lam_e = lg ? (float)(S.lam_start * exp((double)qe * S.lam_step)) : 0.f;
+    const float e1h = expm1_small(dln), phh = phi_small(dln);
+    const float inv_w = lg ? (float)(1.0 / (J.tel_start * exp((double)min(jb, J.n_tel - 1) * J.tel_step) *
+                                            2.0 * sinh(0.5 * J.tel_step)))
+                           : 1.f;
     const PrepRec *prep = J.prep;
     float acc = 0.f, tot = 0.f;
     int since = 0;
@@ -570,8 +605,15 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restri
         // the integral over the lane's edge segment from its node to the edge (P) and over the
         // whole segment (Tn); a bin's value is P(upper edge) - P(lower edge), plus the lower
         // segment's Tn when the upper edge lies in the next segment
-        const float P = a * fmaf(0.5f * a, s1 - s0, s0);
-        const float Tn = 0.5f * (s0 + s1);
+        float P, Tn;
+        if (lg) {
+          const float lamk = node_lambda(klo, qe, lam_e, lam0, dln);
+          P = log_partial(lamk, s0, s1 - s0, a, dln);
+          Tn = lamk * fmaf(s0, e1h, (s1 - s0) * phh);
+        } else {
+          P = a * fmaf(0.5f * a, s1 - s0, s0);
+          Tn = 0.5f * (s0 + s1);
+        }
         const float Ph = __shfl_down(P, 1, 64);
         const float vv = (Ph - P) + (khi > klo ? Tn : 0.f);
         v = empty ? 0.f : vv;
@@ -588,13 +630,19 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restri
           s1 = fmaf(r.a[1], ldf(rs, e + b1 + 4u, 0), s1);
           s1 = fmaf(r.a[2], ldf(rs, e + b2 + 4u, 0), s1);
           s1 = fmaf(r.a[3], ldf(rs, e + b3 + 4u, 0), s1);
-          v += seg_integral(s0, s1, k == klo ? a : 0.f, k == khi ? b : 1.f);
+          const float x = k == klo ? a : 0.f, y = k == khi ? b : 1.f;
+          if (lg) {
+            const float lamk = node_lambda(k, qe, lam_e, lam0, dln);
+            v += log_partial(lamk, s0, s1 - s0, y, dln) - log_partial(lamk, s0, s1 - s0, x, dln);
+          } else {
+            v += seg_integral(s0, s1, x, y);
+          }
         }
       }
       acc += v;
       if (++since == kCubeSubsum) { tot += acc; acc = 0.f; since = 0; }
     }
-    tot += acc;
+    tot = (tot + acc) * inv_w;
     if (act) {
       if (ch.slot < 0) J.cube_raw[(int64_t)ch.s * J.n_tel + jb] = tot;
       else J.partial[(int64_t)ch.slot * J.n_tel + jb] = tot;

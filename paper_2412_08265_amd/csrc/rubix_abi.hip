@@ -199,8 +199,8 @@ static int validate_jobs(const rubix_job *jobs, int n_jobs, Call call) {
       return fail(RUBIX_EINVAL, "job %d: a log-spaced telescope grid needs start > 0", k);
     if (j.resample != 0 && j.resample != 1)
       return fail(RUBIX_EINVAL, "job %d: resample must be 0 or 1", k);
-    if (j.resample == 1 && j.tel.log_spaced)
-      return fail(RUBIX_EINVAL, "job %d: bin-mean resampling needs linear grids", k);
+    if (j.resample == 1 && j.tel.log_spaced && call == CALL_BWD)
+      return fail(RUBIX_EINVAL, "job %d: no adjoint for bin-mean resampling on log grids", k);
     if (!(j.z_sys > -1.0) || !isfinite(j.z_sys)) return fail(RUBIX_EINVAL, "job %d: z_sys must be > -1", k);
     if (!isfinite(j.flux_scale)) return fail(RUBIX_EINVAL, "job %d: flux_scale not finite", k);
     for (int a = 0; a < 3; ++a)
@@ -237,11 +237,16 @@ static int validate_jobs(const rubix_job *jobs, int n_jobs, Call call) {
 
 // Every telescope grid must be of the SSP grid's kind (both uniform in lambda or in ln lambda).
 static int check_grid_kinds(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp) {
-  for (int k = 0; k < n_jobs; ++k)
+  for (int k = 0; k < n_jobs; ++k) {
     if (jobs[k].tel.log_spaced != ssp->lam.log_spaced)
       return fail(RUBIX_EINVAL, "job %d: telescope grid %s but SSP grid %s", k,
                   jobs[k].tel.log_spaced ? "log-spaced" : "linear",
                   ssp->lam.log_spaced ? "log-spaced" : "linear");
+    // the bin-mean kernel's segment weights on log grids are series in the SSP step
+    if (jobs[k].resample == 1 && ssp->lam.log_spaced && !(ssp->lam.step <= 0.05))
+      return fail(RUBIX_EINVAL, "job %d: bin-mean resampling on log grids needs an SSP step "
+                  "of at most 0.05 in ln(lambda)", k);
+  }
   return RUBIX_OK;
 }
 
@@ -348,7 +353,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
     d.log_lambda = j.tel.log_spaced;
     d.resample = j.resample;
     d.n_tiles_b = z.n_tiles_b;
-    d.bin_scale = ssp ? ssp->lam.step / j.tel.step : 1.0;
+    d.bin_scale = (ssp && !j.tel.log_spaced) ? ssp->lam.step / j.tel.step : 1.0;
     if (ssp && j.tel.log_spaced) {
       // node index of bin j at rest: q_off + j q_ratio (exact when the two grids coincide)
       d.q_off = ((log(j.tel.start) - log(ssp->lam.start)) - log1p(j.z_sys)) / ssp->lam.step;

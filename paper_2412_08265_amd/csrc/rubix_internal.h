@@ -106,7 +106,7 @@ struct JobDev {
                                                      // 1 = both grids uniform in ln(lambda)
   double q_off, q_ratio;  // log grids: rest-frame node index of bin j is q_off + j * q_ratio
   int32_t resample, n_tiles_b;  // 1 = bin-mean resampling; its tiles of kBinTL bins
-  double bin_scale;             // bin mean: dlam_ssp / dlam_tel
+  double bin_scale;             // bin mean: dlam_ssp / dlam_tel (linear grids), 1 (log grids)
   double bin_slope;                                  // d(node index)/d(bin) at rest
   double inv_opz, inv_ds;  // 1/(1+z_sys) and 1/dlam_ssp (linear grids: the rest-frame index)
   int32_t n_chunk_ub, n_comb_ub, lsf_r, psf_r;
@@ -226,10 +226,16 @@ __device__ __forceinline__ void split_index(const JobDev &J, const SspDev &S, in
   }
 }
 
-// The same for telescope bin edge e (the lower edge of bin e, the upper edge of bin e - 1, at
-// wavelength start + (e - 1/2) step). Linear grids (bin-mean resampling).
+// The same for telescope bin edge e (the lower edge of bin e, the upper edge of bin e - 1): at
+// wavelength start + (e - 1/2) step on linear grids; on log grids at ln lambda = ln start +
+// (e - 1/2) step, where Q = q_off + (e - 1/2) q_ratio and the Doppler factor is 1.
 __device__ __forceinline__ void bin_edge(const JobDev &J, const SspDev &S, int e, int &qi,
                                          float &qf, float &lamf) {
+  if (J.log_lambda) {
+    split_q(J.q_off + ((double)e - 0.5) * J.q_ratio, qi, qf);
+    lamf = 1.0f;
+    return;
+  }
   const double lam = J.tel_start + ((double)e - 0.5) * J.tel_step;
   split_q(rest_q(J, S, lam), qi, qf);
   lamf = (float)lam;
