@@ -529,6 +529,9 @@ __device__ __forceinline__ float log_partial(float lamk, float s0, float d, floa
   return lamk * fmaf(s0, expm1_small(h), d * a * phi_small(h));
 }
 
+// One instance per grid kind (every job of a call shares the SSP grid's kind), so the linear
+// kernel carries none of the log path's registers.
+template <bool kLog>
 __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restrict__ T) {
   __shared__ float slots[kCubeThreads / 64][64];
   const SspDev &S = T->h.ssp;
@@ -547,6 +550,7 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restri
     const int tile = (int)(local / J.n_chunk_ub);
     const int c = (int)(local - (int64_t)tile * J.n_chunk_ub);
     if (c >= ((CInt *)J.counts)[0]) continue;
+    if ((J.log_lambda != 0) != kLog) continue;             // the other instance's job
     const int jw = tile * kBinTL + w * kBinWaveBins;
     if (jw >= J.n_tel) continue;                           // wave-uniform
     CInt *chp = (CInt *)(J.chunks + c);
@@ -561,7 +565,7 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube_bin(const Table *__restri
     // log grids: the node wavelengths' base and step, the wavelength of the lane's edge node at
     // rest (a node k's is lam_e e^{(k - qe) dln}, the exponent small), the whole-segment series,
     // and 1 / the bin's width in wavelength
-    const bool lg = J.log_lambda != 0;
+    constexpr bool lg = kLog;
     const float lam0 = (float)S.lam_start, dln = (float)S.lam_step;
     const float lam_e = lg ? (float)(S.lam_start * exp((double)qe * S.lam_step)) : 0.f;
     const float e1h = expm1_small(dln), phh = phi_small(dln);
@@ -693,7 +697,14 @@ hipError_t launch_cube(const Table *dt, const TableHeader &h, int cap, hipStream
   if ((g = grid_for(h.total[K_CUBE], cap)))
     hipLaunchKernelGGL(k_cube, dim3(g), dim3(kCubeThreads), 0, s, dt);
   if ((g = grid_for(h.total[K_CUBEB], cap)))
-    hipLaunchKernelGGL(k_cube_bin, dim3(g), dim3(kCubeThreads), 0, s, dt);
+  {
+    // the instance of the SSP grid's kind; both (each skipping the other kind's jobs) when the
+    // table lives only on the device and its kind is not known here (log_lambda = -1)
+    if (h.ssp.log_lambda != 1)
+      hipLaunchKernelGGL(k_cube_bin<false>, dim3(g), dim3(kCubeThreads), 0, s, dt);
+    if (h.ssp.log_lambda != 0)
+      hipLaunchKernelGGL(k_cube_bin<true>, dim3(g), dim3(kCubeThreads), 0, s, dt);
+  }
   if (timed) (void)hipEventRecord(t_cube_events[1], s);
   if ((g = grid_for(h.total[K_COMB], cap)))
     hipLaunchKernelGGL(k_combine, dim3(g), dim3(kCubeThreads), 0, s, dt);
@@ -714,7 +725,7 @@ int cube_kernel_kind(const void *f) {
   if (f == (const void *)k_prep) return K_PREP;
   if (f == (const void *)k_chunks) return K_CHUNK;
   if (f == (const void *)k_vbound) return K_VB;
-  if (f == (const void *)k_cube_bin) return K_CUBEB;
+  if (f == (const void *)k_cube_bin<false> || f == (const void *)k_cube_bin<true>) return K_CUBEB;
   if (f == (const void *)k_cube) return K_CUBE;
   if (f == (const void *)k_combine) return K_COMB;
   return -1;

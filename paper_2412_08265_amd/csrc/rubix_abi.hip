@@ -671,6 +671,7 @@ int rubix_forward_packed(const void *dev_table, int grid_blocks, int max_psf_rad
   TableHeader h;
   memset(&h, 0, sizeof h);
   for (int q = 0; q < NK; ++q) h.total[q] = grid_blocks;
+  h.ssp.log_lambda = -1;       // grid kind known only to the device table
   h.max_passes = max_sort_passes;
   h.max_psf_r = max_psf_radius;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -726,6 +727,7 @@ int rubix_graph_create(const void *dev_table, int max_jobs, int max_psf_radius,
     TableHeader h;
     memset(&h, 0, sizeof h);
     for (int q = 0; q < NK; ++q) h.total[q] = 1;
+    h.ssp.log_lambda = -1;     // grid kind known only to the device table
     h.max_passes = max_sort_passes;
     h.max_psf_r = max_psf_radius;
     const Table *dt = static_cast<const Table *>(dev_table);
@@ -764,7 +766,9 @@ int rubix_graph_create(const void *dev_table, int max_jobs, int max_psf_radius,
     g->kinds.push_back(kind);
   }
   if (e != hipSuccess) { graph_free(g); return device_status(e, "graph kernel nodes"); }
-  const size_t expect = 3u * max_sort_passes + 2 + 6 + 4;
+  // rotate/bin: 3 per sort pass + rotate + segment offsets; cube: chunks, bounds, prep, the
+  // bin-centre sum, the bin-mean sum's two instances (linear and log grids), combine; PSF/LSF: 4
+  const size_t expect = 3u * max_sort_passes + 2 + 7 + 4;
   if (g->nodes.size() != expect) {
     const size_t got = g->nodes.size();
     graph_free(g);
