@@ -591,8 +591,6 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
       dL/dphi_k = sum_i dL/dvlos_i (dR/dphi_k v_i)_z,   dL/dv_i = dL/dvlos_i R[2, :].
     Particles outside the field get zero. Positions get no gradient (binning is piecewise
     constant)."""
-    if cfg.resample == 1 and cfg.log_lambda:
-        raise NotImplementedError("no adjoint for bin-mean resampling on log grids")
     if fw is None:
         fw = forward(p, cfg, with_cube=False)
     R, key, vlos = fw["R"], fw["key"], fw["vlos"]
@@ -627,8 +625,8 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
         beta = v / C_KMS
         ja, jz, ta, tz, w, ina, inz = ssp_weights(age, met, la_nodes, mz_nodes)
         if cfg.resample == 1:
-            _adjoint_bin_mean(cfg, G, key[ii], age, mass, v, ja, jz, ta, tz, w, ina, inz,
-                              out, sel)
+            fn = _adjoint_bin_mean_log if cfg.log_lambda else _adjoint_bin_mean
+            fn(cfg, G, key[ii], age, mass, v, ja, jz, ta, tz, w, ina, inz, out, sel)
             continue
         q = doppler_index(cfg, v)
         k, valid = node_decision(cfg, v, nl)
@@ -717,6 +715,48 @@ def _adjoint_bin_mean(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, inz, o
         inside = (q > 0.0) & (q < nl - 1.0)
         term += sgn * np.where(inside, linear_at(S, q) * (-edge / f2), 0.0)
     out["vlos"][sel] = B * mass * np.sum(g * term, axis=1) / C_KMS
+
+
+def _adjoint_bin_mean_log(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, inz, out, sel):
+    """Gradients for the bin-mean resampling on log grids, particles `sel` of the chunk.
+
+    f_i(j) = fs m_i / dlam_j sum_c w_ic I_c(j), I_c(j) the integral over rest wavelength of
+    corner c's interpolant (linear in the log-grid index) between the bin's rest-frame edges,
+    clipped to the grid. With X_ic = sum_j G[s, j] I_c(j) / dlam_j the mass, age and [M/H]
+    gradients take the form of the linear-grid bin mean with B = fs. The integrand
+    Slin(q) lam(q) dln_ssp does not depend on beta; the limits move with
+    dq/dbeta = -1/((1+beta) dln_ssp) at both edges (Leibniz rule), so
+      dL/dbeta_i = -fs m_i / (1+beta_i) sum_j G[s, j] / dlam_j
+                   (Slin_i(q_hi) lam(q_hi) [q_hi inside] - Slin_i(q_lo) lam(q_lo) [q_lo inside]),
+    an edge outside (0, n-1) being clipped and contributing nothing."""
+    T = cfg.ssp_flux
+    nl = T.shape[2]
+    la_nodes, mz_nodes = cfg.log_age_nodes, cfg.met_nodes
+    width = cfg.tel_lambda() * (2.0 * math.sinh(0.5 * cfg.tel_step))
+    g = G[keys] / width[None, :]                           # [m, n_tel]
+    q_lo, q_hi = bin_edge_indices_log(cfg, v)
+    corners = [(ja, jz), (ja, jz + 1), (ja + 1, jz), (ja + 1, jz + 1)]
+    X = np.zeros((keys.shape[0], 4))
+    for c, (a_, z_) in enumerate(corners):
+        X[:, c] = np.sum(g * integral_log_weighted(T[a_, z_], q_lo, q_hi, cfg.ssp_lam_start,
+                                                   cfg.ssp_lam_step), axis=1)
+    B = cfg.flux_scale
+    out["mass"][sel] = B * np.sum(w * X, axis=1)
+    dwa = np.stack([-(1 - tz), -tz, (1 - tz), tz], axis=-1)
+    dwz = np.stack([-(1 - ta), (1 - ta), -ta, ta], axis=-1)
+    du_a = la_nodes[ja + 1] - la_nodes[ja]
+    du_z = mz_nodes[jz + 1] - mz_nodes[jz]
+    out["age"][sel] = np.where(ina, B * mass * np.sum(dwa * X, axis=1) / du_a
+                               / (age * math.log(10.0)), 0.0)
+    out["met"][sel] = np.where(inz, B * mass * np.sum(dwz * X, axis=1) / du_z, 0.0)
+    S = interp_templates(T, ja, jz, w)
+    beta = np.asarray(v, dtype=np.float64) / C_KMS
+    term = np.zeros_like(q_lo)
+    for q, sgn in ((q_hi, 1.0), (q_lo, -1.0)):
+        inside = (q > 0.0) & (q < nl - 1.0)
+        lam_r = cfg.ssp_lam_start * np.exp(q * cfg.ssp_lam_step)
+        term += sgn * np.where(inside, linear_at(S, q) * lam_r, 0.0)
+    out["vlos"][sel] = (-B * mass / (1.0 + beta)) * np.sum(g * term, axis=1) / C_KMS
 
 
 def _adjoint_part(part):

@@ -452,12 +452,14 @@ def test_log_bin_average_conserves_flux_and_a_constant():
     np.testing.assert_allclose(f, 3.0 * 2.0 / (1 + v / O.C_KMS), rtol=1e-11)
 
 
-def test_log_bin_average_refuses_the_adjoint():
-    ssp = synth.make_ssp(3, 3, 4000.0, 1e-4, 50, log_lambda=True)
-    cfg = _cfg(ssp=ssp, resample=1)
-    p = _single()
-    with pytest.raises(NotImplementedError):
-        O.adjoint(p, cfg, np.zeros((cfg.n_spaxels, cfg.n_tel)))
+def test_log_bin_average_adjoint_euler_identity():
+    """Log grids: the raw cube is homogeneous of degree 1 in the masses, so
+    sum_i m_i dL/dm_i = <G, C_raw> for the linear functional L = <G, C_raw>."""
+    p, cfg, fw, G = _bin_mean_log_setup(seed=9)
+    g = O.adjoint(p, cfg, G, fw)
+    lhs = np.sum(p.mass.astype(float) * g["mass"])
+    rhs = np.vdot(G, fw["cube_raw"])
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
 
 
 def test_out_of_band_is_zero_and_last_node_is_included():
@@ -668,11 +670,24 @@ def _bin_mean_setup(seed=31, n=220):
     return p, cfg, fw, G
 
 
-def test_bin_mean_adjoint_matches_central_differences():
+def _bin_mean_log_setup(seed=37, n=220):
+    ssp = synth.make_ssp(7, 5, 4000.0, 5.0e-4, 220, log_lambda=True)
+    # bins of 6.7e-4 in ln(lambda) (coarser than the nodes) reaching the red end of the SSP grid
+    cfg = _cfg(nx=9, ny=8, s=1.0, angles=(math.radians(55), 0.2, 0.3), ssp=ssp,
+               tel=(4003.3, 6.7e-4, 165), z_sys=0.002, resample=1)
+    p = _parts(n, seed, r=4.5)
+    fw = O.forward(p, cfg)
+    G = np.random.default_rng(seed).normal(size=fw["cube_raw"].shape)
+    return p, cfg, fw, G
+
+
+@pytest.mark.parametrize("grid", ["linear", "log"])
+def test_bin_mean_adjoint_matches_central_differences(grid):
     """The bin-mean value is C1 in the velocity (the integral of a continuous piecewise-linear
     spectrum), so central differences of the oracle's own forward under the linear functional
-    L = <G, C_raw> pin every gradient, the Leibniz term for the velocity included."""
-    p, cfg, fw, G = _bin_mean_setup()
+    L = <G, C_raw> pin every gradient, the Leibniz term for the velocity included; on linear
+    grids and on grids uniform in ln(lambda)."""
+    p, cfg, fw, G = _bin_mean_setup() if grid == "linear" else _bin_mean_log_setup()
     g = O.adjoint(p, cfg, G, fw)
     key, vlos = fw["key"], fw["vlos"]
     rng = np.random.default_rng(1)
@@ -691,13 +706,17 @@ def test_bin_mean_adjoint_matches_central_differences():
 
         m, a, z, v = float(p.mass[i]), float(p.age[i]), float(p.met[i]), float(vlos[i])
         la, mz = cfg.log_age_nodes, cfg.met_nodes
-        if np.min(np.abs(la - math.log10(a))) < 1e-4 or np.min(np.abs(mz - z)) < 1e-4:
+        if np.min(np.abs(la - math.log10(a))) < 1e-3 or np.min(np.abs(mz - z)) < 1e-3:
             continue
+        # steps: the oracle's log-grid integral differences larger prefix sums, so its central
+        # differences need larger steps against rounding (the spectrum is linear in [M/H] and in
+        # log age inside a cell, so they stay exact there)
+        hm, ha, hz, hv = (1e-6, 1e-6, 1e-6, 1e-3) if grid == "linear" else (1e-4, 1e-4 * a, 1e-4, 0.3)
         for name, h, kw_p, kw_m in (
-                ("mass", 1e-6 * m, dict(mass=[m + 1e-6 * m]), dict(mass=[m - 1e-6 * m])),
-                ("age", 1e-6, dict(age=[a + 1e-6]), dict(age=[a - 1e-6])),
-                ("met", 1e-6, dict(met=[z + 1e-6]), dict(met=[z - 1e-6])),
-                ("vlos", 1e-3, dict(vlos=v + 1e-3), dict(vlos=v - 1e-3))):
+                ("mass", hm * m, dict(mass=[m + hm * m]), dict(mass=[m - hm * m])),
+                ("age", ha, dict(age=[a + ha]), dict(age=[a - ha])),
+                ("met", hz, dict(met=[z + hz]), dict(met=[z - hz])),
+                ("vlos", hv, dict(vlos=v + hv), dict(vlos=v - hv))):
             fd = float(np.dot(G[key[i]], spec(**kw_p) - spec(**kw_m))) / (2 * h)
             an = g[name][i]
             scale = max(abs(fd), 1e-3 * np.abs(g[name]).max())
