@@ -186,8 +186,7 @@ def main():
                     default="centre",
                     help="resampling reading / grid kind of the forward step: bin-centre sampling "
                          "on linear grids (default, the headline), bin mean (flux conserving), "
-                         "grids uniform in ln(lambda), or the bin mean on those grids (forward "
-                         "only: no adjoint there)")
+                         "grids uniform in ln(lambda), or the bin mean on those grids")
     ap.add_argument("--serve", action="store_true",
                     help="print the serving report (request stream, batched graph path vs "
                          "one-at-a-time plain launches) instead of the forward-step line")
@@ -216,7 +215,6 @@ def main():
         w = synth.large_log_workload(n=args.n)
         if args.variant == "binmeanlog":
             w.resample = 1
-            args.no_backward = True          # the bin mean on log grids has no adjoint
     else:
         w = synth.large_workload(n=args.n)
         if args.variant == "binmean":

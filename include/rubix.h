@@ -111,7 +111,7 @@ typedef struct {
   float      *cube_raw;         /* [ny][nx][tel.n] written by rubix_cube                       */
   float      *cube;             /* [ny][nx][tel.n] optional; rubix_psf_lsf may write it        */
   int32_t     resample;         /* 0: bin-centre sampling (below); 1: bin mean (flux conserving;
-                                   on log grids forward only, SSP step <= 0.05)                 */
+                                   on log grids the SSP step must be <= 0.05)                   */
   int32_t     reserved;         /* 0                                                            */
 } rubix_job;
 
@@ -152,7 +152,7 @@ int rubix_rotate_bin(const rubix_job *jobs, int n_jobs, void *ws, size_t ws_byte
  *    f_i(j) = flux_scale m_i / dlam_j * integral of Slin_i over rest wavelength between the bin's
  *    rest-frame edges, Slin linear in the log-grid index, dlam_j = 2 lam_j sinh(step/2) (each
  *    segment's exponential weight evaluated by a four-term series, so the SSP step must be at
- *    most 0.05; no adjoint).
+ *    most 0.05).
  *  - cube_raw[s][j] = sum of f_i(lam_j) over the particles of spaxel s, FP32, accumulated per
  *    work item in a fixed order (deterministic; independent of the other jobs in the batch). */
 int rubix_cube(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp, void *ws,
@@ -176,7 +176,8 @@ int rubix_psf_lsf(const rubix_job *jobs, int n_jobs, const float *const *in, flo
  * Particles outside the field get 0. Derivatives at SSP nodes / wavelength nodes take the
  * right-hand cell; clamped age or metallicity gives 0 along that axis. Positions get no gradient.
  * Bin-mean jobs (resample = 1): the integrand does not depend on beta, the bin's limits do, so
- * d_vlos is the Leibniz sum over the bin edges of Slin at the edge times its d q/d beta; an edge
+ * d_vlos is the Leibniz sum over the bin edges of the integrand at the edge times its dq/dbeta
+ * (on log grids the integrand is Slin lam dln and dq/dbeta = -1/((1+beta) dln)); an edge
  * clipped to the SSP grid's end (q <= 0 or q >= n-1) contributes nothing.
  * Reads key, perm, seg_off, vlos from rubix_rotate_bin. Per-particle dot products are reduced in
  * FP64 in a fixed order (deterministic). */

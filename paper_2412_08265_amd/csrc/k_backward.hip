@@ -227,6 +227,13 @@ __device__ __forceinline__ SegTerms seg_terms(float w0, float w1, float w2, floa
 // of its edge's segment and integrates that segment, and a bin combines its two edges' partial
 // integrals. Otherwise each lane walks its bin's segments with direct gathers. Each lane
 // accumulates its bins in increasing order; the wave's sums are reduced in FP64.
+// Log grids (kLog): the integrals run over rest wavelength (each segment's partials carry the
+// weights E1 and Phi and the node's wavelength, as in the forward kernel), each bin's gradient
+// is divided by the bin's width, and the Leibniz term of an edge is Slin lam_edge dln (both
+// edges move by dq/dbeta = -1/((1+beta) dln)); where both edges are inside,
+// lam_hi S_hi - lam_lo S_lo = lam_lo ((S_hi - S_lo) + S_hi expm1(dln_tel)), the rest-frame
+// edges' wavelength ratio being e^{dln_tel}.
+template <bool kLog>
 __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ T) {
   __shared__ float rows[4][4][64];     // [wave][corner][node - n0]
   const SspDev &S = T->h.ssp;
@@ -247,6 +254,12 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
     const int64_t pbase = (vb - J.vb_start[K_BWDB]) * kBwdParticles;
     const int n_in = J.seg_off[J.n_s];
     const float dlam = (float)J.tel_step;
+    // log grids: node wavelengths, whole-segment weights, the edges' wavelength ratio - 1, and
+    // the bins' widths lam_j 2 sinh(dln_tel / 2) = w0 e^{j dln_tel}
+    const float lam0 = (float)S.lam_start, dln = (float)S.lam_step;
+    const float e1h = expm1_small(dln), phh = phi_small(dln);
+    const float rt1 = kLog ? (float)expm1(J.tel_step) : 0.f;
+    const float inv_w0 = kLog ? (float)(1.0 / (J.tel_start * 2.0 * sinh(0.5 * J.tel_step))) : 0.f;
     const __amdgpu_buffer_rsrc_t rt =
         __builtin_amdgcn_make_buffer_rsrc((void *)J.bintab, (short)0, (J.n_tel + 1) * 16, 0x00020000);
     for (int q = w; q < kBwdParticles; q += 4) {
@@ -265,7 +278,8 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
       for (int jw = 0; jw < J.n_tel; jw += kBinWaveBins) {
         const bool act = (lane < kBinWaveBins) && (jw + lane < J.n_tel);
         const int jc = min(jw + min(lane, kBinWaveBins - 1), J.n_tel - 1);
-        const float graw = ld_grad(rg, jc);
+        float graw = ld_grad(rg, jc);
+        if (kLog) graw *= inv_w0 * expf(-(float)jc * dlam);      // / the bin's width
         // lane l splits edge jw + l, the lower edge of its bin; the upper edge is the next lane's
         // (lanes past the window's last edge take it, so the node span stays the bins')
         const float4 lo = ld_bintab(rt, min(jw + min(lane, kBinWaveBins), J.n_tel));
@@ -284,6 +298,13 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
         const int nmax = __builtin_amdgcn_readlane(khi, 63) + 1;
         const bool multi = !empty && (khi - klo > 1);
         float Is = 0.f, Ia = 0.f, Iz = 0.f, D = 0.f, s_lo = 0.f, s_hi = 0.f;
+        // log grids: wavelength of the lower edge's node and of the edge itself (every lane, so
+        // that the previous lane can take its upper edge's)
+        float lamk_lo = 0.f, lam_lo = 0.f;
+        if (kLog) {
+          lamk_lo = lam0 * expf((float)klo * dln);
+          lam_lo = fmaf(lamk_lo, expm1_small(a * dln), lamk_lo);
+        }
         if (nmax - n0 <= 63 && !__builtin_amdgcn_ballot_w64(multi)) {
           // every lane's nodes klo .. khi+1 lie in n0 .. n0+63; rows read past the end of a row
           // (or of the grid, as zeros) only feed lanes that do not use them
@@ -307,12 +328,22 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
           // (T); a bin's integrals are P(upper edge) - P(lower edge), plus the lower segment's T
           // when the upper edge lies in the next segment, the upper values coming from the next
           // lane
-          const SegTerms te = seg_terms(w0, w1, w2, w3, ta, tz, pv, qv, 0.f, a);
+          SegTerms te = seg_terms(w0, w1, w2, w3, ta, tz, pv, qv, 0.f, a);
           const float ap = (1.f - tz) * (pv[2] - pv[0]) + tz * (pv[3] - pv[1]);
           const float aq = (1.f - tz) * (qv[2] - qv[0]) + tz * (qv[3] - qv[1]);
           const float zp = (1.f - ta) * (pv[1] - pv[0]) + ta * (pv[3] - pv[2]);
           const float zq = (1.f - ta) * (qv[1] - qv[0]) + ta * (qv[3] - qv[2]);
-          const float TS = fmaf(0.5f, te.ds, te.p), TA = 0.5f * (ap + aq), TZ = 0.5f * (zp + zq);
+          float TS = fmaf(0.5f, te.ds, te.p), TA = 0.5f * (ap + aq), TZ = 0.5f * (zp + zq);
+          if (kLog) {
+            // the same partials and wholes over rest wavelength
+            const float lamk = lamk_lo;
+            te.is = log_partial(lamk, te.p, te.ds, a, dln);
+            te.ia = log_partial(lamk, ap, aq - ap, a, dln);
+            te.iz = log_partial(lamk, zp, zq - zp, a, dln);
+            TS = lamk * fmaf(te.p, e1h, te.ds * phh);
+            TA = lamk * fmaf(ap, e1h, (aq - ap) * phh);
+            TZ = lamk * fmaf(zp, e1h, (zq - zp) * phh);
+          }
           const float Se = fmaf(a, te.ds, te.p);
           const float PSn = __shfl_down(te.is, 1, 64), PAn = __shfl_down(te.ia, 1, 64);
           const float PZn = __shfl_down(te.iz, 1, 64), dSn = __shfl_down(te.ds, 1, 64);
@@ -336,17 +367,36 @@ __global__ __launch_bounds__(256) void k_bwd_dots_bin(const Table *__restrict__ 
             }
             const float x = k == klo ? a : 0.f, xe = k == khi ? b : 1.f;
             const SegTerms t = seg_terms(w0, w1, w2, w3, ta, tz, pv, qv, x, xe);
-            Is += t.is;
-            Ia += t.ia;
-            Iz += t.iz;
+            if (kLog) {
+              const float lamk = lam0 * expf((float)k * dln);
+              const float ap = (1.f - tz) * (pv[2] - pv[0]) + tz * (pv[3] - pv[1]);
+              const float aq = (1.f - tz) * (qv[2] - qv[0]) + tz * (qv[3] - qv[1]);
+              const float zp = (1.f - ta) * (pv[1] - pv[0]) + ta * (pv[3] - pv[2]);
+              const float zq = (1.f - ta) * (qv[1] - qv[0]) + ta * (qv[3] - qv[2]);
+              Is += log_partial(lamk, t.p, t.ds, xe, dln) - log_partial(lamk, t.p, t.ds, x, dln);
+              Ia += log_partial(lamk, ap, aq - ap, xe, dln) - log_partial(lamk, ap, aq - ap, x, dln);
+              Iz += log_partial(lamk, zp, zq - zp, xe, dln) - log_partial(lamk, zp, zq - zp, x, dln);
+            } else {
+              Is += t.is;
+              Ia += t.ia;
+              Iz += t.iz;
+            }
             D = fmaf(t.ds, xe - x, D);
             s_lo = k == klo ? fmaf(a, t.ds, t.p) : s_lo;
             s_hi = k == khi ? fmaf(b, t.ds, t.p) : s_hi;
           }
         }
         float e;
-        if (in_lo && in_hi) e = fmaf(lo.z, D, dlam * s_hi);
-        else e = (in_hi ? lhi * s_hi : 0.f) - (in_lo ? lo.z * s_lo : 0.f);
+        if (kLog) {
+          // Leibniz terms per unit of dq/dbeta: Slin lam dln at each edge
+          const float lam_hi = __shfl_down(lam_lo, 1, 64);
+          if (in_lo && in_hi) e = dln * lam_lo * fmaf(s_hi, rt1, D);
+          else e = dln * ((in_hi ? lam_hi * s_hi : 0.f) - (in_lo ? lam_lo * s_lo : 0.f));
+        } else if (in_lo && in_hi) {
+          e = fmaf(lo.z, D, dlam * s_hi);
+        } else {
+          e = (in_hi ? lhi * s_hi : 0.f) - (in_lo ? lo.z * s_lo : 0.f);
+        }
         // an empty bin, or a lane past the window's bins, adds nothing
         const float g = (act && !empty) ? graw : 0.f;
         sm = fmaf(g, Is, sm);
@@ -492,7 +542,12 @@ hipError_t launch_backward(const Table *dt, const TableHeader &h, int cap, hipSt
   int g;
   if ((g = grid_for(h.total[K_BINTAB], cap))) hipLaunchKernelGGL(k_bintab, dim3(g), dim3(256), 0, s, dt);
   if ((g = grid_for(h.total[K_BWD], cap))) hipLaunchKernelGGL(k_bwd_dots, dim3(g), dim3(256), 0, s, dt);
-  if ((g = grid_for(h.total[K_BWDB], cap))) hipLaunchKernelGGL(k_bwd_dots_bin, dim3(g), dim3(256), 0, s, dt);
+  if ((g = grid_for(h.total[K_BWDB], cap))) {
+    if (h.ssp.log_lambda)
+      hipLaunchKernelGGL(k_bwd_dots_bin<true>, dim3(g), dim3(256), 0, s, dt);
+    else
+      hipLaunchKernelGGL(k_bwd_dots_bin<false>, dim3(g), dim3(256), 0, s, dt);
+  }
   if ((g = grid_for(h.total[K_FIN], cap))) hipLaunchKernelGGL(k_bwd_final, dim3(g), dim3(kFinThreads), 0, s, dt);
   if ((g = grid_for(h.total[K_ANG], cap))) hipLaunchKernelGGL(k_bwd_angles, dim3(g), dim3(256), 0, s, dt);
   return hipGetLastError();

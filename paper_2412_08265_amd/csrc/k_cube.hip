@@ -510,25 +510,6 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
 // ABI admits steps up to 0.05, where the next terms are below 1e-7), and each bin's sum is divided
 // by its width in wavelength.
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ float expm1_small(float h) {
-  return h * fmaf(h, fmaf(h, fmaf(h, 1.f / 24.f, 1.f / 6.f), 0.5f), 1.f);
-}
-__device__ __forceinline__ float phi_small(float h) {
-  return h * fmaf(h, fmaf(h, fmaf(h, 1.f / 30.f, 0.125f), 1.f / 3.f), 0.5f);
-}
-// wavelength of node k from the lane's reference node qe (wavelength lam_e): a short series in
-// the small exponent (k - qe) dln, or the exponential itself where the exponent is not small
-__device__ __forceinline__ float node_lambda(int k, int qe, float lam_e, float lam0, float dln) {
-  const float x = (float)(k - qe) * dln;
-  if (fabsf(x) <= 0.05f) return fmaf(lam_e, expm1_small(x), lam_e);
-  return lam0 * expf((float)k * dln);
-}
-// integral over rest wavelength of the segment from node k (value s0, slope d) to fraction a
-__device__ __forceinline__ float log_partial(float lamk, float s0, float d, float a, float dln) {
-  const float h = a * dln;
-  return lamk * fmaf(s0, expm1_small(h), d * a * phi_small(h));
-}
-
 // One instance per grid kind (every job of a call shares the SSP grid's kind), so the linear
 // kernel carries none of the log path's registers.
 template <bool kLog>

@@ -199,8 +199,6 @@ static int validate_jobs(const rubix_job *jobs, int n_jobs, Call call) {
       return fail(RUBIX_EINVAL, "job %d: a log-spaced telescope grid needs start > 0", k);
     if (j.resample != 0 && j.resample != 1)
       return fail(RUBIX_EINVAL, "job %d: resample must be 0 or 1", k);
-    if (j.resample == 1 && j.tel.log_spaced && call == CALL_BWD)
-      return fail(RUBIX_EINVAL, "job %d: no adjoint for bin-mean resampling on log grids", k);
     if (!(j.z_sys > -1.0) || !isfinite(j.z_sys)) return fail(RUBIX_EINVAL, "job %d: z_sys must be > -1", k);
     if (!isfinite(j.flux_scale)) return fail(RUBIX_EINVAL, "job %d: flux_scale not finite", k);
     for (int a = 0; a < 3; ++a)

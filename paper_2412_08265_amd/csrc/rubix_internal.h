@@ -241,6 +241,28 @@ __device__ __forceinline__ void bin_edge(const JobDev &J, const SspDev &S, int e
   lamf = (float)lam;
 }
 
+// Log grids (bin mean): the weight of rest wavelength over a segment, by Taylor series in
+// h = (fraction) * dln: E1(h) = e^h - 1 and Phi(h) = e^h - (e^h - 1)/h, four terms each (the ABI
+// admits SSP steps up to 0.05, where the next terms are below 1e-7).
+__device__ __forceinline__ float expm1_small(float h) {
+  return h * fmaf(h, fmaf(h, fmaf(h, 1.f / 24.f, 1.f / 6.f), 0.5f), 1.f);
+}
+__device__ __forceinline__ float phi_small(float h) {
+  return h * fmaf(h, fmaf(h, fmaf(h, 1.f / 30.f, 0.125f), 1.f / 3.f), 0.5f);
+}
+// wavelength of node k from the lane's reference node qe (wavelength lam_e): a short series in
+// the small exponent (k - qe) dln, or the exponential itself where the exponent is not small
+__device__ __forceinline__ float node_lambda(int k, int qe, float lam_e, float lam0, float dln) {
+  const float x = (float)(k - qe) * dln;
+  if (fabsf(x) <= 0.05f) return fmaf(lam_e, expm1_small(x), lam_e);
+  return lam0 * expf((float)k * dln);
+}
+// integral over rest wavelength of the segment from node k (value s0, slope d) to fraction a
+__device__ __forceinline__ float log_partial(float lamk, float s0, float d, float a, float dln) {
+  const float h = a * dln;
+  return lamk * fmaf(s0, expm1_small(h), d * a * phi_small(h));
+}
+
 // Launchers (one per translation unit); grid = number of blocks (persistent if < total).
 hipError_t launch_upload(const void *host_table, size_t bytes, void *dev_table, hipStream_t s);
 hipError_t launch_rotate_bin(const Table *dt, const TableHeader &h, int grid_cap, hipStream_t s);

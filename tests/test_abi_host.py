@@ -197,7 +197,7 @@ def test_resample_mode_is_validated(lib):
     j.resample = 2
     assert _ws_size(lib, [j])[0] == _lib.RUBIX_EINVAL
     j.resample = 1
-    j.tel = ops.RubixLGrid(4000.0, 1.6e-4, 300, 1)    # bin mean on log grids: a forward job
+    j.tel = ops.RubixLGrid(4000.0, 1.6e-4, 300, 1)    # bin mean on log grids
     assert _ws_size(lib, [j])[0] == _lib.RUBIX_OK
     lssp, keep_l = _ssp_c([-1, 0, 1], [-2, 0])
     lssp.lam = ops.RubixLGrid(3600.0, 1.6e-4, 100, 1)
@@ -205,12 +205,11 @@ def test_resample_mode_is_validated(lib):
     lssp.lam = ops.RubixLGrid(3600.0, 0.06, 100, 1)    # beyond the step its series admit
     rc = _ws_size(lib, [j], ctypes.byref(lssp))[0]
     assert rc == _lib.RUBIX_EINVAL and b"0.05" in lib.rubix_last_error()
-    lssp.lam = ops.RubixLGrid(3600.0, 1.6e-4, 100, 1)
     ptrs = (ctypes.c_void_p * 1)(0x1000)
-    # ... and no adjoint for it
+    # the adjoint applies the same limit before any device work
     rc = lib.rubix_cube_backward(_arr(j), 1, ctypes.byref(lssp), ptrs, ptrs, ptrs, ptrs, ptrs,
                                  None, 0x1000, 0x1000, 1 << 40, None)
-    assert rc == _lib.RUBIX_EINVAL and b"no adjoint" in lib.rubix_last_error()
+    assert rc == _lib.RUBIX_EINVAL and b"0.05" in lib.rubix_last_error()
     j.tel = ops.RubixLGrid(4000.0, 1.25, 300, 0)
     ssp, keep = _ssp_c([-1, 0, 1], [-2, 0])
     # the adjoint validates the mode before any device work

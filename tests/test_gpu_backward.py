@@ -184,6 +184,30 @@ def test_ragged_particle_counts_backward(n):
     assert np.abs(a[:2] - b[:2]).max() <= 2e-5 * max(np.abs(b[:2]).max(), 1e-300) and a[2] == 0.0
 
 
+@pytest.mark.parametrize("ratio,n_tel,seed", [(1.3, 1300, 61), (2.6, 660, 67), (0.6, 2800, 71)])
+def test_log_grid_bin_mean_seeded_gradient(ratio, n_tel, seed):
+    """Adjoint of the bin mean on grids uniform in ln(lambda): the corner integrals over rest
+    wavelength (divided by the bin widths) and the Leibniz terms Slin lam dln at the moving
+    edges. Bins of 1.3, 2.6 and 0.6 SSP steps, the band running past both ends of the SSP grid.
+    Oracle on every particle and FP64 finite differences (steps sized against the oracle's
+    prefix-sum rounding)."""
+    p = synth.make_galaxy(3000, seed)
+    ssp = synth.cached_ssp(12, 6, 3600.0, 3.0e-4, 1000, log_lambda=True)
+    step = ratio * 3.0e-4
+    w = synth.Workload(f"grad-binmean-log-{ratio}", p, (55.0, 12.0, 20.0), 14, 12, 2.0,
+                       3600.0 * math.exp(-5 * step), step, n_tel, ssp, psf_sigma_spx=1.2,
+                       lsf_sigma_A=6.0, z_sys=0.002, log_lambda=True, resample=1)
+    cfg = O.config_from_workload(w)
+    fo = O.forward(w.particles, cfg)
+    rng = np.random.default_rng(seed)
+    G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
+    _, g = _gpu_grads(w, G)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo)
+    _compare(g, ref, 2e-5, f"log bin-mean x{ratio} seeded-G")
+    _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False, h_vlos=0.03,
+              h_met=1e-3, h_age=1e-4, age_rel=True)
+
+
 def _fd_delta_L(cfg, G, s, dplus, dminus, quadratic=True):
     """L(+) - L(-) when one particle of spaxel s changes its spectrum by d+/d- (FP64).
     For the loss L = |A C - T|^2 / 2 with G = A(A C - T):
@@ -203,7 +227,8 @@ def _fd_delta_L(cfg, G, s, dplus, dminus, quadratic=True):
     return float(np.dot(dplus - dminus, G[s])) + 0.5 * P2 * (np.dot(Lp, Lp) - np.dot(Lm, Lm))
 
 
-def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-4, h_met=1e-6):
+def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-4, h_met=1e-6,
+              h_age=1e-6, age_rel=False):
     """FP64 central differences of the oracle's particle spectra against the GPU gradient, on up
     to n_check in-field particles at least 1e-4 away from SSP nodes. h_vlos (km/s) and h_met
     (dex) are the velocity and metallicity steps: the oracle's bin mean is a difference of prefix
@@ -221,8 +246,10 @@ def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-
         if checked >= n_check:
             break
         m, a, z, v = float(p.mass[i]), float(p.age[i]), float(p.met[i]), float(vlos[i])
+        ha = h_age * a if age_rel else h_age       # (a step relative to the age: log10 age)
         # one linear piece on both sides of the step: away from SSP nodes and clamps
-        if np.min(np.abs(la - math.log10(a))) < 1e-4 or np.min(np.abs(mz - z)) < 1e-4:
+        if (np.min(np.abs(la - math.log10(a))) < max(1e-4, 2 * ha / (a * math.log(10)))
+                or np.min(np.abs(mz - z)) < max(1e-4, 2 * h_met)):
             continue
         if any(abs(gpu[k][i]) < 1e-2 * maxg[k] for k in GRAD_KEYS):
             continue
@@ -238,7 +265,7 @@ def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-
 
         base = spec()
         for k, h, mk in (("mass", 1e-6 * m, lambda d: spec("mass", m + d)),
-                         ("age", 1e-6, lambda d: spec("age", a + d)),
+                         ("age", ha, lambda d: spec("age", a + d)),
                          ("met", h_met, lambda d: spec("met", z + d)),
                          ("vlos", h_vlos, lambda d: spec(vv=v + d))):
             dl = _fd_delta_L(cfg, G, int(key[i]), mk(h) - base, mk(-h) - base, quadratic)
