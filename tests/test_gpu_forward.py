@@ -106,32 +106,46 @@ def test_medium_full_size_matches_oracle():
     assert_cube_close(g["cube"], fo["cube"], what="medium cube")
 
 
-def test_large_full_size_sampled_spaxels():
-    """The 1e7-particle workload (150x150x4563): keys/perm/seg_off in full, bit-exact; cube rows
-    of sampled spaxels (the two heaviest, two split into exactly 2 work chunks, 40 random) from
-    the oracle one spaxel at a time."""
-    w = synth.large_workload()
-    log("large: GPU forward")
+def _full_size_sampled(w, tag, n_heavy, n_rand):
+    """Keys/perm/seg_off in full, bit-exact; cube rows of sampled spaxels (the heaviest, two split
+    into exactly 2 work chunks, random ones) from the oracle one spaxel at a time, within 1e-5 of
+    the sampled rows' maximum; empty spaxels zero and the cube non-negative everywhere."""
+    log(f"{tag}: GPU forward")
     _, g = gpu_forward(w)
     cfg = O.config_from_workload(w)
-    log("large: oracle rotate/bin")
+    log(f"{tag}: oracle rotate/bin")
     fo = O.forward(w.particles, cfg, with_cube=False)
     _check_rotate_bin(w, g, fo)
     cnt = np.diff(fo["seg_off"])
     order = np.argsort(-cnt, kind="stable")
     two = np.flatnonzero((cnt > 2048) & (cnt <= 4096))[:2]
     rng = np.random.default_rng(3)
-    rand = rng.choice(np.flatnonzero(cnt > 0), 40, replace=False)
-    spx = list(dict.fromkeys([int(s) for s in np.r_[order[:2], two, rand]]))
-    log(f"large: oracle rows for {len(spx)} spaxels (max count {cnt[spx].max()})")
+    rand = rng.choice(np.flatnonzero(cnt > 0), n_rand, replace=False)
+    spx = list(dict.fromkeys([int(s) for s in np.r_[order[:n_heavy], two, rand]]))
+    log(f"{tag}: oracle rows for {len(spx)} spaxels (max count {cnt[spx].max()})")
     ref = oracle_rows_parallel(w.particles, cfg, fo, spx)
     got = g["cube_raw"][spx]
     err = np.abs(got - ref).max(axis=1) / np.abs(ref).max()
-    log(f"large: worst sampled row error {err.max():.3e} (global scale = sampled max)")
+    log(f"{tag}: worst sampled row error {err.max():.3e} (global scale = sampled max)")
     assert err.max() <= 1e-5
     # properties at full size: empty spaxels are zero, cube is non-negative (templates > 0)
     assert np.all(g["cube_raw"][cnt == 0] == 0)
     assert g["cube_raw"].min() >= 0
+
+
+def test_large_full_size_sampled_spaxels():
+    """The 1e7-particle workload (150x150x4563) at bin-centre sampling on linear grids."""
+    _full_size_sampled(synth.large_workload(), "large", 2, 40)
+
+
+@pytest.mark.parametrize("variant", ["binmean", "loglam", "binmeanlog"])
+def test_large_full_size_sampled_spaxels_variants(variant):
+    """The same 1e7-particle galaxy as timed by the bench's other variants: bin-mean resampling
+    on linear grids, bin centres on grids uniform in ln(lambda), and bin means on those."""
+    w = synth.large_log_workload() if variant in ("loglam", "binmeanlog") else synth.large_workload()
+    if variant.startswith("binmean"):
+        w.resample = 1
+    _full_size_sampled(w, f"large {variant}", 1, 24)
 
 
 def test_deterministic_and_linear_in_mass():
