@@ -199,7 +199,7 @@ def main():
                     help="executors to compare (the first one decides when the sweep stops)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the lambda-sharded "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the lambda-sharded "
               "design is documented, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
