@@ -89,6 +89,40 @@ def test_graph_replays_with_device_work_between(ssp_grid, dssp, mode):
         log(f"{mode} replay {rep} matches the eager result")
 
 
+@pytest.mark.parametrize("mode", ["native", "persistent"])
+def test_batch_mixing_bin_centre_and_bin_mean_requests(ssp_grid, dssp, mode):
+    """A batch whose jobs alternate between bin-centre sampling and bin means: the packed tables
+    launch both cube kernels, each skipping the other kind's jobs; every cube equals the plain
+    entry points' bitwise, in the mix and alone."""
+    ws = _workloads(ssp_grid, range(20, 24), n_max=1e5)
+    for k, w in enumerate(ws):
+        w.resample = k % 2
+        log(f"request {w.name}: n={w.particles.n} grid {w.nx}x{w.ny} n_tel={w.n_tel} "
+            f"resample={w.resample}")
+    reqs = _requests(ws)
+    plain = _plain_cubes(dssp, reqs)
+    ex = GraphExecutor(dssp, max_jobs=4, lanes=1, mode=mode, grid_blocks=1024)
+    mix = _graph_batch(ex, reqs)
+    alone = [_graph_batch(ex, [r])[0] for r in reqs]
+    for k in range(len(reqs)):
+        assert plain[k].abs().max() > 0
+        assert torch.equal(mix[k], plain[k]), k
+        assert torch.equal(alone[k], plain[k]), k
+
+
+def test_served_bin_mean_request_matches_oracle(ssp_grid, dssp):
+    w = synth.serving_request(5, ssp_grid, n_max=3e4, n_min=1e4)
+    w.resample = 1
+    req = Request.from_particles(w.particles, ops.Observation.from_workload(w), rid=0)
+    ex = GraphExecutor(dssp, max_jobs=4, lanes=2)
+    s = Scheduler(ex, budget_bytes=8 << 30, max_slots=4)
+    fut = s.submit(req)
+    s.drain()
+    cube = fut.result(timeout=0).cube.cpu().numpy().reshape(w.nx * w.ny, w.n_tel)
+    fo = O.forward(w.particles, O.config_from_workload(w), workers=WORKERS)
+    assert_cube_close(cube, fo["cube"], what=f"served bin-mean cube ({w.particles.n} particles)")
+
+
 def test_served_request_matches_oracle(ssp_grid, dssp):
     w = synth.serving_request(3, ssp_grid, n_max=3e4, n_min=1e4)
     req = Request.from_particles(w.particles, ops.Observation.from_workload(w), rid=0)
