@@ -239,6 +239,16 @@ def _size_job(req: Request) -> RubixJob:
     return j
 
 
+def check_grid_kind(ssp: ops.DeviceSSP, req: Request) -> None:
+    """A request's telescope grid must be of the executor's SSP grid kind (linear in lambda or
+    uniform in ln lambda): the library refuses a launch that mixes them, which would fail the
+    whole batch."""
+    if bool(req.obs.log_lambda) != ssp.log_lambda:
+        kind = ("uniform in ln(lambda)", "linear in lambda")
+        raise ValueError(f"telescope grid {kind[not req.obs.log_lambda]} but SSP grid "
+                         f"{kind[not ssp.log_lambda]}")
+
+
 def _al(b: int) -> int:
     return (b + 511) // 512 * 512        # torch's allocator rounds blocks to 512 bytes
 
@@ -345,8 +355,14 @@ class GraphExecutor(_DeviceExecutorBase):
         z[FIELDS.index("age")] = 1.0
         gal = ops.DeviceGalaxy({f: z[k] for k, f in enumerate(FIELDS)})
         ssp = self.ssp
-        obs = ops.Observation((0.0, 0.0, 0.0), 2, 2, 1.0, ssp.lam_start + 10 * ssp.lam_step,
-                              ssp.lam_step, 64, psf_sigma_spx=0.5, lsf_sigma_A=ssp.lam_step)
+        # a telescope grid of the SSP grid's kind (the library refuses mixed kinds), 64 bins from
+        # the SSP grid's 10th node, LSF about one bin wide
+        if ssp.log_lambda:
+            t0, lsf = ssp.lam_start * math.exp(10 * ssp.lam_step), ssp.lam_start * ssp.lam_step
+        else:
+            t0, lsf = ssp.lam_start + 10 * ssp.lam_step, ssp.lam_step
+        obs = ops.Observation((0.0, 0.0, 0.0), 2, 2, 1.0, t0, ssp.lam_step, 64, psf_sigma_spx=0.5,
+                              lsf_sigma_A=lsf, log_lambda=ssp.log_lambda)
         buf = ops.JobBuffers.allocate(n, obs, self.device)
         job = ops.make_job(gal, obs, buf)
         nt = ops.rubix_table_bytes(1)
@@ -359,6 +375,7 @@ class GraphExecutor(_DeviceExecutorBase):
         torch.cuda.synchronize(self.device)
 
     def check(self, req: Request) -> None:
+        check_grid_kind(self.ssp, req)
         if psf_radius(req.obs) > self.max_psf_radius:
             raise ValueError(f"PSF radius {psf_radius(req.obs)} > {self.max_psf_radius}")
         if sort_passes(req.obs) > self.max_sort_passes:
@@ -404,7 +421,7 @@ class PlainExecutor(_DeviceExecutorBase):
     lanes = 1
 
     def check(self, req: Request) -> None:
-        return None
+        check_grid_kind(self.ssp, req)
 
     def launch(self, reqs: Sequence[Request]):
         if len(reqs) != 1:

@@ -10,8 +10,8 @@ from helpers import WORKERS, assert_cube_close, log
 
 import oracle as O
 from paper_2412_08265_amd import ops, synth
-from paper_2412_08265_amd.serve import (GraphExecutor, PlainExecutor, Request, Scheduler,
-                                        replay_trace)
+from paper_2412_08265_amd.serve import (GraphExecutor, PlainExecutor, Rejected, Request,
+                                        Scheduler, replay_trace)
 
 pytestmark = pytest.mark.gpu
 
@@ -108,6 +108,42 @@ def test_batch_mixing_bin_centre_and_bin_mean_requests(ssp_grid, dssp, mode):
         assert plain[k].abs().max() > 0
         assert torch.equal(mix[k], plain[k]), k
         assert torch.equal(alone[k], plain[k]), k
+
+
+@pytest.mark.parametrize("mode", ["native", "persistent"])
+def test_batch_on_log_lambda_grids(mode):
+    """An executor on an SSP grid uniform in ln(lambda): requests of different sizes, orientations
+    and telescope grids (bins of 0.8 to 2.1 SSP steps), alternating bin centres and bin means;
+    every cube equals the plain entry points' bitwise, in the mix and alone."""
+    ssp = synth.cached_ssp(40, 8, 3600.0, 1.2e-4, 3000, log_lambda=True)
+    dssp_log = ops.DeviceSSP.from_grid(ssp)
+    ws = []
+    for k, (n, ratio, n_tel, incl) in enumerate([(3000, 1.0, 2900, 30.0), (20000, 1.3, 2000, 60.0),
+                                                 (50000, 0.8, 3300, 75.0), (8000, 2.1, 1200, 10.0)]):
+        side = 24 + 4 * k
+        w = synth.Workload(f"log{k}", synth.make_galaxy(n, 600 + k), (incl, 0.0, 0.0), side, side,
+                           30.0 / side, 3600.0 * np.exp((0.37 + 5 * k) * 1.2e-4), 1.2e-4 * ratio,
+                           n_tel, ssp, psf_sigma_spx=1.0, lsf_sigma_A=1.2, z_sys=0.002,
+                           log_lambda=True)
+        w.resample = k % 2
+        log(f"request {w.name}: n={n} grid {side}x{side} n_tel={n_tel} ratio={ratio} "
+            f"resample={w.resample}")
+        ws.append(w)
+    reqs = _requests(ws)
+    plain = _plain_cubes(dssp_log, reqs)
+    ex = GraphExecutor(dssp_log, max_jobs=4, lanes=1, mode=mode, grid_blocks=1024)
+    mix = _graph_batch(ex, reqs[::-1])[::-1]
+    alone = [_graph_batch(ex, [r])[0] for r in reqs]
+    for k in range(len(reqs)):
+        assert plain[k].abs().max() > 0
+        assert torch.equal(mix[k], plain[k]), k
+        assert torch.equal(alone[k], plain[k]), k
+    # a request on a linear telescope grid is rejected at submission, before any launch
+    lin = synth.serving_request(0, n_max=2e3, n_min=1e3)
+    s = Scheduler(ex, budget_bytes=1 << 30, max_slots=2)
+    fut = s.submit(Request.from_particles(lin.particles, ops.Observation.from_workload(lin), rid=9))
+    with pytest.raises(Rejected, match="linear in lambda but SSP grid uniform in ln"):
+        fut.result(timeout=0)
 
 
 def test_served_bin_mean_request_matches_oracle(ssp_grid, dssp):
