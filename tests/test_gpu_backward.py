@@ -410,3 +410,34 @@ def test_bin_mean_adjoint_on_the_differentiation_workload():
         assert err <= 1e-4, (k, err)
     _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=32, seed=3, quadratic=False,
               h_vlos=1e-2, h_met=5e-5)
+
+
+@pytest.mark.parametrize("resample", [0, 1])
+def test_adjoint_on_the_full_size_log_lambda_galaxy(resample):
+    """The adjoint that the bench times on grids uniform in ln(lambda), at full size (1e7
+    particles, 150x150x4563, bin centres and bin means) with a seeded dL/dC_raw: GPU gradients vs
+    the oracle's on 4000 sampled particles (max-norm per parameter), and particles outside the
+    field get zero."""
+    import dataclasses
+    w = dataclasses.replace(synth.large_log_workload(), resample=resample)
+    cfg = O.config_from_workload(w)
+    tag = f"log 1e7 resample={resample}"
+    log(f"{tag}: oracle keys and velocities ({WORKERS} workers)")
+    fo = O.forward(w.particles, cfg, workers=WORKERS, with_cube=False)
+    rng = np.random.default_rng(23)
+    G = rng.standard_normal(size=(w.nx * w.ny, w.n_tel), dtype=np.float32)
+    log(f"{tag}: GPU forward + backward")
+    _, g = _gpu_grads(w, G)
+    sub = rng.choice(w.particles.n, 4000, replace=False)
+    log(f"{tag}: oracle adjoint on 4000 sampled particles")
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, idx=sub)
+    for k in GRAD_KEYS:
+        a = np.asarray(g[k][sub], dtype=np.float64)
+        b = np.asarray(ref[k], dtype=np.float64)
+        err = np.abs(a - b).max() / np.abs(b).max()
+        log(f"{tag} d{k}: max-norm rel err {err:.3e}")
+        assert err <= 1e-4, (k, err)
+    out = np.asarray(fo["key"]) >= w.nx * w.ny
+    assert out.any()
+    for k in GRAD_KEYS:
+        assert np.all(g[k][out] == 0), k
