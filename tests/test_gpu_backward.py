@@ -412,16 +412,17 @@ def test_bin_mean_adjoint_on_the_differentiation_workload():
               h_vlos=1e-2, h_met=5e-5)
 
 
-@pytest.mark.parametrize("resample", [0, 1])
-def test_adjoint_on_the_full_size_log_lambda_galaxy(resample):
-    """The adjoint that the bench times on grids uniform in ln(lambda), at full size (1e7
-    particles, 150x150x4563, bin centres and bin means) with a seeded dL/dC_raw: GPU gradients vs
-    the oracle's on 4000 sampled particles (max-norm per parameter), and particles outside the
-    field get zero."""
+@pytest.mark.parametrize("grids,resample", [("log", 0), ("log", 1), ("linear", 0), ("linear", 1)])
+def test_adjoint_on_the_full_size_galaxy(grids, resample):
+    """The adjoint that the bench times, at full size (1e7 particles, 150x150x4563, grids linear
+    in lambda or uniform in ln(lambda), bin centres and bin means) with a seeded dL/dC_raw: GPU
+    gradients vs the oracle's on 4000 sampled particles (max-norm per parameter), and particles
+    outside the field get zero."""
     import dataclasses
-    w = dataclasses.replace(synth.large_log_workload(), resample=resample)
+    base = synth.large_log_workload() if grids == "log" else synth.large_workload()
+    w = dataclasses.replace(base, resample=resample)
     cfg = O.config_from_workload(w)
-    tag = f"log 1e7 resample={resample}"
+    tag = f"{grids} 1e7 resample={resample}"
     log(f"{tag}: oracle keys and velocities ({WORKERS} workers)")
     fo = O.forward(w.particles, cfg, workers=WORKERS, with_cube=False)
     rng = np.random.default_rng(23)
