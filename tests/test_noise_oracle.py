@@ -1,9 +1,30 @@
-"""Pins of the noise oracle: the counter-based generator's outputs are uniform, independent and
-a bijection of the counter; the Gaussian deviates and the noise model have the stated moments."""
+"""Pins of the noise oracle: the counter-based generator reproduces its published known-answer
+vectors, and its outputs are uniform, independent and a bijection of the counter; the Gaussian
+deviates and the noise model have the stated moments."""
+import os
+
 import numpy as np
 import scipy.stats
 
 from oracle import noise as N
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_philox_reproduces_published_known_answer_vectors():
+    """Philox-4x32-10 against the known-answer vectors published with the generator (Salmon et
+    al., SC 2011; tests/golden/philox4x32_10_kat.txt): a wrong multiplier, Weyl constant, round
+    count or word order changes every output word."""
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(x, 16) for x in line.split()])
+    assert len(rows) == 3
+    for v in rows:
+        ctr = [np.array([c], dtype=np.uint64) for c in v[:4]]
+        out = N.philox4x32_10(ctr, (v[4], v[5]))
+        assert [int(o[0]) for o in out] == v[6:], [hex(int(o[0])) for o in out]
 
 
 def test_philox_outputs_are_uniform_and_a_bijection_of_the_counter():
