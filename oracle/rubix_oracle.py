@@ -37,7 +37,8 @@ C_KMS = 299792.458  # km/s
 __all__ = [
     "C_KMS", "rotation_matrix", "rotation_matrix_derivs", "rotate_positions", "los_velocity",
     "spaxel_keys", "sort_by_key", "ssp_cell", "ssp_weights", "interp_templates",
-    "rest_index", "doppler_index", "doppler_index_dbeta", "node_decision", "resample_linear",
+    "rest_index", "doppler_index", "doppler_index_dbeta", "node_cell", "node_ties",
+    "one_sided_cells", "cell_linear", "resample_linear", "particle_spectra_bounds",
     "integral_linear", "linear_at", "bin_edge_indices", "bin_edge_indices_log",
     "integral_log_weighted", "particle_spectra", "cube_raw", "gaussian_weights",
     "convolve_axis", "psf_lsf", "forward", "loss", "loss_grad_cube", "adjoint",
@@ -283,54 +284,57 @@ def doppler_index_dbeta(cfg: OracleConfig, vlos: np.ndarray) -> np.ndarray:
                                          * cfg.ssp_lam_step)
 
 
-def node_decision(cfg: OracleConfig, vlos: np.ndarray, n_nodes: int):
-    """Integer SSP node index k_ij = floor(q_ij) and the in-range mask, decided in FP32 the way
-    the GPU kernels decide them, so that both sides put every bin in the same node interval.
-
-    The fraction inside the interval stays FP64 (q - k); only the integer decision is shared.
-    The split form: q = Qi_j + t with Q_j = rest_index (FP64), Qi_j = floor(Q_j),
-    t = fl32(fl32(Q_j - Qi_j) - L_j * g) rounded once (a fused multiply-add), where, with
-    beta = fl32(v_los)/c,
-      linear grids: L_j = fl32(lam_j), g = fl32(beta/(1+beta) / ((1+z) dlam));
-      log grids:    L_j = 1,           g = fl32(ln(1+beta) / dln).
-    In range iff k >= 0 and (k < n-1, or k = n-1 with t's fraction exactly 0)."""
-    Q = rest_index(cfg)
-    Qi = np.floor(Q)
-    Qf = (Q - Qi).astype(np.float32).astype(np.float64)
-    beta = np.asarray(vlos, dtype=np.float32).astype(np.float64) / C_KMS
-    if cfg.log_lambda:
-        L = np.ones(cfg.n_tel)
-        g32 = (np.log1p(beta) / cfg.ssp_lam_step).astype(np.float32).astype(np.float64)
-    else:
-        L = cfg.tel_lambda().astype(np.float32).astype(np.float64)
-        g32 = (beta / (1.0 + beta) / ((1.0 + cfg.z_sys) * cfg.ssp_lam_step)
-               ).astype(np.float32).astype(np.float64)
-    # the product of two FP32 values is exact in FP64 and so is the difference here: rounding it
-    # once to FP32 reproduces a fused multiply-add
-    t = (Qf[None, :] - L[None, :] * g32[:, None]).astype(np.float32)
-    fl = np.floor(t)
-    frac = t - fl
-    k = Qi[None, :].astype(np.int64) + fl.astype(np.int64)
-    valid = (k >= 0) & ((k < n_nodes - 1) | ((k == n_nodes - 1) & (frac == 0)))
+def node_cell(q: np.ndarray, n_nodes: int):
+    """The node interval [k, k+1] holding q and whether q lies on the SSP grid, in FP64:
+    valid iff 0 <= q <= n-1, k = floor(q) with the last node mapped to (k = n-2, tau = 1)."""
+    valid = (q >= 0.0) & (q <= n_nodes - 1)
+    k = np.minimum(np.floor(np.where(valid, q, 0.0)), n_nodes - 2).astype(np.int64)
     return k, valid
 
 
-def resample_linear(S: np.ndarray, q: np.ndarray, k: Optional[np.ndarray] = None,
-                    valid: Optional[np.ndarray] = None) -> np.ndarray:
-    """Piecewise-linear interpolation of row i of S at fractional node positions q[i, :];
-    zero where q < 0 or q > n-1. The last node maps to (k = n-2, tau = 1).
+def node_ties(q: np.ndarray, d: np.ndarray, n_nodes: int, ties):
+    """Pairs whose node interval is decided by rounding, for a method that computes q with an
+    absolute error of at most eps = eps_abs + eps_rel |d| (`ties` = (eps_abs, eps_rel); d is the
+    Doppler part of q, its change from the particle at rest). Such a method may put a q within eps
+    of a node r in [0, n-1] on either side of r: in the interval left of r (r-1, which is off the
+    grid for r = 0) or right of it (r, off the grid for r = n-1). Returns the mask and r.
 
-    k / valid: optional integer interval and range decision (see node_decision); by default
-    k = floor(q) and valid = 0 <= q <= n-1 in FP64."""
-    n = S.shape[1]
-    if k is None:
-        valid = (q >= 0.0) & (q <= n - 1)
-        k = np.floor(np.where(valid, q, 0.0)).astype(np.int64)
-    k = np.where(valid, np.minimum(k, n - 2), 0)
-    tau = np.where(valid, q - k, 0.0)
-    s0 = np.take_along_axis(S, k, axis=1)
-    s1 = np.take_along_axis(S, k + 1, axis=1)
+    At an interior node the interpolated value is continuous, so only its slope (the adjoint)
+    depends on the side; at the two ends of the SSP range the value itself does (in the band or
+    zero). Every one-sided result is a correct result there (several correct results)."""
+    eps_abs, eps_rel = ties
+    r = np.rint(np.where(np.isfinite(q), q, -2.0))
+    eps = eps_abs + eps_rel * np.abs(np.where(np.isfinite(d), d, 0.0))
+    tie = (np.abs(q - r) <= eps) & (r >= 0) & (r <= n_nodes - 1)
+    return tie, r.astype(np.int64)
+
+
+def one_sided_cells(q: np.ndarray, d: np.ndarray, n_nodes: int, ties):
+    """The FP64 cell (node_cell) and, for the pairs tied at a node r (node_ties), the cell left of
+    r (r-1) and the cell right of r (r), each on the grid iff it lies in [0, n-2]; untied pairs
+    keep the FP64 cell on both sides. Returns (k, valid), (k_left, valid_left),
+    (k_right, valid_right) and the tie mask. The FP64 cell of a tied pair is one of the two."""
+    k, valid = node_cell(q, n_nodes)
+    tie, r = node_ties(q, d, n_nodes, ties)
+    left = (np.where(tie, r - 1, k), np.where(tie, r >= 1, valid))
+    right = (np.where(tie, r, k), np.where(tie, r <= n_nodes - 2, valid))
+    return (k, valid), left, right, tie
+
+
+def cell_linear(S: np.ndarray, q: np.ndarray, k: np.ndarray, valid: np.ndarray) -> np.ndarray:
+    """The linear function of node interval [k, k+1] of row i of S evaluated at q (tau = q - k),
+    zero where the interval is off the grid (valid false)."""
+    kk = np.where(valid, k, 0)
+    tau = np.where(valid, q - kk, 0.0)
+    s0 = np.take_along_axis(S, kk, axis=1)
+    s1 = np.take_along_axis(S, kk + 1, axis=1)
     return np.where(valid, (1.0 - tau) * s0 + tau * s1, 0.0)
+
+
+def resample_linear(S: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Piecewise-linear interpolation of row i of S at fractional node positions q[i, :];
+    zero where q < 0 or q > n-1. The last node maps to (k = n-2, tau = 1)."""
+    return cell_linear(S, q, *node_cell(q, S.shape[1]))
 
 
 def integral_linear(S: np.ndarray, q_lo: np.ndarray, q_hi: np.ndarray) -> np.ndarray:
@@ -441,38 +445,82 @@ def particle_spectra(p, idx: np.ndarray, vlos: np.ndarray, cfg: OracleConfig) ->
         scale = cfg.flux_scale * mass * (cfg.ssp_lam_step / cfg.tel_step)
         return scale[:, None] * integral_linear(S, q_lo, q_hi)
     q = doppler_index(cfg, v)
-    k, valid = node_decision(cfg, v, S.shape[1])
     J = 1.0 / ((1.0 + cfg.z_sys) * (1.0 + v / C_KMS))
-    return (cfg.flux_scale * mass * J)[:, None] * resample_linear(S, q, k, valid)
+    return (cfg.flux_scale * mass * J)[:, None] * resample_linear(S, q)
+
+
+def particle_spectra_bounds(p, idx: np.ndarray, vlos: np.ndarray, cfg: OracleConfig, ties):
+    """particle_spectra together with the range of its correct results where the node interval
+    is decided by rounding (node_ties with `ties` = (eps_abs, eps_rel)): returns f, lo, hi and the
+    number of tied (particle, bin) pairs, lo/hi the smaller/larger of the two one-sided values
+    (equal to f elsewhere). Only bin-centre sampling has such pairs that matter: the bin mean is an
+    integral, continuous in its edges' positions, so there lo = hi = f."""
+    f = particle_spectra(p, idx, vlos, cfg)
+    if cfg.resample == 1:
+        return f, f, f, 0
+    v = vlos[idx]
+    q = doppler_index(cfg, v)
+    n = cfg.ssp_flux.shape[2]
+    tie, r = node_ties(q, q - rest_index(cfg)[None, :], n, ties)
+    ti, tj = np.nonzero(tie)
+    if ti.size == 0:
+        return f, f, f, 0
+    # the one-sided values at the tied pairs only (the cells left and right of node r)
+    sub = np.asarray(idx)[ti]
+    age, met = _p64(p, "age")[sub], _p64(p, "met")[sub]
+    ja, jz, _, _, w, _, _ = ssp_weights(age, met, cfg.log_age_nodes, cfg.met_nodes)
+    S = interp_templates(cfg.ssp_flux, ja, jz, w)          # one row per tied pair
+    qt, rt = q[ti, tj][:, None], r[ti, tj][:, None]
+    J = 1.0 / ((1.0 + cfg.z_sys) * (1.0 + v[ti] / C_KMS))
+    scale = cfg.flux_scale * _p64(p, "mass")[sub] * J
+    fl = scale * cell_linear(S, qt, rt - 1, rt >= 1)[:, 0]
+    fr = scale * cell_linear(S, qt, rt, rt <= n - 2)[:, 0]
+    lo, hi = f.copy(), f.copy()
+    lo[ti, tj] = np.minimum(fl, fr)
+    hi[ti, tj] = np.maximum(fl, fr)
+    return f, lo, hi, int(ti.size)
 
 
 # --------------------------------------------------------------------------------------------------
 # step 6: spaxel sum (Sec. 3, "the stellar spectra in each spaxel are summed up")
 # --------------------------------------------------------------------------------------------------
 def _cube_rows(args):
-    s_lo, s_hi, chunk = args
+    s_lo, s_hi, chunk, ties = args
     st = _POOL_STATE
     p, key, perm, seg_off, vlos, cfg = (st["p"], st["key"], st["perm"], st["seg_off"],
                                         st["vlos"], st["cfg"])
     out = np.zeros((s_hi - s_lo, cfg.n_tel))
+    lo_out = np.zeros_like(out) if ties is not None else None
+    hi_out = np.zeros_like(out) if ties is not None else None
+    n_tied = 0
     i0, i1 = int(seg_off[s_lo]), int(seg_off[s_hi])
     for c0 in range(i0, i1, chunk):
         idx = perm[c0:min(i1, c0 + chunk)]
-        f = particle_spectra(p, idx, vlos, cfg)
         k = key[idx] - s_lo
         starts = np.flatnonzero(np.r_[True, k[1:] != k[:-1]])
+        if ties is None:
+            f = particle_spectra(p, idx, vlos, cfg)
+        else:
+            f, lo, hi, nt = particle_spectra_bounds(p, idx, vlos, cfg, ties)
+            n_tied += nt
+            lo_out[k[starts]] += np.add.reduceat(lo, starts, axis=0)
+            hi_out[k[starts]] += np.add.reduceat(hi, starts, axis=0)
         out[k[starts]] += np.add.reduceat(f, starts, axis=0)
-    return s_lo, out
+    return s_lo, out, lo_out, hi_out, n_tied
 
 
 _POOL_STATE: Dict = {}
 
 
 def cube_raw(p, key, perm, seg_off, vlos, cfg: OracleConfig, workers: Optional[int] = None,
-             chunk: int = 1024) -> np.ndarray:
+             chunk: int = 1024, ties=None):
     """C_raw[s, j] = sum over particles with key s of f_i(lam_j), FP64, shape [ny*nx, n_tel].
 
-    Works over spaxel ranges; with workers > 1 the ranges run in forked processes."""
+    Works over spaxel ranges; with workers > 1 the ranges run in forked processes.
+    With `ties` = (eps_abs, eps_rel) it returns (C_raw, C_lo, C_hi, n_tied) instead: C_lo / C_hi
+    sum every particle's smaller / larger one-sided value at the pairs whose node interval is
+    decided by rounding (particle_spectra_bounds), so any choice of sides per pair lies between
+    them."""
     n_s = cfg.n_spaxels
     n_in = int(seg_off[n_s])
     workers = workers if workers is not None else int(os.environ.get("ORACLE_WORKERS", "1"))
@@ -482,20 +530,34 @@ def cube_raw(p, key, perm, seg_off, vlos, cfg: OracleConfig, workers: Optional[i
     bounds = np.searchsorted(seg_off, np.linspace(0, n_in, n_ranges + 1), side="left")
     bounds[0], bounds[-1] = 0, n_s
     bounds = np.unique(np.clip(bounds, 0, n_s))
-    tasks = [(int(a), int(b), chunk) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    tasks = [(int(a), int(b), chunk, ties) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
     out = np.zeros((n_s, cfg.n_tel))
+    lo = np.zeros_like(out) if ties is not None else None
+    hi = np.zeros_like(out) if ties is not None else None
+    n_tied = 0
+
+    def put(res):
+        nonlocal n_tied
+        s_lo, rows, rlo, rhi, nt = res
+        out[s_lo:s_lo + rows.shape[0]] = rows
+        if ties is not None:
+            lo[s_lo:s_lo + rows.shape[0]] = rlo
+            hi[s_lo:s_lo + rows.shape[0]] = rhi
+            n_tied += nt
+
     if workers > 1 and len(tasks) > 1:
         import multiprocessing as mp
         ctx = mp.get_context("fork")
         with ctx.Pool(workers) as pool:
-            for s_lo, rows in pool.imap_unordered(_cube_rows, tasks):
-                out[s_lo:s_lo + rows.shape[0]] = rows
+            for res in pool.imap_unordered(_cube_rows, tasks):
+                put(res)
     else:
         for t in tasks:
-            s_lo, rows = _cube_rows(t)
-            out[s_lo:s_lo + rows.shape[0]] = rows
+            put(_cube_rows(t))
     _POOL_STATE.clear()
-    return out
+    if ties is None:
+        return out
+    return out, lo, hi, n_tied
 
 
 # --------------------------------------------------------------------------------------------------
@@ -541,10 +603,13 @@ def psf_lsf(c_raw: np.ndarray, cfg: OracleConfig) -> np.ndarray:
 # whole forward pass
 # --------------------------------------------------------------------------------------------------
 def forward(p, cfg: OracleConfig, workers: Optional[int] = None, frozen_key=None,
-            with_cube=True) -> Dict[str, np.ndarray]:
+            with_cube=True, ties=None) -> Dict[str, np.ndarray]:
     """Run steps 1-7. Returns key, perm, seg_off, vlos (FP64), cube_raw and cube (FP64).
 
-    `frozen_key` replaces the binning result (used when differentiating w.r.t. angles)."""
+    `frozen_key` replaces the binning result (used when differentiating w.r.t. angles).
+    With `ties` = (eps_abs, eps_rel) (node_ties) it also returns the range of correct cubes:
+    cube_raw_lo / cube_raw_hi (cube_raw's bounds) and cube_lo / cube_hi (their PSF/LSF images,
+    which bound the cube since the Gaussian weights are positive), and n_ties."""
     R = rotation_matrix(*cfg.angles_rad)
     xp, yp, _ = rotate_positions(p, R)
     vlos = los_velocity(p, R)
@@ -553,7 +618,12 @@ def forward(p, cfg: OracleConfig, workers: Optional[int] = None, frozen_key=None
     perm, seg_off = sort_by_key(key, cfg.n_spaxels)
     out = dict(R=R, key=key, perm=perm, seg_off=seg_off, vlos=vlos)
     if with_cube:
-        c = cube_raw(p, key, perm, seg_off, vlos, cfg, workers=workers)
+        if ties is None:
+            c = cube_raw(p, key, perm, seg_off, vlos, cfg, workers=workers)
+        else:
+            c, lo, hi, nt = cube_raw(p, key, perm, seg_off, vlos, cfg, workers=workers, ties=ties)
+            out.update(cube_raw_lo=lo, cube_raw_hi=hi, cube_lo=psf_lsf(lo, cfg),
+                       cube_hi=psf_lsf(hi, cfg), n_ties=nt)
         out["cube_raw"] = c
         out["cube"] = psf_lsf(c, cfg)
     return out
@@ -575,22 +645,30 @@ def loss_grad_cube(cube: np.ndarray, target: np.ndarray, cfg: OracleConfig) -> n
 
 def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
             idx: Optional[np.ndarray] = None, chunk: int = 512,
-            workers: int = 1) -> Dict[str, np.ndarray]:
+            workers: int = 1, ties=None) -> Dict[str, np.ndarray]:
     """Analytic gradients of L given G = dL/dC_raw, for particles `idx` (default: all). For the
     bin-mean resampling see _adjoint_bin_mean; the bin-centre form is below.
 
-    Per particle i in the field (spaxel s), with a_ic = flux_scale m_i J_i w_ic and
-    X_ic = sum_j G[s, j] Tlin_c(q_ij):
-      dL/dm_i      = flux_scale J_i sum_c w_ic X_ic
-      dL/dage_i    = flux_scale m_i J_i sum_c (dw_c/dt_a) X_ic / (du_a) / (age_i ln 10)
-      dL/dmet_i    = flux_scale m_i J_i sum_c (dw_c/dt_z) X_ic / (du_z)
+    Per particle i in the field (spaxel s), as sums over the telescope bins j of per-bin terms,
+    with the bilinear spectrum Slin_i = sum_c w_ic Tlin_c and its cell-direction derivatives
+    Sa_i = sum_c (dw_c/dt_a) Tlin_c, Sz_i = sum_c (dw_c/dt_z) Tlin_c (all at q_ij):
+      dL/dm_i      = flux_scale J_i sum_j G[s,j] Slin_i
+      dL/dage_i    = flux_scale m_i J_i sum_j G[s,j] Sa_i / (du_a) / (age_i ln 10)
+      dL/dmet_i    = flux_scale m_i J_i sum_j G[s,j] Sz_i / (du_z)
       dL/dvlos_i   = (1/c) sum_j G[s,j] flux_scale m_i [dJ/dbeta Slin_i(q_ij)
                                           + J_i Slin_i'(q_ij) dq_ij/dbeta]
-    with Slin' the slope of the linear interpolant on the right-hand cell (one-sided at nodes),
-    zero outside the SSP range, and clamped axes giving zero. Angles use frozen keys:
+    with Slin' the slope of the linear interpolant on the node interval holding q (node_cell: the
+    right-hand one at a node), zero outside the SSP range, and clamped axes giving zero. Angles use
+    frozen keys:
       dL/dphi_k = sum_i dL/dvlos_i (dR/dphi_k v_i)_z,   dL/dv_i = dL/dvlos_i R[2, :].
     Particles outside the field get zero. Positions get no gradient (binning is piecewise
-    constant)."""
+    constant).
+
+    With `ties` = (eps_abs, eps_rel) (node_ties) the result also holds, per quantity, `<name>_lo`
+    and `<name>_hi`: the range of correct gradients when each (particle, bin) pair whose node
+    interval is decided by rounding may take either side (a bin's terms from the left or the right
+    interval; for the bin mean, an edge at either end of the SSP range inside or outside it), and
+    n_ties, the number of such pairs (edges)."""
     if fw is None:
         fw = forward(p, cfg, with_cube=False)
     R, key, vlos = fw["R"], fw["key"], fw["vlos"]
@@ -598,22 +676,31 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
     if idx is None:
         idx = np.arange(n)
     idx = np.asarray(idx, dtype=np.int64)
+    names = ("mass", "age", "met", "vlos")
     if workers > 1 and idx.shape[0] > 4 * chunk:
         # the per-particle gradients are independent: evaluate index ranges in forked processes
         import multiprocessing as mp
         parts = np.array_split(idx, workers * 4)
-        _POOL_STATE.update(adj=(p, cfg, G, fw, chunk))
+        _POOL_STATE.update(adj=(p, cfg, G, fw, chunk, ties))
         with mp.get_context("fork").Pool(workers) as pool:
             res = pool.map(_adjoint_part, parts)
         _POOL_STATE.clear()
-        out = {k: np.concatenate([r[k] for r in res]) for k in ("mass", "age", "met", "vlos")}
+        keys = names if ties is None else names + tuple(f"{k}_{e}" for k in names
+                                                         for e in ("lo", "hi"))
+        out = {k: np.concatenate([r[k] for r in res]) for k in keys}
+        if ties is not None:
+            out["n_ties"] = sum(r["n_ties"] for r in res)
         return _adjoint_angles(p, cfg, R, idx, out)
     n_s = cfg.n_spaxels
-    out = {k: np.zeros(idx.shape[0]) for k in ("mass", "age", "met", "vlos")}
+    out = {k: np.zeros(idx.shape[0]) for k in names}
+    if ties is not None:
+        out.update({f"{k}_{e}": np.zeros(idx.shape[0]) for k in names for e in ("lo", "hi")})
+        out["n_ties"] = 0
     nl = cfg.ssp_flux.shape[2]
     T = cfg.ssp_flux
     la_nodes, mz_nodes = cfg.log_age_nodes, cfg.met_nodes
     inf = key[idx] < n_s
+    Q = rest_index(cfg)[None, :]
     for c0 in range(0, idx.shape[0], chunk):
         sel = np.arange(c0, min(idx.shape[0], c0 + chunk))
         sel = sel[inf[sel]]
@@ -626,40 +713,53 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
         ja, jz, ta, tz, w, ina, inz = ssp_weights(age, met, la_nodes, mz_nodes)
         if cfg.resample == 1:
             fn = _adjoint_bin_mean_log if cfg.log_lambda else _adjoint_bin_mean
-            fn(cfg, G, key[ii], age, mass, v, ja, jz, ta, tz, w, ina, inz, out, sel)
+            fn(cfg, G, key[ii], age, mass, v, ja, jz, ta, tz, w, ina, inz, out, sel, ties)
             continue
         q = doppler_index(cfg, v)
-        k, valid = node_decision(cfg, v, nl)
-        k = np.where(valid, np.minimum(k, nl - 2), 0)
-        tau = np.where(valid, q - k, 0.0)
         g = G[key[ii]]                                   # [m, n_tel]
         corners = [(ja, jz), (ja, jz + 1), (ja + 1, jz), (ja + 1, jz + 1)]
-        X = np.zeros((ii.shape[0], 4))
-        Sl = np.zeros_like(q)                            # Slin_i(q)
-        dS = np.zeros_like(q)                            # Slin_i'(q) per index unit
-        for c, (a_, z_) in enumerate(corners):
-            row = T[a_, z_]                               # [m, nl]
-            t0 = np.take_along_axis(row, k, axis=1)
-            t1 = np.take_along_axis(row, k + 1, axis=1)
-            tl = np.where(valid, (1.0 - tau) * t0 + tau * t1, 0.0)
-            X[:, c] = np.sum(g * tl, axis=1)
-            Sl += w[:, c:c + 1] * tl
-            dS += w[:, c:c + 1] * np.where(valid, t1 - t0, 0.0)
         fs = cfg.flux_scale
         J = 1.0 / ((1.0 + cfg.z_sys) * (1.0 + beta))
-        out["mass"][sel] = fs * J * np.sum(w * X, axis=1)
+        dJ = -J / (1.0 + beta)
+        dq = doppler_index_dbeta(cfg, v)
         dwa = np.stack([-(1 - tz), -tz, (1 - tz), tz], axis=-1)
         dwz = np.stack([-(1 - ta), (1 - ta), -ta, ta], axis=-1)
         du_a = la_nodes[ja + 1] - la_nodes[ja]
         du_z = mz_nodes[jz + 1] - mz_nodes[jz]
-        d_ua = fs * mass * J * np.sum(dwa * X, axis=1) / du_a
-        d_uz = fs * mass * J * np.sum(dwz * X, axis=1) / du_z
-        out["age"][sel] = np.where(ina, d_ua / (age * math.log(10.0)), 0.0)
-        out["met"][sel] = np.where(inz, d_uz, 0.0)
-        dJ = -J / (1.0 + beta)
-        dq = doppler_index_dbeta(cfg, v)
-        dbeta = fs * mass * np.sum(g * (dJ[:, None] * Sl + J[:, None] * dS * dq), axis=1)
-        out["vlos"][sel] = dbeta / C_KMS
+        c_age = np.where(ina, fs * mass * J / du_a / (age * math.log(10.0)), 0.0)[:, None]
+        c_met = np.where(inz, fs * mass * J / du_z, 0.0)[:, None]
+
+        def terms(k, valid):
+            # per-bin terms of the four gradients with node interval k (valid: on the grid)
+            Sl = np.zeros_like(q)
+            Sa = np.zeros_like(q)
+            Sz = np.zeros_like(q)
+            dS = np.zeros_like(q)                        # slope of Slin per node index
+            kk = np.where(valid, k, 0)
+            for c, (a_, z_) in enumerate(corners):
+                row = T[a_, z_]                           # [m, nl]
+                tl = cell_linear(row, q, k, valid)
+                Sl += w[:, c:c + 1] * tl
+                Sa += dwa[:, c:c + 1] * tl
+                Sz += dwz[:, c:c + 1] * tl
+                t0 = np.take_along_axis(row, kk, axis=1)
+                t1 = np.take_along_axis(row, kk + 1, axis=1)
+                dS += w[:, c:c + 1] * np.where(valid, t1 - t0, 0.0)
+            return (fs * J[:, None] * g * Sl, c_age * g * Sa, c_met * g * Sz,
+                    fs * mass[:, None] * g * (dJ[:, None] * Sl + J[:, None] * dS * dq) / C_KMS)
+
+        if ties is None:
+            base = terms(*node_cell(q, nl))
+            for name, t in zip(names, base):
+                out[name][sel] = np.sum(t, axis=1)
+            continue
+        cell, left, right, tie = one_sided_cells(q, q - Q, nl, ties)
+        base, tl_, tr_ = terms(*cell), terms(*left), terms(*right)
+        out["n_ties"] += int(tie.sum())
+        for name, t, a_, b_ in zip(names, base, tl_, tr_):
+            out[name][sel] = np.sum(t, axis=1)
+            out[f"{name}_lo"][sel] = np.sum(np.where(tie, np.minimum(a_, b_), t), axis=1)
+            out[f"{name}_hi"][sel] = np.sum(np.where(tie, np.maximum(a_, b_), t), axis=1)
     return _adjoint_angles(p, cfg, R, idx, out)
 
 
@@ -675,7 +775,8 @@ def linear_at(S: np.ndarray, q: np.ndarray) -> np.ndarray:
     return s0 + t * (s1 - s0)
 
 
-def _adjoint_bin_mean(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, inz, out, sel):
+def _adjoint_bin_mean(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, inz, out, sel,
+                      ties=None):
     """Gradients for the bin-mean resampling (reading 1), particles `sel` of the chunk.
 
     f_i(j) = B m_i sum_c w_ic I_c(j), B = flux_scale dlam_ssp/dlam, I_c(j) the integral of the
@@ -687,7 +788,9 @@ def _adjoint_bin_mean(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, inz, o
     bilinear spectrum's interpolant,
       dL/dbeta_i = B m_i sum_j G[s, j] (Slin_i(q_hi) dq_hi/dbeta - Slin_i(q_lo) dq_lo/dbeta),
     an edge outside (0, n-1) being clipped and contributing nothing, and
-    dq/dbeta = -lam_edge / ((1+z)(1+beta)^2 dlam_ssp) at the bin edge lam_edge = lam_j -/+ dlam/2."""
+    dq/dbeta = -lam_edge / ((1+z)(1+beta)^2 dlam_ssp) at the bin edge lam_edge = lam_j -/+ dlam/2.
+    The integrals are continuous in the edges' positions, so only the Leibniz term of an edge at
+    either end of the SSP range depends on rounding (edge_terms)."""
     T = cfg.ssp_flux
     nl = T.shape[2]
     la_nodes, mz_nodes = cfg.log_age_nodes, cfg.met_nodes
@@ -710,14 +813,43 @@ def _adjoint_bin_mean(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, inz, o
     beta = np.asarray(v, dtype=np.float64) / C_KMS
     lam = cfg.tel_lambda()[None, :]
     f2 = (1.0 + cfg.z_sys) * (1.0 + beta[:, None]) ** 2 * cfg.ssp_lam_step
-    term = np.zeros_like(q_lo)
-    for q, edge, sgn in ((q_hi, lam + 0.5 * cfg.tel_step, 1.0), (q_lo, lam - 0.5 * cfg.tel_step, -1.0)):
+    rest_lo, rest_hi = bin_edge_indices(cfg, np.zeros(1))
+    scale = (B * mass / C_KMS)[:, None] * g
+    edges = [(q_hi, q_hi - rest_hi, scale * linear_at(S, q_hi) * (-(lam + 0.5 * cfg.tel_step) / f2)),
+             (q_lo, q_lo - rest_lo, -scale * linear_at(S, q_lo) * (-(lam - 0.5 * cfg.tel_step) / f2))]
+    edge_terms(edges, nl, ties, out, sel)
+
+
+def edge_terms(edges, nl, ties, out, sel):
+    """The Leibniz terms of the bin-mean velocity gradient: per edge (q, d, y), y the edge's term
+    in every bin if the edge lies strictly inside (0, n-1) and 0 otherwise (a clipped edge does
+    not move the integral). With `ties` an edge within eps of either end of the range (node_ties'
+    eps, d the Doppler part of q) may count as inside or outside, and the bounds take both."""
+    total = 0.0
+    lo = hi = 0.0
+    n_tied = 0
+    for q, d, y in edges:
         inside = (q > 0.0) & (q < nl - 1.0)
-        term += sgn * np.where(inside, linear_at(S, q) * (-edge / f2), 0.0)
-    out["vlos"][sel] = B * mass * np.sum(g * term, axis=1) / C_KMS
+        t = np.where(inside, y, 0.0)
+        total = total + t
+        if ties is not None:
+            eps = ties[0] + ties[1] * np.abs(np.where(np.isfinite(d), d, 0.0))
+            tie = (np.abs(q) <= eps) | (np.abs(q - (nl - 1.0)) <= eps)
+            n_tied += int(tie.sum())
+            lo = lo + np.where(tie, np.minimum(y, 0.0), t)
+            hi = hi + np.where(tie, np.maximum(y, 0.0), t)
+    out["vlos"][sel] = np.sum(total, axis=1)
+    if ties is not None:
+        out["vlos_lo"][sel] = np.sum(lo, axis=1)
+        out["vlos_hi"][sel] = np.sum(hi, axis=1)
+        out["n_ties"] += n_tied
+        for k in ("mass", "age", "met"):
+            out[f"{k}_lo"][sel] = out[k][sel]
+            out[f"{k}_hi"][sel] = out[k][sel]
 
 
-def _adjoint_bin_mean_log(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, inz, out, sel):
+def _adjoint_bin_mean_log(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, inz, out, sel,
+                          ties=None):
     """Gradients for the bin-mean resampling on log grids, particles `sel` of the chunk.
 
     f_i(j) = fs m_i / dlam_j sum_c w_ic I_c(j), I_c(j) the integral over rest wavelength of
@@ -728,7 +860,7 @@ def _adjoint_bin_mean_log(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, in
     dq/dbeta = -1/((1+beta) dln_ssp) at both edges (Leibniz rule), so
       dL/dbeta_i = -fs m_i / (1+beta_i) sum_j G[s, j] / dlam_j
                    (Slin_i(q_hi) lam(q_hi) [q_hi inside] - Slin_i(q_lo) lam(q_lo) [q_lo inside]),
-    an edge outside (0, n-1) being clipped and contributing nothing."""
+    an edge outside (0, n-1) being clipped and contributing nothing (edge_terms)."""
     T = cfg.ssp_flux
     nl = T.shape[2]
     la_nodes, mz_nodes = cfg.log_age_nodes, cfg.met_nodes
@@ -751,25 +883,33 @@ def _adjoint_bin_mean_log(cfg, G, keys, age, mass, v, ja, jz, ta, tz, w, ina, in
     out["met"][sel] = np.where(inz, B * mass * np.sum(dwz * X, axis=1) / du_z, 0.0)
     S = interp_templates(T, ja, jz, w)
     beta = np.asarray(v, dtype=np.float64) / C_KMS
-    term = np.zeros_like(q_lo)
-    for q, sgn in ((q_hi, 1.0), (q_lo, -1.0)):
-        inside = (q > 0.0) & (q < nl - 1.0)
-        lam_r = cfg.ssp_lam_start * np.exp(q * cfg.ssp_lam_step)
-        term += sgn * np.where(inside, linear_at(S, q) * lam_r, 0.0)
-    out["vlos"][sel] = (-B * mass / (1.0 + beta)) * np.sum(g * term, axis=1) / C_KMS
+    rest_lo, rest_hi = bin_edge_indices_log(cfg, np.zeros(1))
+    scale = (-B * mass / (1.0 + beta) / C_KMS)[:, None] * g
+    edges = []
+    for q, rest, sgn in ((q_hi, rest_hi, 1.0), (q_lo, rest_lo, -1.0)):
+        lam_r = cfg.ssp_lam_start * np.exp(np.clip(q, 0.0, nl - 1.0) * cfg.ssp_lam_step)
+        edges.append((q, q - rest, sgn * scale * linear_at(S, q) * lam_r))
+    edge_terms(edges, nl, ties, out, sel)
 
 
 def _adjoint_part(part):
-    p, cfg, G, fw, chunk = _POOL_STATE["adj"]
-    return adjoint(p, cfg, G, fw, idx=part, chunk=chunk, workers=1)
+    p, cfg, G, fw, chunk, ties = _POOL_STATE["adj"]
+    return adjoint(p, cfg, G, fw, idx=part, chunk=chunk, workers=1, ties=ties)
 
 
 def _adjoint_angles(p, cfg, R, idx, out):
-    """dL/dphi_k = sum_i dL/dvlos_i (dR/dphi_k v_i)_z and dL/dv_i = dL/dvlos_i R[2, :]."""
+    """dL/dphi_k = sum_i dL/dvlos_i (dR/dphi_k v_i)_z and dL/dv_i = dL/dvlos_i R[2, :]; with
+    bounds on dL/dvlos_i (vlos_lo / vlos_hi) also the bounds of both that follow from them."""
     dR = rotation_matrix_derivs(*cfg.angles_rad)
     vx, vy, vz = _p64(p, "vx")[idx], _p64(p, "vy")[idx], _p64(p, "vz")[idx]
+    coef = [dR[k, 2, 0] * vx + dR[k, 2, 1] * vy + dR[k, 2, 2] * vz for k in range(3)]
     dv = out["vlos"]
-    out["angles"] = np.array([np.sum(dv * (dR[k, 2, 0] * vx + dR[k, 2, 1] * vy
-                                           + dR[k, 2, 2] * vz)) for k in range(3)])
+    out["angles"] = np.array([np.sum(dv * coef[k]) for k in range(3)])
     out["vel"] = dv[None, :] * R[2, :, None]
+    if "vlos_lo" in out:
+        lo, hi = out["vlos_lo"], out["vlos_hi"]
+        out["angles_lo"] = np.array([np.sum(np.minimum(lo * c, hi * c)) for c in coef])
+        out["angles_hi"] = np.array([np.sum(np.maximum(lo * c, hi * c)) for c in coef])
+        a, b = lo[None, :] * R[2, :, None], hi[None, :] * R[2, :, None]
+        out["vel_lo"], out["vel_hi"] = np.minimum(a, b), np.maximum(a, b)
     return out

@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 from paper_2412_08265_amd import synth
-from tests.helpers import WORKERS, log
+from tests.helpers import TIES, WORKERS, assert_grads_in, log, outside
 
 pytestmark = pytest.mark.gpu
 
@@ -29,18 +29,20 @@ def _gpu_grads(w, G_rows):
 
 
 def _compare(gpu, ref, tol, what):
-    for k in GRAD_KEYS:
-        a = np.asarray(gpu[k], dtype=np.float64)
-        b = np.asarray(ref[k], dtype=np.float64)
-        err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
-        log(f"{what} d{k}: max-norm rel err {err:.3e}")
-        assert err <= tol, (what, k, err)
+    """Every gradient kind, the angles (phi3 exactly 0) and the velocity gradient within tol of
+    the max-norm of the oracle's, measured from the oracle's range of correct values (ref from
+    O.adjoint(..., ties=TIES))."""
+    assert_grads_in(gpu, ref, GRAD_KEYS, tol, what)
     a, b = np.asarray(gpu["angles"]), np.asarray(ref["angles"])
-    err = np.abs(a[:2] - b[:2]).max() / np.abs(b[:2]).max()
-    log(f"{what} dangles: rel err {err:.3e}; gpu phi3 = {a[2]:.3e}")
+    lo, hi = ref.get("angles_lo", b), ref.get("angles_hi", b)
+    err = outside(a[:2], lo[:2], hi[:2]).max() / np.abs(b[:2]).max()
+    log(f"{what} dangles: distance from the oracle's range {err:.3e} "
+        f"(vs FP64 value {np.abs(a[:2] - b[:2]).max() / np.abs(b[:2]).max():.3e}); "
+        f"gpu phi3 = {a[2]:.3e}")
     assert err <= tol and a[2] == 0.0
-    np.testing.assert_allclose(gpu["vel"], np.asarray(ref["vel"], dtype=np.float64),
-                               rtol=0, atol=tol * np.abs(ref["vel"]).max())
+    vb = np.asarray(ref["vel"], dtype=np.float64)
+    e = outside(gpu["vel"], ref.get("vel_lo", vb), ref.get("vel_hi", vb)).max()
+    assert e <= tol * np.abs(vb).max(), (what, "vel", e / np.abs(vb).max())
 
 
 def _small_workload(n=3000, seed=31):
@@ -66,7 +68,7 @@ def test_log_grid_gradient_vs_oracle_and_fd():
     rng = np.random.default_rng(7)
     G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
     _, g = _gpu_grads(w, G)
-    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, ties=TIES)
     _compare(g, ref, 2e-5, "log-grid seeded-G")
     _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False)
 
@@ -78,7 +80,7 @@ def test_backward_kernel_on_seeded_gradient():
     rng = np.random.default_rng(5)
     G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
     _, g = _gpu_grads(w, G)
-    ref = O.adjoint(w.particles, cfg, G.astype(np.float64))
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), ties=TIES)
     _compare(g, ref, 2e-5, "seeded-G")
 
 
@@ -104,7 +106,7 @@ def test_seeded_gradient_with_bins_past_both_ends_of_the_ssp_grid():
     rng = np.random.default_rng(11)
     G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
     _, g = _gpu_grads(w, G)
-    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, ties=TIES)
     _compare(g, ref, 2e-5, "edges seeded-G")
     _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False)
 
@@ -122,7 +124,7 @@ def test_seeded_gradient_on_a_coarse_telescope_grid():
     rng = np.random.default_rng(13)
     G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
     _, g = _gpu_grads(w, G)
-    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, ties=TIES)
     _compare(g, ref, 2e-5, "coarse seeded-G")
     _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False)
 
@@ -147,7 +149,7 @@ def test_bin_mean_seeded_gradient(ratio, n_tel, seed):
     rng = np.random.default_rng(seed)
     G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
     _, g = _gpu_grads(w, G)
-    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, ties=TIES)
     _compare(g, ref, 2e-5, f"bin-mean x{ratio} seeded-G")
     _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False, h_vlos=1e-2,
               h_met=5e-5)
@@ -172,16 +174,11 @@ def test_ragged_particle_counts_backward(n):
         assert np.all(np.asarray(g["angles"]) == 0.0)
         return
     cfg = O.config_from_workload(w)
-    ref = O.adjoint(w.particles, cfg, G.astype(np.float64))
-    for k in GRAD_KEYS:
-        a = np.asarray(g[k], dtype=np.float64)
-        b = np.asarray(ref[k], dtype=np.float64)
-        scale = np.abs(b).max()
-        err = np.abs(a - b).max() / scale if scale > 0 else np.abs(a).max()
-        log(f"n={n} d{k}: max-norm rel err {err:.3e}")
-        assert err <= 2e-5, (k, err)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), ties=TIES)
+    assert_grads_in(g, ref, GRAD_KEYS, 2e-5, f"n={n}")
     a, b = np.asarray(g["angles"]), np.asarray(ref["angles"])
-    assert np.abs(a[:2] - b[:2]).max() <= 2e-5 * max(np.abs(b[:2]).max(), 1e-300) and a[2] == 0.0
+    err = outside(a[:2], ref["angles_lo"][:2], ref["angles_hi"][:2]).max()
+    assert err <= 2e-5 * max(np.abs(b[:2]).max(), 1e-300) and a[2] == 0.0
 
 
 @pytest.mark.parametrize("ratio,n_tel,seed", [(1.3, 1300, 61), (2.6, 660, 67), (0.6, 2800, 71)])
@@ -202,7 +199,7 @@ def test_log_grid_bin_mean_seeded_gradient(ratio, n_tel, seed):
     rng = np.random.default_rng(seed)
     G = rng.normal(size=(w.nx * w.ny, w.n_tel)).astype(np.float32)
     _, g = _gpu_grads(w, G)
-    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, ties=TIES)
     _compare(g, ref, 2e-5, f"log bin-mean x{ratio} seeded-G")
     _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=30, quadratic=False, h_vlos=0.03,
               h_met=1e-3, h_age=1e-4, age_rel=True)
@@ -230,7 +227,8 @@ def _fd_delta_L(cfg, G, s, dplus, dminus, quadratic=True):
 def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-4, h_met=1e-6,
               h_age=1e-6, age_rel=False):
     """FP64 central differences of the oracle's particle spectra against the GPU gradient, on up
-    to n_check in-field particles at least 1e-4 away from SSP nodes. h_vlos (km/s) and h_met
+    to n_check in-field particles at least 1e-4 away from SSP nodes whose oracle gradients are
+    all at least 1e-2 of the sample's largest. h_vlos (km/s) and h_met
     (dex) are the velocity and metallicity steps: the oracle's bin mean is a difference of prefix
     sums over the node grid, whose rounding needs larger steps than bin-centre sampling does (the
     spectrum is linear in [M/H] inside a cell, so any step below the node distance is exact)."""
@@ -238,8 +236,12 @@ def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-
     key, vlos = fo["key"], fo["vlos"]
     la, mz = cfg.log_age_nodes, cfg.met_nodes
     rng = np.random.default_rng(seed)
-    cand = rng.permutation(np.flatnonzero(key < cfg.n_spaxels))
-    maxg = {k: np.abs(gpu[k]).max() for k in GRAD_KEYS}
+    cand = rng.permutation(np.flatnonzero(key < cfg.n_spaxels))[:max(4000, 60 * n_check)]
+    # particles are chosen by the oracle's gradient (never the GPU's): a GPU gradient wrongly
+    # near zero cannot exclude its own particle
+    ora = O.adjoint(p, cfg, G, fo, idx=cand)
+    ora_at = {int(i): r for r, i in enumerate(cand)}
+    maxg = {k: np.abs(ora[k]).max() for k in GRAD_KEYS}
     checked = 0
     worst = {k: 0.0 for k in GRAD_KEYS}
     for i in cand:
@@ -251,7 +253,7 @@ def _fd_check(w, cfg, fo, G, gpu, n_check=64, seed=0, quadratic=True, h_vlos=1e-
         if (np.min(np.abs(la - math.log10(a))) < max(1e-4, 2 * ha / (a * math.log(10)))
                 or np.min(np.abs(mz - z)) < max(1e-4, 2 * h_met)):
             continue
-        if any(abs(gpu[k][i]) < 1e-2 * maxg[k] for k in GRAD_KEYS):
+        if any(abs(ora[k][ora_at[int(i)]]) < 1e-2 * maxg[k] for k in GRAD_KEYS):
             continue
         one = {f: np.asarray(getattr(p, f)[i:i + 1], dtype=np.float64) for f in p.FIELDS}
 
@@ -291,7 +293,7 @@ def test_small_loss_gradient_vs_oracle_and_fd():
     target = _oracle_target(w, 1)
     fo = O.forward(w.particles, cfg)
     G = O.loss_grad_cube(fo["cube"], target, cfg)
-    ref = O.adjoint(w.particles, cfg, G, fo)
+    ref = O.adjoint(w.particles, cfg, G, fo, ties=TIES)
     # GPU: the whole loss path on the device (forward, residual, adjoint PSF/LSF, backward)
     import torch
     from paper_2412_08265_amd import ops
@@ -369,19 +371,17 @@ def test_differentiation_workload_full_size():
     rng = np.random.default_rng(1)
     sub = rng.choice(w.particles.n, 4000, replace=False)
     log("C5: oracle adjoint on 4000 sampled particles")
-    ref = O.adjoint(w.particles, cfg, G, fo, idx=sub)
+    ref = O.adjoint(w.particles, cfg, G, fo, idx=sub, ties=TIES)
     gs = {k: g[k][sub] for k in GRAD_KEYS}
     gs["vel"] = g["vel"][:, sub]
     # angles: the full sum needs every particle; compare the oracle's full gradient
     log("C5: oracle adjoint (all particles) for the angle gradient")
-    ref_all = O.adjoint(w.particles, cfg, G, fo, chunk=256, workers=WORKERS)
+    ref_all = O.adjoint(w.particles, cfg, G, fo, chunk=256, workers=WORKERS, ties=TIES)
     gs["angles"] = g["angles"]
     ref["angles"] = ref_all["angles"]
+    ref["angles_lo"], ref["angles_hi"] = ref_all["angles_lo"], ref_all["angles_hi"]
     _compare(gs, ref, 1e-4, "C5")
-    for k in GRAD_KEYS:
-        e = np.abs(g[k] - ref_all[k]).max() / np.abs(ref_all[k]).max()
-        log(f"C5 full-vector d{k}: max-norm rel err {e:.3e}")
-        assert e <= 1e-4
+    assert_grads_in(g, ref_all, GRAD_KEYS, 1e-4, "C5 full-vector")
     _fd_check(w, cfg, fo, G, g, n_check=64, seed=2)
 
 
@@ -401,13 +401,8 @@ def test_bin_mean_adjoint_on_the_differentiation_workload():
     _, g = _gpu_grads(w, G)
     sub = rng.choice(w.particles.n, 4000, replace=False)
     log("bin-mean C5: oracle adjoint on 4000 sampled particles")
-    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, idx=sub)
-    for k in GRAD_KEYS:
-        a = np.asarray(g[k][sub], dtype=np.float64)
-        b = np.asarray(ref[k], dtype=np.float64)
-        err = np.abs(a - b).max() / np.abs(b).max()
-        log(f"bin-mean C5 d{k}: max-norm rel err {err:.3e}")
-        assert err <= 1e-4, (k, err)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, idx=sub, ties=TIES)
+    assert_grads_in({k: g[k][sub] for k in GRAD_KEYS}, ref, GRAD_KEYS, 1e-4, "bin-mean C5")
     _fd_check(w, cfg, fo, G.astype(np.float64), g, n_check=32, seed=3, quadratic=False,
               h_vlos=1e-2, h_met=5e-5)
 
@@ -431,13 +426,8 @@ def test_adjoint_on_the_full_size_galaxy(grids, resample):
     _, g = _gpu_grads(w, G)
     sub = rng.choice(w.particles.n, 4000, replace=False)
     log(f"{tag}: oracle adjoint on 4000 sampled particles")
-    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, idx=sub)
-    for k in GRAD_KEYS:
-        a = np.asarray(g[k][sub], dtype=np.float64)
-        b = np.asarray(ref[k], dtype=np.float64)
-        err = np.abs(a - b).max() / np.abs(b).max()
-        log(f"{tag} d{k}: max-norm rel err {err:.3e}")
-        assert err <= 1e-4, (k, err)
+    ref = O.adjoint(w.particles, cfg, G.astype(np.float64), fo, idx=sub, ties=TIES)
+    assert_grads_in({k: g[k][sub] for k in GRAD_KEYS}, ref, GRAD_KEYS, 1e-4, tag)
     out = np.asarray(fo["key"]) >= w.nx * w.ny
     assert out.any()
     for k in GRAD_KEYS:

@@ -755,3 +755,94 @@ def test_bin_mean_adjoint_identities():
             ends += sgn * float(O.linear_at(S, np.array([[q]]))[0, 0]) * (-lam_e / f2)
     expect = B * float(p.mass[i]) * ends / O.C_KMS
     assert abs(g1["vlos"][i] - expect) <= 1e-9 * max(abs(expect), 1e-30) + 1e-12 * abs(g1["vlos"]).max()
+
+
+# ------------------------------------------------------------------ node decisions and ties
+def test_node_cell_matches_brute_force_loop():
+    """floor(q) with the last node mapped to the last interval, off the grid outside [0, n-1]:
+    a plain per-element loop with explicit comparisons."""
+    n = 7
+    q = np.array([[-1.5, -1e-12, 0.0, 0.3, 1.0, 2.999999, 5.5, 6.0, 6.0 + 1e-12, 9.0, np.nan]])
+    k, valid = O.node_cell(q, n)
+    for j, x in enumerate(q[0]):
+        ok = (not math.isnan(x)) and 0.0 <= x <= n - 1
+        assert valid[0, j] == ok
+        if ok:
+            assert k[0, j] == min(int(math.floor(x)), n - 2)
+
+
+def test_ties_at_the_band_ends_bracket_in_band_and_zero():
+    """A particle at rest on identical grids: bin 0 sits exactly on node 0 and the last bin on
+    node n-1. The FP64 definition counts both in the band (value m S at the node); a method whose
+    index carries an error may also find either just outside (value 0), so the bounds are
+    [0, m S] there and collapse to the plain value at every other bin."""
+    ssp = synth.make_ssp(6, 4, 4000.0, 2.0, 300)
+    cfg = _cfg(ssp=ssp)
+    p = _single(mass=2.0)
+    f, lo, hi, nt = O.particle_spectra_bounds(p, np.array([0]), np.zeros(1), cfg, (1e-7, 0.0))
+    ja, jz, ta, tz, w, _, _ = O.ssp_weights(p.age, p.met, cfg.log_age_nodes, cfg.met_nodes)
+    S = O.interp_templates(cfg.ssp_flux, ja, jz, w)[0]
+    assert nt == 300                                  # every bin centre is on a node
+    for j in (0, 299):
+        assert f[0, j] == pytest.approx(2.0 * S[j], rel=1e-14)
+        assert lo[0, j] == 0.0 and hi[0, j] == pytest.approx(2.0 * S[j], rel=1e-14)
+    inner = slice(1, 299)
+    np.testing.assert_allclose(lo[0, inner], f[0, inner], rtol=1e-13)
+    np.testing.assert_allclose(hi[0, inner], f[0, inner], rtol=1e-13)
+    # no ties without rounding: the plain values come back unchanged
+    f2, lo2, hi2, nt2 = O.particle_spectra_bounds(p, np.array([0]), np.array([123.4]), cfg,
+                                                  (0.0, 0.0))
+    assert nt2 == 0 and np.array_equal(lo2, f2) and np.array_equal(hi2, f2)
+
+
+def test_tied_velocity_gradient_brackets_both_one_sided_differences():
+    """At rest on identical grids every bin lies on a node, where the interpolant has a kink:
+    dL/dv_los has a left and a right derivative. The bounds of the adjoint (each bin's term from
+    the interval left or right of its node) must hold both one-sided finite differences of the
+    forward model (v = +h moves every bin to the interval left of its node, v = -h to the right),
+    and the two must differ (the kinks are real)."""
+    ssp = synth.make_ssp(6, 4, 4000.0, 2.0, 300)
+    cfg = _cfg(nx=1, ny=1, s=4.0, ssp=ssp)
+    p = _single(mass=1.5, age=2.5, met=-0.7)
+    fw = O.forward(p, cfg)
+    rng = np.random.default_rng(3)
+    G = rng.normal(size=(1, 300))
+    G[0, [0, 299]] = 0.0      # the end bins jump (in band / zero): no derivative there
+    g = O.adjoint(p, cfg, G, fw, ties=(1e-7, 0.0))
+    assert g["n_ties"] == 300
+    base = O.particle_spectra(p, np.array([0]), np.zeros(1), cfg)[0]
+    h = 1e-3
+    right = np.dot(G[0], O.particle_spectra(p, np.array([0]), np.array([h]), cfg)[0] - base) / h
+    left = np.dot(G[0], base - O.particle_spectra(p, np.array([0]), np.array([-h]), cfg)[0]) / h
+    lo, hi = g["vlos_lo"][0], g["vlos_hi"][0]
+    tol = 1e-6 * max(abs(left), abs(right))
+    assert abs(right - left) > 1e3 * tol
+    for d in (left, right):
+        assert lo - tol <= d <= hi + tol, (lo, d, hi)
+    assert lo - tol <= g["vlos"][0] <= hi + tol
+    # the angle bounds follow: dL/dphi1 = dL/dv_los * (dR/dphi1 v)_z at zero angles
+    assert g["angles_lo"][0] <= g["angles"][0] <= g["angles_hi"][0]
+
+
+def test_tied_bin_mean_edge_brackets_both_one_sided_differences():
+    """Bin mean on identical grids at rest: the lowest bin's lower edge lies half a node below
+    node 0, and bin 0's upper edge half a node above; with telescope bins shifted by half a step
+    an edge sits exactly on node 0. Moving it into the grid adds flux, moving it out adds none,
+    so the velocity gradient has two one-sided values there; the bounds hold both."""
+    ssp = synth.make_ssp(6, 4, 4000.0, 2.0, 300)
+    cfg = _cfg(nx=1, ny=1, s=4.0, ssp=ssp, tel=(4001.0, 2.0, 10), resample=1)
+    p = _single(mass=1.5, age=2.5, met=-0.7)
+    fw = O.forward(p, cfg)
+    G = np.zeros((1, 10))
+    G[0, 0] = 1.0                                    # only bin 0, whose lower edge is node 0
+    g = O.adjoint(p, cfg, G, fw, ties=(1e-7, 0.0))
+    assert g["n_ties"] >= 1
+    base = O.particle_spectra(p, np.array([0]), np.zeros(1), cfg)[0]
+    h = 1e-3
+    right = np.dot(G[0], O.particle_spectra(p, np.array([0]), np.array([h]), cfg)[0] - base) / h
+    left = np.dot(G[0], base - O.particle_spectra(p, np.array([0]), np.array([-h]), cfg)[0]) / h
+    lo, hi = g["vlos_lo"][0], g["vlos_hi"][0]
+    tol = 1e-5 * max(abs(left), abs(right))
+    assert abs(right - left) > 1e2 * tol
+    for d in (left, right):
+        assert lo - tol <= d <= hi + tol, (lo, d, hi)
