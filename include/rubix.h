@@ -26,7 +26,11 @@
  *    outside the field (key nx*ny); one whose line-of-sight velocity is not finite contributes
  *    nothing to the cube; a NaN age or [M/H] takes the first node of its axis (infinities clamp
  *    to the matching end); a non-finite mass makes the voxels its spectrum reaches non-finite.
- *  - Sizes: particle counts up to 2^31-1 per job; int32 spaxel keys and offsets.
+ *  - Sizes: particle counts up to 2^31-1 per job; int32 spaxel keys and offsets; SSP grids of
+ *    fewer than 2^30 values (their byte offsets are 32-bit), larger ones fail with RUBIX_ERANGE.
+ *  - Line-of-sight velocities: a particle whose v_los is not finite adds nothing to the cube in
+ *    either resampling mode, and rubix_cube_backward gives it zero gradients and no share of the
+ *    angle gradients.
  */
 #ifndef RUBIX_H
 #define RUBIX_H
@@ -217,10 +221,10 @@ int rubix_add_noise(const rubix_job *jobs, int n_jobs, const rubix_noise *noise,
  *   3. rubix_forward_packed launches rotate/bin -> cube -> PSF/LSF (cube_raw -> cube) for every
  *      job of that table. Its launch arguments depend only on (dev_table, grid_blocks,
  *      max_psf_radius, max_sort_passes), never on the table's contents, so the launches can be
- *      captured once and replayed: each kernel runs grid_blocks blocks that claim the work items
- *      the table describes one at a time (persistent blocks). The claims consume counters held
- *      in the device table, so the table must be copied afresh from the host buffer before every
- *      launch (replaying without the copy skips the work).
+ *      captured once and replayed: each kernel runs grid_blocks blocks that stride over the work
+ *      items the table describes (block b takes items b, b + grid_blocks, ...; persistent
+ *      blocks). The table holds no state the launches consume: copy it before a replay only when
+ *      the batch changes.
  * The jobs' workspace regions are laid out inside `ws` (size: rubix_workspace_size minus
  * rubix_table_bytes), which must stay valid until the launches complete. */
 

@@ -452,7 +452,9 @@ __global__ __launch_bounds__(kFinThreads) void k_bwd_final(const Table *__restri
     if (i < J.n) {
       const int64_t j = i;
       float gm = 0.f, ga = 0.f, gz = 0.f, gv = 0.f;
-      if (J.key[j] < J.n_s) {
+      // a particle whose line-of-sight velocity is not finite adds nothing to the cube (its
+      // forward weights are zero), so it carries no gradient and no angle term either
+      if (J.key[j] < J.n_s && isfinite(J.vlos[j])) {
         const double age = J.age[j], m = J.mass[j], met = J.met[j], v = J.vlos[j];
         const int na = S.n_age, nz = S.n_met;
         const bool in_a = (age >= S.age_thr[0]) && (age <= S.age_thr[na - 1]);

@@ -109,12 +109,18 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__
     const double jac = 1.0 / (opz * (1.0 + beta));
     // forward weights: flux_scale m J for bin-centre sampling; for the bin mean the Jacobian
     // cancels against the change of variable lambda -> node index, leaving dlam_ssp/dlam_tel
-    const double scale = mode != 0 ? 1.0
+    // a line-of-sight velocity that is not finite: the particle adds nothing (zero weights; the
+    // Jacobian would be NaN) and its Doppler slope is set to 0 below, so every kernel that reads
+    // the record sees finite indices and no NaN reaches a bin
+    const bool moving = isfinite(v);
+    const double scale = !moving ? 0.0
+                         : mode != 0 ? 1.0
                          : J.resample ? J.flux_scale * m * J.bin_scale : J.flux_scale * m * jac;
     PrepRec r;
     r.row = (ja * S.n_met + jz) * S.n_lam;
     bool fits;
     doppler_slope(J, S, v, r.g, fits);
+    if (!moving) r.g = 0.f;
     r.a[0] = (float)(scale * (1.0 - ta) * (1.0 - tz));
     r.a[1] = (float)(scale * (1.0 - ta) * tz);
     r.a[2] = (float)(scale * ta * (1.0 - tz));

@@ -172,8 +172,9 @@ static int validate_ssp(const rubix_ssp *ssp) {
     return fail(RUBIX_EINVAL, "ssp.lam.log_spaced must be 0 or 1");
   if (ssp->lam.log_spaced && !finite_pos(ssp->lam.start))
     return fail(RUBIX_EINVAL, "a log-spaced SSP grid needs start > 0");
-  if ((int64_t)ssp->n_age * ssp->n_met * ssp->lam.n > INT32_MAX)
-    return fail(RUBIX_ERANGE, "ssp grid has more than 2^31-1 values");
+  // the kernels address the template grid through 32-bit byte offsets
+  if ((int64_t)ssp->n_age * ssp->n_met * ssp->lam.n >= ((int64_t)1 << 30))
+    return fail(RUBIX_ERANGE, "ssp grid has 2^30 or more values (32-bit byte offsets)");
   return RUBIX_OK;
 }
 

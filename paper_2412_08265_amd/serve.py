@@ -397,14 +397,21 @@ class GraphExecutor(_DeviceExecutorBase):
             ops.rubix_forward_pack(jobs, self.ssp, ws, lane["host"], self.max_psf_radius,
                                    self.max_sort_passes)
             self._free.popleft()
-            self.compute.wait_event(up)
-            for d in hosts:
-                d.record_stream(self.compute)
-            if self.mode == "native":
-                ops.rubix_graph_launch(lane["graph"], lane["host"][:nt])
-            else:
-                lane["dev"][:nt].copy_(lane["host"][:nt], non_blocking=True)
-                lane["graph"].replay()
+            try:
+                self.compute.wait_event(up)
+                for d in hosts:
+                    d.record_stream(self.compute)
+                if self.mode == "native":
+                    ops.rubix_graph_launch(lane["graph"], lane["host"][:nt])
+                else:
+                    lane["dev"][:nt].copy_(lane["host"][:nt], non_blocking=True)
+                    lane["graph"].replay()
+            except BaseException:
+                # the lane goes back once whatever reached the stream has finished with its
+                # buffers, so a failed launch does not lose it
+                self.compute.synchronize()
+                self._free.append(lane)
+                raise
             done = torch.cuda.Event()
             done.record(self.compute)
         return {"lane": lane, "done": done, "bufs": bufs, "hosts": hosts, "ws": ws,

@@ -124,6 +124,11 @@ def test_ssp_validation(lib):
         assert _ws_size(lib, [_job()], ctypes.byref(bad))[0] == -1, (la, mz, n)
     big, keep3 = _ssp_c(np.arange(256) * 0.01, np.arange(64) * 0.01, 200000)
     assert _ws_size(lib, [_job()], ctypes.byref(big))[0] == -4
+    # the kernels' 32-bit byte offsets: 2^30 template values are one too many, 2^30 - 16384 fit
+    edge, keep4 = _ssp_c(np.arange(256) * 0.01, np.arange(64) * 0.01, 65536)
+    assert _ws_size(lib, [_job()], ctypes.byref(edge))[0] == -4
+    fits, keep5 = _ssp_c(np.arange(256) * 0.01, np.arange(64) * 0.01, 65535)
+    assert _ws_size(lib, [_job()], ctypes.byref(fits))[0] == 0
 
 
 def test_packed_table_sizes_and_validation(lib):
