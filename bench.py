@@ -61,12 +61,26 @@ def traffic_from_profile(units_kernel: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, n_in_full: int, sample_particles: int):
     """The FP64 oracle on a seeded random sample of the same galaxy, scaled to the full workload:
-    t = t_particles(sample) * N_in/N_in(sample) + t_psf_lsf(row band) * n_s/rows."""
+    t = t_particles(sample) * N_in/N_in(sample) + t_psf_lsf(row band) * n_s/rows. It runs in
+    forked processes, one per host core available to this job: all of os.cpu_count() up to 16,
+    the host share a one-GPU job may use."""
     import numpy as np
     import oracle as O
-    cores = min(os.cpu_count() or 1, 16)
+    host = os.cpu_count() or 1
+    cores = min(host, 16)
     cfg = O.config_from_workload(w)
     rng = np.random.default_rng(12345)
     idx = np.sort(rng.choice(w.particles.n, sample_particles, replace=False))
@@ -91,6 +105,10 @@ def cpu_baseline(w, n_in_full: int, sample_particles: int):
     t_total = t_part * (n_in_full / max(1, n_in_s)) + t_psf * (cfg.ny / (rows + 2 * r))
     value = n_in_full * cfg.n_tel / t_total
     return {"value": value, "unit": "particle*lambda-bins/s", "cores": cores, "kind": "oracle",
+            "host_cpus": host, "cpu_model": cpu_model(),
+            "method": ("extrapolated: the particle stage from a random particle sample (time "
+                       "scales with in-field particles at fixed bins), the PSF/LSF stage from a "
+                       "band of rows (time scales with rows)"),
             "sample": (f"{sample_particles} random particles of the same galaxy ({n_in_s} in "
                        f"field, all {cfg.n_tel} bins, {t_part:.1f} s on {cores} processes) plus "
                        f"PSF/LSF of a {rows + 2 * r}-row band ({t_psf:.1f} s), scaled to "
@@ -169,6 +187,50 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+def sweep_main(args):
+    """Runtime of the forward step against the particle count on one GPU (the one-GPU part of the
+    paper's strong-scaling experiment, Sec. 4): the 1e7-particle workload's galaxy generator,
+    grids and filters at each N, inputs resident, median of the timed steps. The 6e6 point is the
+    particle count of the paper's speed comparison (Sec. 4: 8.58 s on one A100, spaxel and
+    wavelength grids not stated), quoted as context."""
+    import numpy as np
+    import torch
+    from paper_2412_08265_amd import ops, synth
+    rows = []
+    for n in [int(float(x)) for x in args.sweep_n.split(",")]:
+        w = synth.large_workload(n=n)
+        fw = ops.Forward(ops.DeviceGalaxy.from_host(w.particles), ops.Observation.from_workload(w),
+                         ops.DeviceSSP.from_grid(w.ssp))
+        for _ in range(args.warmup):
+            fw()
+        torch.cuda.synchronize()
+        n_in = int(fw.buf.seg_off[-1].item())
+        ts = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fw()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        rows.append({"particles": n, "in_field": n_in, "ms_per_step": ms,
+                     "p90_ms": float(np.percentile(ts, 90)),
+                     "particle_lambda_bins_per_s": n_in * w.n_tel / (ms * 1e-3)})
+        err(f"N={n}: {ms:.3f} ms per step ({n_in} in field)")
+        del fw
+        torch.cuda.empty_cache()
+    out = {"metric": "forward step time vs particle count (1 GPU)",
+           "workload": "disk+bulge galaxy (seed 3) at each N, 150x150 spaxels of 0.2 kpc, 4563 "
+                       "bins of 1.25 A from 4700 A, SSP 106x12x4563, PSF 2 spx, LSF 2.7 A",
+           "timing": f"HIP events around rotate/bin + cube + PSF/LSF, median of {args.steps} steps "
+                     f"after {args.warmup} warm-ups",
+           "context": "paper Sec. 4: 6e6 particles in 8.58 s on one A100 (end to end, grids not "
+                      "stated) and 123.57 s on a 24-core CPU",
+           "data": "synthetic", "sweep": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +249,9 @@ def main():
                     help="resampling reading / grid kind of the forward step: bin-centre sampling "
                          "on linear grids (default, the headline), bin mean (flux conserving), "
                          "grids uniform in ln(lambda), or the bin mean on those grids")
+    ap.add_argument("--sweep-n", default=None,
+                    help="comma-separated particle counts: print the forward step time against N "
+                         "instead of the forward-step line")
     ap.add_argument("--serve", action="store_true",
                     help="print the serving report (request stream, batched graph path vs "
                          "one-at-a-time plain launches) instead of the forward-step line")
@@ -205,6 +270,9 @@ def main():
 
     if args.serve:
         serve_main(args)
+        return
+    if args.sweep_n:
+        sweep_main(args)
         return
 
     import torch
@@ -345,6 +413,24 @@ def main():
         torch.cuda.synchronize()
         out["stages_ms"]["backward"] = b0.elapsed_time(b1) / nb
         err(f"backward {out['stages_ms']['backward']:.3f} ms")
+    # achievable HBM rate on this GPU: a 1 GiB device-to-device copy (read + write), quoted beside
+    # the 8 TB/s peak
+    ca = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        cb.copy_(ca)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * ca.numel() * 4 * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    out["hbm_copy"] = {"GBs": copy_gbs, "frac_of_peak": copy_gbs / PEAK_HBM_GBS,
+                       "what": "1 GiB device-to-device copy (torch copy_ kernel), read + write "
+                               "bytes / time, 10 repeats"}
+    del ca, cb
+    err(f"copy {copy_gbs:.0f} GB/s")
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
