@@ -212,6 +212,21 @@ typedef struct {
 int rubix_add_noise(const rubix_job *jobs, int n_jobs, const rubix_noise *noise,
                     float *const *cubes, void *stream);
 
+/* ---- Allocation-free PSF/LSF ------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, hosts that forbid hipMalloc): rubix_psf_lsf without a workspace argument. The job table
+ * and the intermediate cubes live in a static device array of RUBIX_NOALLOC_SCRATCH_BYTES that
+ * each GPU the library runs on holds until the process ends; the call allocates nothing and
+ * clears nothing (every byte it reads there it has written first). The caller still owns in[k]
+ * and out[k]. Fails with RUBIX_ERANGE, before any device work, if the batch needs more scratch
+ * than that: the aligned job table plus 4 * nx * ny * tel.n bytes (rounded up to 256) per job.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU (other
+ * threads, or other streams not ordered with this one) race; calls ordered on one stream do not.
+ * Results equal rubix_psf_lsf's bit for bit. */
+#define RUBIX_NOALLOC_SCRATCH_BYTES (64 << 20)
+int rubix_psf_lsf_noalloc(const rubix_job *jobs, int n_jobs, const float *const *in,
+                          float *const *out, void *stream);
+
 /* ---- Batched forward pass for replayed launches (serving) -----------------------------------
  * The calls above upload their job table through kernel arguments. For a serving loop that
  * replays one captured launch sequence (a HIP graph) for every batch, the table instead lives in

@@ -59,7 +59,7 @@ EXPORTS = ("rubix_workspace_size", "rubix_rotate_bin", "rubix_cube", "rubix_psf_
            "rubix_cube_backward", "rubix_last_error", "rubix_version", "rubix_table_bytes",
            "rubix_forward_pack", "rubix_forward_packed", "rubix_graph_create",
            "rubix_graph_launch", "rubix_graph_destroy", "rubix_cube_timer",
-           "rubix_cube_timer_read", "rubix_add_noise")
+           "rubix_cube_timer_read", "rubix_add_noise", "rubix_psf_lsf_noalloc")
 
 _lib = None
 
@@ -86,6 +86,8 @@ def load() -> ctypes.CDLL:
                                c_void_p]
     lib.rubix_psf_lsf.argtypes = [POINTER(RubixJob), c_int, POINTER(c_void_p), POINTER(c_void_p),
                                   c_void_p, c_size_t, c_void_p]
+    lib.rubix_psf_lsf_noalloc.argtypes = [POINTER(RubixJob), c_int, POINTER(c_void_p),
+                                          POINTER(c_void_p), c_void_p]
     lib.rubix_cube_backward.argtypes = [POINTER(RubixJob), c_int, POINTER(RubixSSP),
                                         POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                         POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
@@ -105,7 +107,8 @@ def load() -> ctypes.CDLL:
     for f in ("rubix_workspace_size", "rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf",
               "rubix_cube_backward", "rubix_forward_pack", "rubix_forward_packed",
               "rubix_graph_create", "rubix_graph_launch", "rubix_graph_destroy",
-              "rubix_cube_timer", "rubix_cube_timer_read", "rubix_add_noise"):
+              "rubix_cube_timer", "rubix_cube_timer_read", "rubix_add_noise",
+              "rubix_psf_lsf_noalloc"):
         getattr(lib, f).restype = c_int
     lib.rubix_last_error.restype = ctypes.c_char_p
     lib.rubix_version.restype = ctypes.c_char_p

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -80,6 +81,7 @@ struct JobSizes {
   size_t o_tmp;                                                       // psf/lsf
   size_t o_bintab, o_dots, o_ang;                                     // backward (+ o_prep)
   size_t region;
+  size_t psf_region;                                                  // psf/lsf alone
 };
 
 static int radius_of(double sigma) { return sigma > 0.0 ? (int)(4.0 * sigma + 0.5) : 0; }
@@ -137,6 +139,7 @@ static JobSizes sizes_of(const rubix_job &j) {
   // psf/lsf region
   z.o_tmp = 0;
   size_t psf_end = al(4ull * z.cube_elems);
+  z.psf_region = psf_end;
   // backward region (prep at the same offset as in the cube region)
   o = al(sizeof(PrepRec) * (size_t)z.n);
   z.o_bintab = o; o += al(16ull * (z.n_tel + 1));  // n_tel + 1 bin edges for bin-mean jobs
@@ -255,6 +258,13 @@ static size_t workspace_bytes(const rubix_job *jobs, int n_jobs) {
   return b;
 }
 
+// Table plus the PSF/LSF intermediate cube of every job: all that rubix_psf_lsf's kernels use.
+static size_t psf_scratch_bytes(const rubix_job *jobs, int n_jobs) {
+  size_t b = al(table_bytes(n_jobs));
+  for (int k = 0; k < n_jobs; ++k) b += al(sizes_of(jobs[k]).psf_region);
+  return b;
+}
+
 static int check_ws(const rubix_job *jobs, int n_jobs, void *ws, size_t ws_bytes) {
   const size_t need = workspace_bytes(jobs, n_jobs);
   if (!ws) return fail(RUBIX_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
@@ -323,7 +333,7 @@ struct BwdIO {
 // region of `ws`. Per-call I/O (PSF/LSF in/out, backward buffers) is optional.
 static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,
                                         void *ws, const PslfIO *pl, const BwdIO *bw,
-                                        bool table_in_ws = true) {
+                                        bool table_in_ws = true, bool psf_only = false) {
   std::vector<uint8_t> buf(table_bytes(n_jobs), 0);
   Table *t = reinterpret_cast<Table *>(buf.data());
   JobDev *J = reinterpret_cast<JobDev *>(buf.data() + ((sizeof(Table) + 255) & ~size_t(255)));
@@ -389,7 +399,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
     d.bintab = reinterpret_cast<float4 *>(region + z.o_bintab);
     d.dots = reinterpret_cast<double *>(region + z.o_dots);
     d.ang_part = reinterpret_cast<double *>(region + z.o_ang);
-    region += al(z.region);
+    region += al(psf_only ? z.psf_region : z.region);
     // PSF/LSF routing: lambda pass, y pass, x pass; the last active pass writes `out`
     int64_t n_lsf = 0, n_psfy = 0, n_psfx = 0, n_copy = 0;
     if (pl) {
@@ -473,6 +483,50 @@ static int run(const std::vector<uint8_t> &tab, void *ws, hipStream_t s, Launche
   const Table *host = reinterpret_cast<const Table *>(tab.data());
   e = fn(static_cast<const Table *>(ws), host->h, 0, s);
   return device_status(e, what);
+}
+
+static int validate_psf_io(const rubix_job *jobs, int n_jobs, const float *const *in,
+                           float *const *out) {
+  int rc;
+  if ((rc = validate_jobs(jobs, n_jobs, CALL_PSF))) return rc;
+  if (!in || !out) return fail(RUBIX_EINVAL, "in/out arrays are NULL");
+  for (int k = 0; k < n_jobs; ++k) {
+    if (!in[k] || !out[k]) return fail(RUBIX_EINVAL, "job %d: in/out cube is NULL", k);
+    const int64_t bytes = (int64_t)jobs[k].grid.nx * jobs[k].grid.ny * jobs[k].tel.n * 4;
+    const char *a = reinterpret_cast<const char *>(in[k]);
+    const char *b = reinterpret_cast<const char *>(out[k]);
+    if (a < b + bytes && b < a + bytes) return fail(RUBIX_EINVAL, "job %d: in and out overlap", k);
+  }
+  return RUBIX_OK;
+}
+
+// Scratch of the allocation-free entry point: the job table and the PSF/LSF intermediate cubes,
+// in a file-scope device array that every GPU the library runs on holds until the process ends.
+// In host code `scratch` names a host-side stand-in, never the device memory: the device address
+// comes from hipGetSymbolAddress, taken once per device with that device current, and only that
+// address is handed to kernels. Calls that overlap on one GPU share the array and race.
+static __device__ __align__(256) uint8_t scratch[RUBIX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices];
+
+static int scratch_on_current_device(void **ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_status(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(RUBIX_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return device_status(e, "hipGetSymbolAddress(scratch)");
+    if (!p || (reinterpret_cast<uintptr_t>(p) & 255))
+      return fail(RUBIX_EDEVICE, "scratch symbol address unusable");
+    g_scratch_dev[dev] = p;
+  }
+  *ptr = g_scratch_dev[dev];
+  return RUBIX_OK;
 }
 
 }  // namespace rubix
@@ -561,19 +615,28 @@ int rubix_psf_lsf(const rubix_job *jobs, int n_jobs, const float *const *in, flo
                   void *ws, size_t ws_bytes, void *stream) {
   g_err.clear();
   int rc;
-  if ((rc = validate_jobs(jobs, n_jobs, CALL_PSF))) return rc;
-  if (!in || !out) return fail(RUBIX_EINVAL, "in/out arrays are NULL");
-  for (int k = 0; k < n_jobs; ++k) {
-    if (!in[k] || !out[k]) return fail(RUBIX_EINVAL, "job %d: in/out cube is NULL", k);
-    const int64_t bytes = (int64_t)jobs[k].grid.nx * jobs[k].grid.ny * jobs[k].tel.n * 4;
-    const char *a = reinterpret_cast<const char *>(in[k]);
-    const char *b = reinterpret_cast<const char *>(out[k]);
-    if (a < b + bytes && b < a + bytes) return fail(RUBIX_EINVAL, "job %d: in and out overlap", k);
-  }
+  if ((rc = validate_psf_io(jobs, n_jobs, in, out))) return rc;
   if ((rc = check_ws(jobs, n_jobs, ws, ws_bytes))) return rc;
   PslfIO io{in, out};
   auto tab = build_table(jobs, n_jobs, nullptr, ws, &io, nullptr);
   return run(tab, ws, static_cast<hipStream_t>(stream), launch_psf_lsf, "rubix_psf_lsf");
+}
+
+int rubix_psf_lsf_noalloc(const rubix_job *jobs, int n_jobs, const float *const *in,
+                          float *const *out, void *stream) {
+  g_err.clear();
+  int rc;
+  if ((rc = validate_psf_io(jobs, n_jobs, in, out))) return rc;
+  const size_t need = psf_scratch_bytes(jobs, n_jobs);
+  if (need > (size_t)RUBIX_NOALLOC_SCRATCH_BYTES)
+    return fail(RUBIX_ERANGE, "rubix_psf_lsf_noalloc: the batch needs %zu bytes of scratch "
+                "(job table and intermediate cubes) > the static %d", need,
+                RUBIX_NOALLOC_SCRATCH_BYTES);
+  void *ws = nullptr;
+  if ((rc = scratch_on_current_device(&ws))) return rc;
+  PslfIO io{in, out};
+  auto tab = build_table(jobs, n_jobs, nullptr, ws, &io, nullptr, true, /*psf_only=*/true);
+  return run(tab, ws, static_cast<hipStream_t>(stream), launch_psf_lsf, "rubix_psf_lsf_noalloc");
 }
 
 int rubix_cube_backward(const rubix_job *jobs, int n_jobs, const rubix_ssp *ssp,

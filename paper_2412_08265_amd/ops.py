@@ -199,6 +199,15 @@ def rubix_psf_lsf(jobs, ins: Sequence[torch.Tensor], outs: Sequence[torch.Tensor
                             _stream(stream)))
 
 
+def rubix_psf_lsf_noalloc(jobs, ins: Sequence[torch.Tensor], outs: Sequence[torch.Tensor],
+                          stream=None) -> None:
+    """rubix_psf_lsf with the library's static scratch instead of a workspace (no allocation)."""
+    lib = _lib.load()
+    a = ptr_array([t.data_ptr() for t in ins])
+    b = ptr_array([t.data_ptr() for t in outs])
+    check(lib.rubix_psf_lsf_noalloc(_jobs_array(jobs), len(jobs), a, b, _stream(stream)))
+
+
 def rubix_cube_backward(jobs, ssp: DeviceSSP, grad_raw, d_mass, d_age, d_met, d_vlos, d_vel,
                         d_angles: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
     lib = _lib.load()

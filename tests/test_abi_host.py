@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol(lib):
     assert {"rubix_rotate_bin", "rubix_cube", "rubix_psf_lsf", "rubix_cube_backward",
             "rubix_workspace_size", "rubix_last_error", "rubix_table_bytes",
             "rubix_forward_pack", "rubix_forward_packed", "rubix_graph_create",
-            "rubix_graph_launch", "rubix_graph_destroy"} <= set(names)
+            "rubix_graph_launch", "rubix_graph_destroy", "rubix_psf_lsf_noalloc"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
     assert lib.rubix_version().decode().startswith("rubix-mi355x")
@@ -103,6 +103,27 @@ def test_entry_points_validate_before_launch(lib):
     assert lib.rubix_rotate_bin(_arr(j), 0, 0x1000, 1 << 30, None) == -1
     too_many = [_job() for _ in range(65)]
     assert lib.rubix_rotate_bin(_arr(*too_many), 65, 0x1000, 1 << 40, None) == -1
+
+
+def test_noalloc_psf_lsf_rejects_before_device_work(lib):
+    """The allocation-free PSF/LSF validates on the host and refuses a batch whose table and
+    intermediate cubes exceed its static scratch, before touching a device."""
+    from paper_2412_08265_amd import ops
+    ins = ops.ptr_array([0x1000])
+    outs = ops.ptr_array([0x1000 + (1 << 40)])
+    j = _job(nx=8, ny=6, tel_n=300)
+    assert lib.rubix_psf_lsf_noalloc(_arr(j), 1, None, outs, None) == -1
+    # 4 * 1024 * 1024 * 16 bytes = 64 MiB of intermediate cube alone: one byte too many with the
+    # table in front of it
+    big = _job(nx=1024, ny=1024, tel_n=16)
+    assert lib.rubix_psf_lsf_noalloc(_arr(big), 1, ins, outs, None) == -4
+    assert b"scratch" in lib.rubix_last_error()
+    over = [_job(nx=512, ny=512, tel_n=16) for _ in range(5)]     # 5 x 16 MiB
+    a5 = ops.ptr_array([0x1000 + k * (1 << 32) for k in range(5)])
+    b5 = ops.ptr_array([0x1000 + (1 << 40) + k * (1 << 32) for k in range(5)])
+    assert lib.rubix_psf_lsf_noalloc(_arr(*over), 5, a5, b5, None) == -4
+    # in and out overlapping
+    assert lib.rubix_psf_lsf_noalloc(_arr(j), 1, ins, ins, None) == -1
 
 
 def _ssp_c(la, mz, n_lam=100):
