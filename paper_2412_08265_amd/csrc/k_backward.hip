@@ -66,6 +66,12 @@ __device__ __forceinline__ void bwd_bin(float w0, float w1, float w2, float w3, 
   y = fmaf(g * lamf, dS, y);
 }
 
+// The value of the next lane (lane l receives lane l+1's; lane 63's result is not used).
+__device__ __forceinline__ float next_lane(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
+                                                               0x130, 0xf, 0xf, false));
+}
+
 __device__ __forceinline__ float4 ld_bintab(__amdgpu_buffer_rsrc_t rt, int j) {
   return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rt, j * 16, 0, 0));
 }
@@ -74,15 +80,24 @@ __device__ __forceinline__ float ld_grad(__amdgpu_buffer_rsrc_t rg, int j) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, j * 4, 0, 0));
 }
 
-// One wave per particle, walking the telescope grid in windows of kCubeWaveBins bins (lane l
-// takes bin jw + l; lanes 62 and 63 only stage). Where the particle's span fits a window (the
-// forward kernel's decision, carried in the record's sign) and the window's 64 nodes n0 .. n0+63
-// (n0 = lane 0's node) lie inside the SSP grid, the four corner rows are staged in the wave's
-// LDS rows with one coalesced load each and every bin reads its two taps per row from there;
-// otherwise each lane gathers its eight template values directly. Each lane accumulates its bins
-// in increasing order; the wave's sums are reduced in FP64.
+// One wave per particle, walking the telescope grid in windows of kCubeWaveBins bins (lane l takes
+// bin jw + l; lanes 62 and 63 only stage, with the constants of the window's last bin, so their
+// nodes stay in the window, and read no gradient). Each lane carries its bin's rest-frame node
+// index at zero velocity in 40-bit fixed point and its wavelength in FP64 from window to window
+// (one integer and one FP64 add per window instead of the split index's FP64 arithmetic).
+// The windows whose 64 nodes n0 .. n0+63 (n0 = lane 0's node) lie inside the SSP grid form one
+// contiguous run (n0 grows with the window's wavelength); for a particle whose span fits a
+// window (the forward kernel's decision, carried in the record's sign) the run takes a loop of
+// its own: the four corner rows are loaded with one coalesced load each (row base in scalar
+// registers) and lane l stages, at node n0 + l, the particle's spectrum, its slope to the next
+// node and its two cell directions in the wave's LDS rows, the slope and the directions formed
+// from differences of the FP32 node values (exact or nearly so) before they meet G; each bin then
+// interpolates the spectrum with the slope and the directions linearly. The
+// windows before and after the run, and every window of a particle that does not fit, gather each
+// lane's eight template values directly. Each lane accumulates its bins in increasing order; the
+// wave's sums are reduced in FP64.
 __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
-  __shared__ float rows[4][4][64];     // [wave][corner][node - n0]
+  __shared__ float rows[4][4][64];     // [wave][spectrum, slope, age, metallicity][node - n0]
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
   const float *__restrict__ flux = S.flux;
@@ -94,14 +109,20 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void *)flux, (short)0, (int)fbytes, 0x00020000);
   // byte offsets of this lane's node in the four corner rows relative to corner (ja, jz)
-  const uint32_t lb[4] = {(uint32_t)lane * 4u, (uint32_t)(lane + o1) * 4u,
-                          (uint32_t)(lane + o2) * 4u, (uint32_t)(lane + o3) * 4u};
+  uint32_t lo[4] = {(uint32_t)lane * 4u, (uint32_t)(lane + o1) * 4u, (uint32_t)(lane + o2) * 4u,
+                    (uint32_t)(lane + o3) * 4u};
+  const uint32_t oc[4] = {0u, (uint32_t)o1 * 4u, (uint32_t)o2 * 4u, (uint32_t)o3 * 4u};
+  const int jl = min(lane, kCubeWaveBins - 1);
+  // gradient offsets: lanes 62 and 63 point past any row, so their loads return 0
+  const uint32_t gofs = lane < kCubeWaveBins ? (uint32_t)lane * 4u : 0x40000000u;
   float *wr = &rows[w][0][0];
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_BWD]; vb += gridDim.x) {
     const int jj = find_job(T, K_BWD, vb);
     const JobDev &J = jobs[jj];
     const int64_t pbase = (vb - J.vb_start[K_BWD]) * kBwdParticles;
     const int n_in = J.seg_off[J.n_s];
+    const int64_t step_x = (int64_t)kCubeWaveBins * J.qrx;
+    const double step_l = (double)kCubeWaveBins * J.tel_step;
     for (int q = w; q < kBwdParticles; q += 4) {
       const int64_t p = pbase + q;
       if (p >= n_in) break;
@@ -110,72 +131,101 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
       const int spx = __builtin_amdgcn_readfirstlane(r.spaxel);
       const int rrow = __builtin_amdgcn_readfirstlane(r.row);
       const int jo = __builtin_amdgcn_readfirstlane(r.pad);     // input index: where the dots go
-      const float *__restrict__ G = J.grad_raw + (int64_t)spx * J.n_tel;
       const float w0 = r.a[0], w1 = r.a[1], w2 = r.a[2], w3 = r.a[3];
       const float ta = w2 + w3, tz = w1 + w3;   // bilinear fractions recovered from the weights
+      const float omta = 1.f - ta, omtz = 1.f - tz;
       const bool fits = rrow >= 0;
       const int row = prep_row(rrow);
+      // the particle's gradient row: loads past its last bin return 0
+      const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(J.grad_raw + (int64_t)spx * J.n_tel), (short)0, J.n_tel * 4, 0x00020000);
+      const float g = r.g;
+      const bool loglam = __builtin_amdgcn_readfirstlane(J.log_lambda) != 0;
       float sm = 0.f, sa = 0.f, sz = 0.f, y = 0.f;
-      // lanes past a window's bins take its last bin, so their nodes stay in the window; the
-      // gradient of the next window is loaded while this window's template rows are (a buffer
-      // load, which completes in order with the row loads, so waiting for the rows does not wait
-      // for it; the index is clamped, so the load past the last window re-reads the last bin)
-      const __amdgpu_buffer_rsrc_t rg =
-          __builtin_amdgcn_make_buffer_rsrc((void *)G, (short)0, J.n_tel * 4, 0x00020000);
-      const int lb_lane = min(lane, kCubeWaveBins - 1);
-      int jc = min(lb_lane, J.n_tel - 1);
-      float g_next = ld_grad(rg, jc);
-      for (int jw = 0; jw < J.n_tel; jw += kCubeWaveBins) {
-        const int jb = jw + lane;
-        const bool act = (lane < kCubeWaveBins) && (jb < J.n_tel);
-        int qi;
-        float qf, lamf;
-        split_index(J, S, jc, qi, qf, lamf);
-        const float gj = act ? g_next : 0.f;
-        jc = min(jw + kCubeWaveBins + lb_lane, J.n_tel - 1);
-        const float tq = fmaf(-lamf, r.g, qf);
+      // this lane's bin (jw + jl) in the current window: fixed-point rest index and wavelength
+      int64_t Qx = J.q0x + (int64_t)jl * J.qrx;
+      double lamd = J.tel_start + (double)jl * J.tel_step;
+      int jw = 0;
+      // node index of this lane's bin in window jw, the window's lowest node n0 (lane 0's) and
+      // the lane's gradient value
+      auto locate = [&](float &lamf, float &tau, int &k, int &n0, float &gj) {
+        const int qi = (int)(Qx >> 40);
+        const float qf = (float)(uint32_t)((uint64_t)Qx >> 8) * 0x1p-32f;
+        lamf = loglam ? 1.0f : (float)lamd;
+        const float tq = fmaf(-lamf, g, qf);
         const float fl = floorf(tq);
-        const float tau = tq - fl;
-        const int k = qi + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
-        const int n0 = __builtin_amdgcn_readfirstlane(k);
+        tau = tq - fl;
+        k = qi + (int)fminf(fmaxf(fl, -1.0e8f), 1.0e8f);
+        n0 = __builtin_amdgcn_readfirstlane(k);
+        gj = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                           rg, gofs + (uint32_t)jw * 4u, 0, 0));
+      };
+      // direct gathers: bins whose node lies outside the SSP grid carry no gradient (a select,
+      // not a store under a branch); the last node takes the last interval with t = 1
+      auto general = [&](float lamf, float tau, int k, float gj) {
+        const bool ok = (k >= 0) & ((k < nl - 1) | ((k == nl - 1) & (tau == 0.f)));
+        const float g = ok ? gj : 0.f;
+        const int kk = min(max(k, 0), nl - 2);
+        const float t = (k > kk) ? 1.f : tau;
+        const uint32_t bo = (uint32_t)(row + kk) * 4u;
         float pv[4], qv[4];
-        if (fits && n0 >= 0 && n0 + 63 <= nl - 1) {
-          // every lane's node k lies in [n0, n0 + 62], inside [0, n - 2]: the bin is on the grid
-          // and its interval is k itself, so no mask or clamp is needed here
-          const uint32_t so = (uint32_t)(row + n0) * 4u;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          pv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, bo + oc[c], 0, 0));
+          qv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, bo + oc[c] + 4u, 0, 0));
+        }
+        bwd_bin(w0, w1, w2, w3, ta, tz, t, g, lamf, pv, qv, sm, sa, sz, y);
+      };
+      if (fits) {
+        // windows before the run
+        for (; jw < J.n_tel; jw += kCubeWaveBins, Qx += step_x, lamd += step_l) {
+          float lamf, tau, gj;
+          int k, n0;
+          locate(lamf, tau, k, n0, gj);
+          if (n0 >= 0 && n0 + 63 <= nl - 1) break;
+          general(lamf, tau, k, gj);
+        }
+        // the run: every lane's node k lies in [n0, n0 + 62], inside [0, n - 2]
+        for (; jw < J.n_tel; jw += kCubeWaveBins, Qx += step_x, lamd += step_l) {
+          // the lane offsets pass through an empty asm each iteration, so their widening to
+          // 64 bits stays next to the loads and the loads take the scalar-base form
+          asm volatile("" : "+v"(lo[0]), "+v"(lo[1]), "+v"(lo[2]), "+v"(lo[3]));
+          float lamf, tau, gj;
+          int k, n0;
+          locate(lamf, tau, k, n0, gj);
+          if (!(n0 >= 0 && n0 + 63 <= nl - 1)) break;
+          const GChar *wb = (const GChar *)flux + (uint32_t)(row + n0) * 4u;
           float st[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
-            st[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lb[c] + so, 0, 0));
-          g_next = ld_grad(rg, jc);
+          for (int c = 0; c < 4; ++c) st[c] = *(const GFloat *)(wb + lo[c]);
+          // the slope to the next node from differences of the FP32 node values (the next
+          // node's values come from the next lane), not as a difference of two rounded spectra:
+          // on fine grids the spectrum changes by 1e-3 of itself per node
+          float d[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) wr[c * 64 + lane] = st[c];
+          for (int c = 0; c < 4; ++c) d[c] = next_lane(st[c]) - st[c];
+          wr[lane] = w0 * st[0] + w1 * st[1] + w2 * st[2] + w3 * st[3];
+          wr[64 + lane] = w0 * d[0] + w1 * d[1] + w2 * d[2] + w3 * d[3];
+          wr[128 + lane] = omtz * (st[2] - st[0]) + tz * (st[3] - st[1]);
+          wr[192 + lane] = omta * (st[1] - st[0]) + ta * (st[3] - st[2]);
           __builtin_amdgcn_wave_barrier();
-          const int i = min(max(k - n0, 0), 62);          // the clamp only guards the LDS rows
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            pv[c] = wr[c * 64 + i];
-            qv[c] = wr[c * 64 + i + 1];
-          }
+          const int i = k - n0;
+          const float s0 = wr[i], dS = wr[64 + i];
+          const float a0 = wr[128 + i], a1 = wr[128 + i + 1];
+          const float z0 = wr[192 + i], z1 = wr[192 + i + 1];
           __builtin_amdgcn_wave_barrier();
-          bwd_bin(w0, w1, w2, w3, ta, tz, tau, gj, lamf, pv, qv, sm, sa, sz, y);
-        } else {
-          // bins whose node lies outside the SSP grid carry no gradient (a select, not a store
-          // under a branch); the last node takes the last interval with t = 1
-          const bool ok = (k >= 0) & ((k < nl - 1) | ((k == nl - 1) & (tau == 0.f)));
-          const float g = ok ? gj : 0.f;
-          const int kk = min(max(k, 0), nl - 2);
-          const float t = (k > kk) ? 1.f : tau;
-          const uint32_t b = (uint32_t)(row + kk) * 4u;
-          const uint32_t oc[4] = {0u, (uint32_t)o1 * 4u, (uint32_t)o2 * 4u, (uint32_t)o3 * 4u};
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            pv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, b + oc[c], 0, 0));
-            qv[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, b + oc[c] + 4u, 0, 0));
-          }
-          g_next = ld_grad(rg, jc);
-          bwd_bin(w0, w1, w2, w3, ta, tz, t, g, lamf, pv, qv, sm, sa, sz, y);
+          sm = fmaf(gj, fmaf(tau, dS, s0), sm);
+          sa = fmaf(gj, fmaf(tau, a1 - a0, a0), sa);
+          sz = fmaf(gj, fmaf(tau, z1 - z0, z0), sz);
+          y = fmaf(gj * lamf, dS, y);
         }
+      }
+      // windows after the run, or every window of a particle that does not fit
+      for (; jw < J.n_tel; jw += kCubeWaveBins, Qx += step_x, lamd += step_l) {
+        float lamf, tau, gj;
+        int k, n0;
+        locate(lamf, tau, k, n0, gj);
+        general(lamf, tau, k, gj);
       }
       const double Sm = wave_sum(sm), Sa = wave_sum(sa), Sz = wave_sum(sz), Y = wave_sum(y);
       if (lane == 0) {

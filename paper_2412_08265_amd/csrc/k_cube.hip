@@ -7,15 +7,19 @@
 //             with several chunks get partial-sum slots.
 //   k_vbound  streams the particles in input order: the job's largest Doppler slope and window
 //             flag for the cube kernel, and a packed 16-byte (mass, age, [M/H], v_los) record each.
-//   k_prep    one thread per sorted in-field particle: gathers the packed record through perm,
-//             finds the SSP cell, and writes a 32-byte record {flux row, Doppler slope g,
-//             4 corner weights, window flag} in spaxel order.
+//   k_prep_sorted  one block per kPrepBlock sorted in-field particles: orders them by (spaxel,
+//             SSP cell) in LDS, then for each position gathers the particle's packed record
+//             through perm, finds its SSP cell and writes a 32-byte record {flux row, Doppler
+//             slope g, 4 corner weights, window flag}; consecutive particles of a spaxel then
+//             share template rows (L1 hits in the cube kernel and the adjoint).
 //   k_cube    one block per (lambda tile of kCubeTL bins, chunk); each wave owns 62 consecutive
 //             telescope bins and walks the chunk's particles, kCubeGroup at a time:
 //               stage    lane l computes the particle's bilinear spectrum at SSP node n0 + l,
 //                        S = sum_c a_c T_c[n0 + l] (four coalesced row loads from the template
-//                        slice in L2), into the wave's own 64-float LDS slot; n0 is lane 0's
-//                        shifted node index, so the slot covers both taps of all 62 bins;
+//                        slice in L1/L2; in the interior path global loads whose row base sits
+//                        in scalar registers, so no VALU work forms their addresses), into the
+//                        wave's own 64-float LDS slot; n0 is lane 0's shifted node index, so the
+//                        slot covers both taps of all 62 bins;
 //               resample each lane reads (S[k - n0], S[k - n0 + 1]) with one ds_read2 and
 //                        accumulates the linear interpolant in registers (no atomics).
 //             Slots are private to a wave, so no block barrier is needed; particle records
@@ -28,7 +32,8 @@
 //   k_cube_bin  bin-mean jobs in place of k_cube: the same work items on tiles of kBinTL bins,
 //             each bin's value the integral of the shifted spectrum over the bin.
 //   k_combine sums a multi-chunk spaxel's partial spectra in chunk order (deterministic).
-// The adjoint's records come from k_pack (the packing half of k_vbound) and k_prep in mode 1.
+// The adjoint's records come from k_pack (the packing half of k_vbound) and k_prep_sorted in
+// mode 1 (plain bilinear weights, the particle's spaxel and input index).
 //
 // Resampling index: for bin centre lam_j the node index of the rest-frame wavelength is
 //   q = (lam_j/((1+z)(1+beta)) - lam0)/dlam = Q_j - lam_j * g,
@@ -36,8 +41,9 @@
 // Q_j is formed in FP64 per lane (split_index, with the job's reciprocals of 1+z and dlam) and
 // split into an integer and an FP32 fraction; only the small Doppler term lam_j*g is FP32, so q
 // carries an absolute error of ~1e-6 nodes instead of the ~1e-3 that an FP32 lam/(1+beta) would
-// give at 9000 A. The integer part k = floor(q) is the same FP32 decision in every kernel
-// (forward and adjoint).
+// give at 9000 A. The integer part k = floor(q) is taken in FP32 from this form; the adjoint
+// carries the same rest index in 40-bit fixed point instead (another rounding of the same q). A q
+// within the index error of a node may land on either side of it, and both are correct results.
 #include "rubix_internal.h"
 
 namespace rubix {
@@ -61,7 +67,7 @@ __device__ __forceinline__ double clamp01(double t) { return fmin(1.0, fmax(0.0,
 // Doppler slope g of the node index (FP32, from FP64) and whether the node span of one wave's
 // kCubeWaveBins bins fits its 64-node window: q advances by bin_slope/(1+beta) nodes per bin, so
 // when 61 steps stay below 61.9 nodes the node indices of 62 consecutive bins span at most 63
-// nodes (0.1 node of margin is far above the FP32 error of q). k_prep and k_vbound both use it.
+// nodes (0.1 node of margin is far above the FP32 error of q). k_prep_sorted and k_vbound both use it.
 // On log grids the Doppler term is the constant index shift ln(1+beta)/dln and the node step per
 // bin does not depend on beta.
 __device__ __forceinline__ void doppler_slope(const JobDev &J, const SspDev &S, double v, float &g,
@@ -80,64 +86,57 @@ __device__ __forceinline__ void doppler_slope(const JobDev &J, const SspDev &S, 
 }
 
 // mode 0: forward weights flux_scale*m*J*w_c; mode 1: plain bilinear weights w_c.
-__global__ __launch_bounds__(kPrepThreads) void k_prep(const Table *__restrict__ T, int mode) {
-  const SspDev &S = T->h.ssp;
-  const JobDev *jobs = table_jobs(T);
-  for (int64_t vb = blockIdx.x; vb < T->h.total[K_PREP]; vb += gridDim.x) {
-    const int jj = find_job(T, K_PREP, vb);
-    const JobDev &J = jobs[jj];
-    const int64_t i = (vb - J.vb_start[K_PREP]) * kPrepThreads + threadIdx.x;
-    const int n_in = J.seg_off[J.n_s];
-    if (i >= n_in) continue;
-    const int j = J.perm[i];
-    // one 16-byte gather of the particle's (mass, age, [M/H], vlos), packed in input order by
-    // k_vbound (forward) or k_pack (backward)
-    const float4 pr = J.pay[j];
-    const double m = pr.x, age = pr.y, met = pr.z, v = pr.w;
-    const int ja = cell_of(S.age_thr, S.n_age, age);
-    double ta;
-    if (!(age > S.age_thr[0])) ta = 0.0;
-    else if (age >= S.age_thr[S.n_age - 1]) ta = 1.0;
-    else ta = clamp01((log10(age) - S.log_age[ja]) / (S.log_age[ja + 1] - S.log_age[ja]));
-    const int jz = cell_of(S.met, S.n_met, met);
-    double tz;
-    if (!(met > S.met[0])) tz = 0.0;
-    else if (met >= S.met[S.n_met - 1]) tz = 1.0;
-    else tz = clamp01((met - S.met[jz]) / (S.met[jz + 1] - S.met[jz]));
-    const double beta = v / kCkms;
-    const double opz = 1.0 + J.z_sys;
-    const double jac = 1.0 / (opz * (1.0 + beta));
-    // forward weights: flux_scale m J for bin-centre sampling; for the bin mean the Jacobian
-    // cancels against the change of variable lambda -> node index, leaving dlam_ssp/dlam_tel
-    // a line-of-sight velocity that is not finite: the particle adds nothing (zero weights; the
-    // Jacobian would be NaN) and its Doppler slope is set to 0 below, so every kernel that reads
-    // the record sees finite indices and no NaN reaches a bin
-    const bool moving = isfinite(v);
-    const double scale = !moving ? 0.0
-                         : mode != 0 ? 1.0
-                         : J.resample ? J.flux_scale * m * J.bin_scale : J.flux_scale * m * jac;
-    PrepRec r;
-    r.row = (ja * S.n_met + jz) * S.n_lam;
-    bool fits;
-    doppler_slope(J, S, v, r.g, fits);
-    if (!moving) r.g = 0.f;
-    r.a[0] = (float)(scale * (1.0 - ta) * (1.0 - tz));
-    r.a[1] = (float)(scale * (1.0 - ta) * tz);
-    r.a[2] = (float)(scale * ta * (1.0 - tz));
-    r.a[3] = (float)(scale * ta * tz);
-    r.spaxel = mode == 0 ? -1 : J.key[j];
-    if (!fits) r.row = ~r.row;
-    r.pad = mode == 0 ? 0 : j;     // backward: the particle's input index (where its dots go)
-    J.prep[i] = r;
-  }
+// The record of sorted particle i (mode 0: forward weights flux_scale*m*J*w_c, or
+// flux_scale*m*dlam_ssp/dlam_tel*w_c for the bin mean; mode 1: plain bilinear weights w_c).
+__device__ __forceinline__ PrepRec make_record(const JobDev &J, const SspDev &S, int64_t i,
+                                               int mode) {
+  const int j = J.perm[i];
+  // one 16-byte gather of the particle's (mass, age, [M/H], vlos), packed in input order by
+  // k_vbound (forward) or k_pack (backward)
+  const float4 pr = J.pay[j];
+  const double m = pr.x, age = pr.y, met = pr.z, v = pr.w;
+  const int ja = cell_of(S.age_thr, S.n_age, age);
+  double ta;
+  if (!(age > S.age_thr[0])) ta = 0.0;
+  else if (age >= S.age_thr[S.n_age - 1]) ta = 1.0;
+  else ta = clamp01((log10(age) - S.log_age[ja]) / (S.log_age[ja + 1] - S.log_age[ja]));
+  const int jz = cell_of(S.met, S.n_met, met);
+  double tz;
+  if (!(met > S.met[0])) tz = 0.0;
+  else if (met >= S.met[S.n_met - 1]) tz = 1.0;
+  else tz = clamp01((met - S.met[jz]) / (S.met[jz + 1] - S.met[jz]));
+  const double beta = v / kCkms;
+  const double opz = 1.0 + J.z_sys;
+  const double jac = 1.0 / (opz * (1.0 + beta));
+  // a line-of-sight velocity that is not finite: the particle adds nothing (zero weights; the
+  // Jacobian would be NaN) and its Doppler slope is set to 0 below, so every kernel that reads
+  // the record sees finite indices and no NaN reaches a bin
+  const bool moving = isfinite(v);
+  const double scale = !moving ? 0.0
+                       : mode != 0 ? 1.0
+                       : J.resample ? J.flux_scale * m * J.bin_scale : J.flux_scale * m * jac;
+  PrepRec r;
+  r.row = (ja * S.n_met + jz) * S.n_lam;
+  bool fits;
+  doppler_slope(J, S, v, r.g, fits);
+  if (!moving) r.g = 0.f;
+  r.a[0] = (float)(scale * (1.0 - ta) * (1.0 - tz));
+  r.a[1] = (float)(scale * (1.0 - ta) * tz);
+  r.a[2] = (float)(scale * ta * (1.0 - tz));
+  r.a[3] = (float)(scale * ta * tz);
+  r.spaxel = mode == 0 ? -1 : J.key[j];
+  if (!fits) r.row = ~r.row;
+  r.pad = mode == 0 ? 0 : j;     // backward: the particle's input index (where its dots go)
+  return r;
 }
 
+
 // Per job, over all its particles in input order: the largest |g| of a particle whose span fits,
-// and whether any particle's span does not fit (doppler_slope, exactly as k_prep decides). The
-// cube kernel uses them to find lambda tiles where every particle's window lies inside the SSP
-// grid. One atomic per work item; k_chunks zeroes counts[2..3] before this kernel runs. The same
-// pass packs each particle's (mass, age, [M/H], vlos) into one 16-byte record, so that k_prep
-// gathers one record per sorted particle instead of four scattered floats.
+// and whether any particle's span does not fit (doppler_slope, exactly as k_prep_sorted
+// decides). The cube kernel uses them to find lambda tiles where every particle's window lies
+// inside the SSP grid. One atomic per work item; k_chunks zeroes counts[2..3] before this kernel
+// runs. The same pass packs each particle's (mass, age, [M/H], vlos) into one 16-byte record, so
+// that k_prep_sorted gathers one record per sorted particle instead of four scattered floats.
 __global__ __launch_bounds__(256) void k_vbound(const Table *__restrict__ T) {
   __shared__ int s_g[4], s_f[4];
   const SspDev &S = T->h.ssp;
@@ -236,7 +235,6 @@ __global__ __launch_bounds__(1024) void k_chunks(const Table *__restrict__ T) {
   }
 }
 
-typedef __attribute__((address_space(1))) const float GFloat;     // global memory
 
 // The template grid is read through a buffer resource: one uniform descriptor and a 32-bit byte
 // offset per lane; offsets past the end of the grid read 0 instead of faulting. The per-particle
@@ -254,6 +252,59 @@ __device__ __forceinline__ float ldf(__amdgpu_buffer_rsrc_t rs, uint32_t voff, u
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + off, 0, 0));
 }
 typedef __attribute__((address_space(4))) const int CInt;         // read-only: scalar loads
+
+// Particle records in blocks of kPrepBlock sorted in-field particles, each block ordered by
+// (spaxel, SSP cell) (stable), so that the particles a wave walks in turn mostly share their four
+// template rows: consecutive row loads then hit in the vector L1. Sorting inside a block keeps
+// every spaxel's particles at the positions its segment held, so every chunk of the cube kernel
+// still sums particles of one spaxel and every spaxel keeps its particles; only the order of the
+// FP32 sums changes. Keys (spaxel rank in the block, cell, position) are bitonic-sorted in LDS;
+// each record is then built for its sorted position and written once.
+__global__ __launch_bounds__(256) void k_prep_sorted(const Table *__restrict__ T, int mode) {
+  __shared__ uint64_t key[kPrepBlock];
+  const SspDev &S = T->h.ssp;
+  const JobDev *jobs = table_jobs(T);
+  const int t = threadIdx.x;
+  for (int64_t vb = blockIdx.x; vb < T->h.total[K_PREP]; vb += gridDim.x) {
+    const int jj = find_job(T, K_PREP, vb);
+    const JobDev &J = jobs[jj];
+    const int n_in = J.seg_off[J.n_s];
+    const int64_t p0 = (vb - J.vb_start[K_PREP]) * kPrepBlock;
+    if (p0 >= n_in) continue;
+    const int n = (int)min((int64_t)kPrepBlock, (int64_t)n_in - p0);
+    const int s0 = J.key[J.perm[p0]];
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = t; i < np; i += 256) {
+      uint64_t k = ~0ull;
+      if (i < n) {
+        const int j = J.perm[p0 + i];
+        const float4 pr = J.pay[j];
+        const int ja = cell_of(S.age_thr, S.n_age, (double)pr.y);
+        const int jz = cell_of(S.met, S.n_met, (double)pr.z);
+        k = ((uint64_t)(J.key[j] - s0) << 32) | ((uint64_t)(ja * S.n_met + jz) << 12) |
+            (uint64_t)i;
+      }
+      key[i] = k;
+    }
+    __syncthreads();
+    for (int size = 2; size <= np; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int q = t; q < (np >> 1); q += 256) {
+          const int lo = 2 * q - (q & (stride - 1));
+          const int hi = lo + stride;
+          const uint64_t a = key[lo], b = key[hi];
+          if ((a > b) == ((lo & size) == 0)) { key[lo] = b; key[hi] = a; }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = t; i < n; i += 256)
+      J.prep[p0 + i] = make_record(J, S, p0 + (int64_t)(key[i] & 4095u), mode);
+    __syncthreads();   // key[] is reused by the block's next item
+  }
+}
+
 
 // A particle record through the scalar cache (the records are read-only in this kernel).
 __device__ __forceinline__ PrepRec load_rec(const PrepRec *p) {
@@ -329,6 +380,7 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
   const __amdgpu_buffer_rsrc_t rs = flux_rsrc(S);
+  const float *__restrict__ flux = S.flux;
   const int nl = S.n_lam;
   const int o1 = nl, o2 = S.n_met * nl, o3 = o2 + nl;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -373,6 +425,7 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
       const int hi = __builtin_amdgcn_readfirstlane(qi0 + floor_i32(fmaf(lam0, gm, qf0)));
       interior = lo >= 0 && hi + 63 <= nl - 1;
     }
+    uint32_t lo[4] = {lb[0], lb[1], lb[2], lb[3]};
     if (interior) {
       // blocks of groups that end on the partial-sum boundaries (every kCubeSubsum particles of
       // the chunk the partial sum moves into the total)
@@ -380,6 +433,9 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
         const int pe = p + min(kCubeSubsum - since, (ch.p1 - p) / kCubeGroup * kCubeGroup);
         since += pe - p;
         for (; p < pe; p += kCubeGroup) {
+          // the lane offsets pass through an empty asm each iteration, so their widening to
+          // 64 bits stays next to the loads and the loads take the scalar-base form
+          asm volatile("" : "+v"(lo[0]), "+v"(lo[1]), "+v"(lo[2]), "+v"(lo[3]));
           PrepRec r[kCubeGroup];
 #pragma unroll
           for (int u = 0; u < kCubeGroup; ++u) r[u] = load_rec(prep + p + u);
@@ -397,8 +453,11 @@ __global__ __launch_bounds__(kCubeThreads) void k_cube(const Table *__restrict__
           float v[kCubeGroup][4];
 #pragma unroll
           for (int u = 0; u < kCubeGroup; ++u) {
+            // in range here: global loads with the window's row base in scalar registers and the
+            // lane's 32-bit offset in a VGPR (no per-particle VALU add)
+            const GChar *wb = (const GChar *)flux + so[u];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) v[u][c] = ldf(rs, lb[c], so[u]);
+            for (int c = 0; c < 4; ++c) v[u][c] = *(const GFloat *)(wb + lo[c]);
           }
 #pragma unroll
           for (int u = 0; u < kCubeGroup; ++u) {
@@ -677,7 +736,7 @@ hipError_t launch_cube(const Table *dt, const TableHeader &h, int cap, hipStream
   if ((g = grid_for(h.total[K_VB], cap)))
     hipLaunchKernelGGL(k_vbound, dim3(g), dim3(256), 0, s, dt);
   if ((g = grid_for(h.total[K_PREP], cap)))
-    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, 0);
+    hipLaunchKernelGGL(k_prep_sorted, dim3(g), dim3(256), 0, s, dt, 0);
   // the summation kernels (bin-centre and bin-mean jobs), timed together when requested
   const bool timed = t_cube_events[0] && t_cube_events[1];
   if (timed) (void)hipEventRecord(t_cube_events[0], s);
@@ -704,12 +763,12 @@ hipError_t launch_prep_backward(const Table *dt, const TableHeader &h, int cap, 
   if ((g = grid_for(h.total[K_VB], cap)))
     hipLaunchKernelGGL(k_pack, dim3(g), dim3(256), 0, s, dt);
   if ((g = grid_for(h.total[K_PREP], cap)))
-    hipLaunchKernelGGL(k_prep, dim3(g), dim3(kPrepThreads), 0, s, dt, 1);
+    hipLaunchKernelGGL(k_prep_sorted, dim3(g), dim3(256), 0, s, dt, 1);
   return hipGetLastError();
 }
 
 int cube_kernel_kind(const void *f) {
-  if (f == (const void *)k_prep) return K_PREP;
+  if (f == (const void *)k_prep_sorted) return K_PREP;
   if (f == (const void *)k_chunks) return K_CHUNK;
   if (f == (const void *)k_vbound) return K_VB;
   if (f == (const void *)k_cube_bin<false> || f == (const void *)k_cube_bin<true>) return K_CUBEB;

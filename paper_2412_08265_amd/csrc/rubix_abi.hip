@@ -373,6 +373,17 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
     }
     d.inv_opz = 1.0 / (1.0 + j.z_sys);
     d.inv_ds = ssp ? 1.0 / ssp->lam.step : 1.0;
+    {
+      // fixed-point rest index: Q_j = Q_0 + j r exactly as the FP64 form groups it for bin 0,
+      // the slope r per bin; 40 fraction bits keep j r within 2e-9 node over 2^22 bins
+      double q0, r;
+      if (ssp && j.tel.log_spaced) { q0 = d.q_off; r = d.q_ratio; }
+      else if (ssp) { q0 = (j.tel.start * d.inv_opz - ssp->lam.start) * d.inv_ds;
+                      r = j.tel.step * d.inv_opz * d.inv_ds; }
+      else { q0 = 0.0; r = 0.0; }
+      d.q0x = (int64_t)llround(q0 * 1099511627776.0);
+      d.qrx = (int64_t)llround(r * 1099511627776.0);
+    }
     // a telescope grid coarser than the SSP grid needs node windows wider than a wave; such jobs
     // gather their two taps per corner directly from the template grid
     d.cube_direct = d.bin_slope > 1.0 ? 1 : 0;
@@ -439,7 +450,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
         /*K_ROT*/ z.n_sort_tiles,
         /*K_SCAN*/ z.n > 0 ? 256 : 0,
         /*K_SEG*/ cdiv(z.n_s + 1, 256),
-        /*K_PREP*/ cdiv(z.n, kPrepThreads),
+        /*K_PREP*/ cdiv(z.n, kPrepBlock),
         /*K_CHUNK*/ 1,
         /*K_CUBE*/ j.resample ? 0 : (int64_t)z.n_tiles * z.n_chunk_ub,
         /*K_COMB*/ (int64_t)z.n_tiles * z.n_comb_ub,
@@ -828,8 +839,9 @@ int rubix_graph_create(const void *dev_table, int max_jobs, int max_psf_radius,
     g->kinds.push_back(kind);
   }
   if (e != hipSuccess) { graph_free(g); return device_status(e, "graph kernel nodes"); }
-  // rotate/bin: 3 per sort pass + rotate + segment offsets; cube: chunks, bounds, prep, the
-  // bin-centre sum, the bin-mean sum's two instances (linear and log grids), combine; PSF/LSF: 4
+  // rotate/bin: 3 per sort pass + rotate + segment offsets; cube: chunks, bounds, cell-ordered
+  // prep, the bin-centre sum, the bin-mean sum's two instances (linear and log grids), combine;
+  // PSF/LSF: 4
   const size_t expect = 3u * max_sort_passes + 2 + 7 + 4;
   if (g->nodes.size() != expect) {
     const size_t got = g->nodes.size();

@@ -17,6 +17,7 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per sort work item
 constexpr int kPrepThreads = 256;
+constexpr int kPrepBlock = 1024;    // sorted particles per record block (ordered by spaxel, SSP cell)
 constexpr int kCubeThreads = 256;   // threads per cube work item (4 waves)
 constexpr int kCubeWaveBins = 62;   // telescope bins per wave; its 64 lanes stage a 64-node window
 constexpr int kCubeTL = 4 * kCubeWaveBins;  // telescope bins per cube tile
@@ -38,7 +39,7 @@ enum Kind : int {
   K_ROT = 0,   // rotate/key and radix-sort tiles (per kSortTile particles)
   K_SCAN,      // per (job, digit)
   K_SEG,       // seg_off, per 256 spaxels
-  K_PREP,      // per kPrepThreads sorted particles
+  K_PREP,      // per kPrepBlock sorted particles
   K_CHUNK,     // one per job
   K_CUBE,      // per (lambda tile, chunk slot)
   K_COMB,      // per (lambda tile, combine slot)
@@ -79,6 +80,9 @@ struct CombRec {
   int32_t s, first_slot, n_slots, pad;
 };
 
+typedef __attribute__((address_space(1))) const float GFloat;     // global memory
+typedef __attribute__((address_space(1))) const char GChar;
+
 struct SspDev {
   const float *flux;
   int32_t n_age, n_met, n_lam, log_lambda;   // log_lambda: nodes lam_start * exp(k lam_step)
@@ -109,6 +113,9 @@ struct JobDev {
   double bin_scale;             // bin mean: dlam_ssp / dlam_tel (linear grids), 1 (log grids)
   double bin_slope;                                  // d(node index)/d(bin) at rest
   double inv_opz, inv_ds;  // 1/(1+z_sys) and 1/dlam_ssp (linear grids: the rest-frame index)
+  // rest-frame node index at zero velocity of bin centre j in 40-bit fixed point:
+  // Q_j * 2^40 = q0x + j * qrx (linear and log grids), for the adjoint's per-window split
+  int64_t q0x, qrx;
   int32_t n_chunk_ub, n_comb_ub, lsf_r, psf_r;
   int32_t n_psf_tiles, n_psf_seg_y, n_psf_seg_x, n_fin_blocks;
   // outputs
@@ -212,8 +219,8 @@ __device__ __forceinline__ double rest_q(const JobDev &J, const SspDev &S, doubl
 // Rest-frame node index of telescope bin jb's centre, split into an integer and an FP32
 // fraction, and the factor lamf that multiplies the particle's Doppler term g (the particle's
 // index is qi + qf - lamf g): the bin wavelength on linear grids; 1 on log grids, where
-// Q = q_off + jb q_ratio. The forward sum and the adjoint both take it from here, so they put
-// every bin in the same node interval.
+// Q = q_off + jb q_ratio. The forward sums and the bin-mean edges take it from here; the adjoint
+// walks the bins with the fixed-point form of the same rest index (q0x, qrx in JobDev).
 __device__ __forceinline__ void split_index(const JobDev &J, const SspDev &S, int jb, int &qi,
                                             float &qf, float &lamf) {
   if (J.log_lambda) {
