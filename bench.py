@@ -33,7 +33,7 @@ CUBE_GATHER_BYTES_PER_UNIT = 16.0 * 64.0 / 62.0
 # aggregate L2 read rate: 8 XCDs x 16 channels x 128 B/clk x 2.4 GHz
 PEAK_L2_TBS = 8 * 16 * 128 * 2.4e9 / 1e12
 ROTBIN_BYTES_PER_PARTICLE = 100  # rotate + key + vlos + two radix passes + offsets (design figure)
-PSF_BYTES_PER_VOXEL = 24       # three 1-D passes, each reads and writes the cube once (FP32)
+PSF_BYTES_PER_VOXEL = 8        # PSF+LSF: the FP32 cube read once and written once
 
 
 def err(msg):

@@ -10,6 +10,14 @@
 //   k_psf<A> (line, 64-spaxel segment, 64-bin tile): 64 lanes span lambda (every load of a
 //            neighbouring spaxel is a contiguous 256-byte row segment); wave w owns 16 output
 //            positions of the segment, four at a time.
+//   k_psf_lsf_fused (lambda tile of kFuseL bins, x segment of kFuseX spaxels): all three filters
+//            in one pass that reads the cube once and writes it once. The work item walks the y
+//            rows in order; per row it stages kFuseX + 2 kFuseR x positions by kFuseL + 2 r_lsf
+//            bins in LDS, filters them along lambda and then along x, and adds the row into a
+//            shift register of 2 kFuseR partial output rows per lane (the y filter), storing the
+//            output row that the new row completes. The next row's loads are in flight while the
+//            current row is filtered. Jobs whose radii exceed the fused bounds, and jobs with an
+//            LSF only, run the 1-D passes.
 // The normalised FP32 weights come with the job table (computed on the host in FP64), padded with
 // kWPad zeros on both sides so a blocked filter needs no branch at the ends of its window.
 #include "rubix_internal.h"
@@ -171,6 +179,174 @@ __global__ __launch_bounds__(256) void k_psf(const Table *__restrict__ T) {
   }
 }
 
+// Bijection on [0, total) that hands each XCD a contiguous run of work items: blocks are dispatched
+// to the XCDs round robin by index, so block b runs on XCD b mod 8, and neighbouring tiles (which
+// share halo rows) then meet in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_run(int64_t vb, int64_t total) {
+  const int64_t full = total & ~int64_t(7);
+  if (vb >= full) return vb;
+  return (vb & 7) * (full >> 3) + (vb >> 3);
+}
+
+// Weight of offset m - kFuseR (m = 0 .. 2 kFuseR) of a filter of radius r <= kFuseR; zero beyond r.
+__device__ __forceinline__ float fuse_weight(const float *w, int r, int m) {
+  const int o = m - kFuseR;
+  return (o >= -r && o <= r) ? w[kWPad + o + r] : 0.f;
+}
+
+// LDS copy of the LSF weights: WL[4 + m] = weight of offset m - r (m = 0 .. 2r), zero for the
+// other m in -4 .. 2 kFuseLsfR + 7, so a block of four outputs reads them as aligned float4s
+constexpr int kFuseWL = 2 * kFuseLsfR + 16;
+
+__global__ __launch_bounds__(256) void k_psf_lsf_fused(const Table *__restrict__ T) {
+  __shared__ __attribute__((aligned(16))) float S[kFuseRows * kFuseW];   // staged input row
+  __shared__ __attribute__((aligned(16))) float M[kFuseRows * kFuseL];   // after the LSF
+  __shared__ __attribute__((aligned(16))) float WL[kFuseWL];
+  const JobDev *jobs = table_jobs(T);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int64_t total = T->h.total[K_FUSE];
+  for (int64_t vb0 = blockIdx.x; vb0 < total; vb0 += gridDim.x) {
+    const int64_t vb = xcd_run(vb0, total);
+    const int jj = find_job(T, K_FUSE, vb);
+    const JobDev &J = jobs[jj];
+    const int nt = J.n_tel, nx = J.nx, ny = J.ny;
+    const int nxs = (nx + kFuseX - 1) / kFuseX;
+    const int64_t local = vb - J.vb_start[K_FUSE];
+    const int lt = (int)(local / nxs);
+    const int x0 = (int)(local - (int64_t)lt * nxs) * kFuseX;
+    const int l0 = lt * kFuseL;
+    const int rl = J.lsf_r;
+    const int wc = kFuseL + 2 * rl + 4;          // staged bins per x position (+ 4: see k_lsf)
+    const int64_t plane = (int64_t)nx * nt;      // floats per y row of the cube
+    for (int i = tid; i < kFuseWL; i += 256) {
+      const int m = i - 4;
+      WL[i] = (m >= 0 && m <= 2 * rl) ? J.lsf_w[kWPad + m] : 0.f;
+    }
+    // staging: wave w stages x positions x0 - kFuseR + w + 4 i (i = 0..7), lane l the bins
+    // l0 - rl + l and, for l + 64 < wc, l0 - rl + l + 64; the bin part of each offset is the
+    // lane's (clamped to the row, a mask zeroes bins outside it), the x part is wave-uniform
+    uint32_t loff[2];
+    bool lin[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = lane + 64 * h;
+      const int g = l0 - rl + c;
+      lin[h] = c < wc && g >= 0 && g < nt;
+      loff[h] = 4u * (uint32_t)min(max(g, 0), nt - 1);
+    }
+    const bool second = lane + 64 < wc;
+    // the x and y filters padded to radius kFuseR
+    float wpx[2 * kFuseR + 1];
+#pragma unroll
+    for (int m = 0; m <= 2 * kFuseR; ++m) wpx[m] = fuse_weight(J.psf_w, J.psf_r, m);
+    const int nq = (2 * rl + 4 + 3) / 4;
+    const float *__restrict__ src = J.fuse_src;
+    float *__restrict__ dst = J.fuse_dst;
+    // outputs of this thread: x = x0 + 4 w + i (i = 0..3), bin l0 + lane
+    const int lb = l0 + lane;
+    const bool lok = lb < nt;
+    // P[i][k]: partial sum of output row y - kFuseR + k before row y is added
+    float P[4][2 * kFuseR];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int k = 0; k < 2 * kFuseR; ++k) P[i][k] = 0.f;
+    float pf[kFuseRows / 4][2];
+    auto load_row = [&](int y) {
+      const GChar *rowp = (const GChar *)(src + (int64_t)y * plane);
+#pragma unroll
+      for (int i = 0; i < kFuseRows / 4; ++i) {
+        const int gx = min(max(x0 - kFuseR + w + 4 * i, 0), nx - 1);
+        const GChar *xp = rowp + 4 * (int64_t)gx * nt;
+        uint32_t o0 = loff[0], o1 = loff[1];
+        asm volatile("" : "+v"(o0), "+v"(o1));
+        pf[i][0] = *(const GFloat *)(xp + o0);
+        pf[i][1] = second ? *(const GFloat *)(xp + o1) : 0.f;
+      }
+    };
+    if (ny > 0) load_row(0);
+    for (int y = 0; y < ny + kFuseR; ++y) {
+      float t[4] = {0.f, 0.f, 0.f, 0.f};
+      if (y < ny) {                                                   // block-uniform
+#pragma unroll
+        for (int i = 0; i < kFuseRows / 4; ++i) {
+          const int gx = x0 - kFuseR + w + 4 * i;
+          const bool xin = gx >= 0 && gx < nx;
+          float *srow = S + (w + 4 * i) * kFuseW + lane;
+          srow[0] = (xin && lin[0]) ? pf[i][0] : 0.f;
+          if (lane < kFuseW - 64) srow[64] = (xin && lin[1]) ? pf[i][1] : 0.f;
+        }
+        if (y + 1 < ny) load_row(y + 1);
+        __syncthreads();
+        // LSF along lambda for staged x positions xx = tid/16 and tid/16 + 16, bins 4 (tid % 16)
+        // + 0..3: out_i = sum_o wl[o - i] S[xx][b4 + o], the weights read from LDS as float4s
+        {
+          const int b4 = 4 * (tid & 15);
+          const float *r0 = S + (tid >> 4) * kFuseW + b4;
+          const float *r1 = r0 + 16 * kFuseW;
+          float a[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+          float4 wa = *reinterpret_cast<const float4 *>(WL);
+          for (int m = 0; m < nq; ++m) {
+            const float4 wb = *reinterpret_cast<const float4 *>(WL + 4 * m + 4);
+            const float4 xs[2] = {*reinterpret_cast<const float4 *>(r0 + 4 * m),
+                                  *reinterpret_cast<const float4 *>(r1 + 4 * m)};
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+              const float4 x = xs[g];
+              // wa = wl[o-4 .. o-1], wb = wl[o .. o+3] with o = 4m
+              a[g][0] = fmaf(wb.x, x.x, a[g][0]);
+              a[g][0] = fmaf(wb.y, x.y, a[g][0]);
+              a[g][0] = fmaf(wb.z, x.z, a[g][0]);
+              a[g][0] = fmaf(wb.w, x.w, a[g][0]);
+              a[g][1] = fmaf(wa.w, x.x, a[g][1]);
+              a[g][1] = fmaf(wb.x, x.y, a[g][1]);
+              a[g][1] = fmaf(wb.y, x.z, a[g][1]);
+              a[g][1] = fmaf(wb.z, x.w, a[g][1]);
+              a[g][2] = fmaf(wa.z, x.x, a[g][2]);
+              a[g][2] = fmaf(wa.w, x.y, a[g][2]);
+              a[g][2] = fmaf(wb.x, x.z, a[g][2]);
+              a[g][2] = fmaf(wb.y, x.w, a[g][2]);
+              a[g][3] = fmaf(wa.y, x.x, a[g][3]);
+              a[g][3] = fmaf(wa.z, x.y, a[g][3]);
+              a[g][3] = fmaf(wa.w, x.z, a[g][3]);
+              a[g][3] = fmaf(wb.x, x.w, a[g][3]);
+            }
+            wa = wb;
+          }
+#pragma unroll
+          for (int g = 0; g < 2; ++g)
+            *reinterpret_cast<float4 *>(M + ((tid >> 4) + 16 * g) * kFuseL + b4) =
+                make_float4(a[g][0], a[g][1], a[g][2], a[g][3]);
+        }
+        __syncthreads();
+        // PSF along x: t[i] = sum_m wpx[m] M[4w + i + m][lane]
+#pragma unroll
+        for (int o = 0; o < 2 * kFuseR + 4; ++o) {
+          const float v = M[(4 * w + o) * kFuseL + lane];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (o - i >= 0 && o - i <= 2 * kFuseR) t[i] = fmaf(wpx[o - i], v, t[i]);
+        }
+      }
+      // PSF along y: row y adds wpx[2R - k] t to output row y - R + k; row y - R is then complete
+      const int yo = y - kFuseR;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float done = fmaf(wpx[2 * kFuseR], t[i], P[i][0]);
+        const int x = x0 + 4 * w + i;
+        if (yo >= 0 && x < nx && lok) dst[(int64_t)yo * plane + (int64_t)x * nt + lb] = done;
+#pragma unroll
+        for (int k = 0; k < 2 * kFuseR - 1; ++k)
+          P[i][k] = fmaf(wpx[2 * kFuseR - 1 - k], t[i], P[i][k + 1]);
+        P[i][2 * kFuseR - 1] = wpx[0] * t[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Identity operator (no PSF and no LSF) into a separate output buffer.
 __global__ __launch_bounds__(256) void k_copy(const Table *__restrict__ T) {
   const JobDev *jobs = table_jobs(T);
@@ -202,6 +378,8 @@ hipError_t launch_psf_lsf(const Table *dt, const TableHeader &h, int cap, hipStr
   if ((g = grid_for(h.total[K_PSFX], cap)))
     hipLaunchKernelGGL(k_psf<1>, dim3(g), dim3(256), psf_lds, s, dt);
   if ((g = grid_for(h.total[K_COPY], cap))) hipLaunchKernelGGL(k_copy, dim3(g), dim3(256), 0, s, dt);
+  if ((g = grid_for(h.total[K_FUSE], cap)))
+    hipLaunchKernelGGL(k_psf_lsf_fused, dim3(g), dim3(256), 0, s, dt);
   return hipGetLastError();
 }
 
@@ -210,6 +388,7 @@ int psf_lsf_kernel_kind(const void *f) {
   if (f == (const void *)k_psf<0>) return K_PSFY;
   if (f == (const void *)k_psf<1>) return K_PSFX;
   if (f == (const void *)k_copy) return K_COPY;
+  if (f == (const void *)k_psf_lsf_fused) return K_FUSE;
   return -1;
 }
 

@@ -13,7 +13,7 @@ namespace rubix {
 // ---------------------------------------------------------------------------------------------
 // rotation, spaxel key, line-of-sight velocity
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ void rotate_one(const JobDev &J, int i) {
+__device__ __forceinline__ int32_t rotate_one(const JobDev &J, int i) {
   double x = J.x[i], y = J.y[i], z = J.z[i];
   double vx = J.vx[i], vy = J.vy[i], vz = J.vz[i];
   int32_t key;
@@ -32,19 +32,29 @@ __device__ __forceinline__ void rotate_one(const JobDev &J, int i) {
   }
   J.key[i] = key;
   J.vlos[i] = (float)vl;
+  return key;
 }
 
+// One sort tile per work item; the tile's digit histogram of the first sort pass is counted in
+// LDS on the way (the first pass needs no separate histogram kernel).
 __global__ __launch_bounds__(kSortThreads) void k_rotate(const Table *__restrict__ T) {
+  __shared__ uint32_t h[256];
   const JobDev *jobs = table_jobs(T);
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_ROT]; vb += gridDim.x) {
     const int j = find_job(T, K_ROT, vb);
     const JobDev &J = jobs[j];
-    const int64_t base = (vb - J.vb_start[K_ROT]) * kSortTile;
+    const int tile = (int)(vb - J.vb_start[K_ROT]);
+    const int64_t base = (int64_t)tile * kSortTile;
+    h[threadIdx.x] = 0;
+    __syncthreads();
 #pragma unroll 4
     for (int it = 0; it < kSortItems; ++it) {
       int64_t i = base + it * kSortThreads + threadIdx.x;
-      if (i < J.n) rotate_one(J, (int)i);
+      if (i < J.n) atomicAdd(&h[(uint32_t)rotate_one(J, (int)i) & 255u], 1u);
     }
+    __syncthreads();
+    J.hist[(int64_t)threadIdx.x * J.n_sort_tiles + tile] = h[threadIdx.x];
+    __syncthreads();
   }
 }
 
@@ -146,12 +156,16 @@ __global__ __launch_bounds__(256) void k_scan(const Table *__restrict__ T, int p
   }
 }
 
-// Stable scatter of one tile: 4 waves x 16 rounds x 64 lanes.
+// Stable scatter of one tile: 4 waves x 16 rounds x 64 lanes. The ranks put the tile in digit
+// order in LDS first; the tile is then written out in that order, so the lanes of a store write
+// consecutive positions of a few digit runs instead of 64 scattered ones.
 __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restrict__ T,
                                                           int pass) {
   __shared__ uint32_t wcnt[4][256];
-  __shared__ uint32_t gbase[256];
+  __shared__ uint32_t gdelta[256];
   __shared__ uint32_t scan_lds[256];
+  __shared__ uint32_t sk[kSortTile];
+  __shared__ uint32_t sv[kSortTile];
   const JobDev *jobs = table_jobs(T);
   const int shift = 8 * pass;
   const int t = threadIdx.x;
@@ -169,10 +183,11 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restric
     uint32_t *dst_k = J.kbuf[pass & 1];
     uint32_t *dst_v = last ? reinterpret_cast<uint32_t *>(J.perm) : J.vbuf[pass & 1];
 
-    // global base of each digit for this tile: digit offset + this tile's prefix in the digit
+    // global position of this tile's first key of digit t: digit offset + the tile's prefix in
+    // the digit (thread t owns digit t)
     uint32_t excl;
     block_exclusive_scan_256(J.dtot[t], scan_lds, excl);
-    gbase[t] = excl + J.hist[(int64_t)t * J.n_sort_tiles + tile];
+    const uint32_t gbase = excl + J.hist[(int64_t)t * J.n_sort_tiles + tile];
     wcnt[0][t] = 0; wcnt[1][t] = 0; wcnt[2][t] = 0; wcnt[3][t] = 0;
     __syncthreads();
 
@@ -211,16 +226,20 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restric
       rank[r] = valid ? (c0 + below) : 0xffffffffu;
     }
     __syncthreads();
-    // per-digit exclusive prefix over the 4 waves (thread t owns digit t)
-    {
-      uint32_t run = 0;
+    // digit t: exclusive prefix over the 4 waves, then over the digits of the tile (the tile's
+    // digit-ordered position of each wave's first key of digit t)
+    uint32_t run = 0;
+    uint32_t wpre[4];
 #pragma unroll
-      for (int ww = 0; ww < 4; ++ww) {
-        uint32_t c = wcnt[ww][t];
-        wcnt[ww][t] = run;
-        run += c;
-      }
+    for (int ww = 0; ww < 4; ++ww) {
+      wpre[ww] = run;
+      run += wcnt[ww][t];
     }
+    uint32_t toff;
+    block_exclusive_scan_256(run, scan_lds, toff);
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) wcnt[ww][t] = toff + wpre[ww];
+    gdelta[t] = gbase - toff;
     __syncthreads();
     if (pass == 0) {
 #pragma unroll
@@ -234,9 +253,22 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const Table *__restric
     for (int r = 0; r < kSortItems; ++r) {
       if (rank[r] != 0xffffffffu) {
         const uint32_t d = (keys[r] >> shift) & 255u;
-        const uint32_t pos = gbase[d] + wcnt[w][d] + rank[r];
-        dst_k[pos] = keys[r];
-        dst_v[pos] = vals[r];
+        const uint32_t lpos = wcnt[w][d] + rank[r];
+        sk[lpos] = keys[r];
+        sv[lpos] = vals[r];
+      }
+    }
+    __syncthreads();
+    // the tile in digit order: position q goes to gdelta[digit] + q
+    const int nv = (int)min((int64_t)kSortTile, J.n - tbase);
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+      const int q = r * kSortThreads + t;
+      if (q < nv) {
+        const uint32_t k = sk[q];
+        const uint32_t pos = gdelta[(k >> shift) & 255u] + (uint32_t)q;
+        dst_k[pos] = k;
+        dst_v[pos] = sv[q];
       }
     }
     __syncthreads();
@@ -276,7 +308,8 @@ hipError_t launch_rotate_bin(const Table *dt, const TableHeader &h, int cap, hip
   int g = grid_for(h.total[K_ROT], cap);
   if (g) hipLaunchKernelGGL(k_rotate, dim3(g), dim3(kSortThreads), 0, s, dt);
   for (int p = 0; p < max_passes; ++p) {
-    if (g) hipLaunchKernelGGL(k_hist, dim3(g), dim3(kSortThreads), 0, s, dt, p);
+    // the first pass's histograms come from k_rotate
+    if (g && p > 0) hipLaunchKernelGGL(k_hist, dim3(g), dim3(kSortThreads), 0, s, dt, p);
     int gs = grid_for(h.total[K_SCAN], cap);
     if (gs) hipLaunchKernelGGL(k_scan, dim3(gs), dim3(256), 0, s, dt, p);
     if (g) hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kSortThreads), 0, s, dt, p);

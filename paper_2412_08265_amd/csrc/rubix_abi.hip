@@ -150,6 +150,13 @@ static JobSizes sizes_of(const rubix_job &j) {
   return z;
 }
 
+// The fused PSF+LSF pass takes PSF radii 1..kFuseR, LSF radii up to kFuseLsfR and y rows
+// (nx * n_tel floats) addressed with 32-bit byte offsets.
+static bool fused_psf_lsf(const rubix_job &j, const JobSizes &z) {
+  return z.psf_r >= 1 && z.psf_r <= kFuseR && z.lsf_r <= kFuseLsfR &&
+         (int64_t)j.grid.nx * z.n_tel * 4 < (int64_t(1) << 31);
+}
+
 static bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
 static int validate_ssp(const rubix_ssp *ssp) {
@@ -411,9 +418,14 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
     d.dots = reinterpret_cast<double *>(region + z.o_dots);
     d.ang_part = reinterpret_cast<double *>(region + z.o_ang);
     region += al(psf_only ? z.psf_region : z.region);
-    // PSF/LSF routing: lambda pass, y pass, x pass; the last active pass writes `out`
-    int64_t n_lsf = 0, n_psfy = 0, n_psfx = 0, n_copy = 0;
-    if (pl) {
+    // PSF/LSF routing: one fused pass where the radii and the row size allow it, else a lambda
+    // pass, a y pass and an x pass, the last active one writing `out`
+    int64_t n_lsf = 0, n_psfy = 0, n_psfx = 0, n_copy = 0, n_fuse = 0;
+    if (pl && fused_psf_lsf(j, z)) {
+      d.fuse_src = pl->in[k];
+      d.fuse_dst = pl->out[k];
+      n_fuse = cdiv(z.n_tel, kFuseL) * cdiv(j.grid.nx, kFuseX);
+    } else if (pl) {
       const float *in = pl->in[k];
       float *out = pl->out[k];
       const bool L = z.lsf_r > 0, P = z.psf_r > 0;
@@ -458,6 +470,7 @@ static std::vector<uint8_t> build_table(const rubix_job *jobs, int n_jobs, const
         /*K_PSFY*/ n_psfy,
         /*K_PSFX*/ n_psfx,
         /*K_COPY*/ n_copy,
+        /*K_FUSE*/ n_fuse,
         /*K_BINTAB*/ j.resample ? cdiv(z.n_tel + 1, 256) : 0,
         /*K_BWD*/ j.resample ? 0 : cdiv(z.n, kBwdParticles),
         /*K_FIN*/ z.n_fin_blocks,
@@ -839,10 +852,11 @@ int rubix_graph_create(const void *dev_table, int max_jobs, int max_psf_radius,
     g->kinds.push_back(kind);
   }
   if (e != hipSuccess) { graph_free(g); return device_status(e, "graph kernel nodes"); }
-  // rotate/bin: 3 per sort pass + rotate + segment offsets; cube: chunks, bounds, cell-ordered
+  // rotate/bin: rotate (with the first pass's histograms), a histogram for every later pass,
+  // scan and scatter per pass, segment offsets; cube: chunks, bounds, cell-ordered
   // prep, the bin-centre sum, the bin-mean sum's two instances (linear and log grids), combine;
-  // PSF/LSF: 4
-  const size_t expect = 3u * max_sort_passes + 2 + 7 + 4;
+  // PSF/LSF: the three 1-D passes, the copy and the fused pass
+  const size_t expect = 3u * max_sort_passes + 1 + 7 + 5;
   if (g->nodes.size() != expect) {
     const size_t got = g->nodes.size();
     graph_free(g);

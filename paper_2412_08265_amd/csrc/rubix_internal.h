@@ -31,6 +31,14 @@ constexpr int kWArray = 2 * RUBIX_MAX_RADIUS + 1 + 16;   // padded filter array 
 constexpr int kLsfOut = 2048;       // bins per LSF work item (two runs of 4 per thread)
 constexpr int kPsfLanes = 64;       // bins per PSF work item
 constexpr int kPsfSeg = 64;         // spaxels of a line per PSF work item (16 per wave)
+// fused PSF+LSF pass: a work item owns kFuseX x positions by kFuseL bins and walks every y row;
+// it takes jobs whose PSF radius is 1..kFuseR and whose LSF radius is at most kFuseLsfR
+constexpr int kFuseX = 16;
+constexpr int kFuseL = 64;
+constexpr int kFuseR = 8;
+constexpr int kFuseLsfR = 22;
+constexpr int kFuseRows = kFuseX + 2 * kFuseR;          // staged x positions per row
+constexpr int kFuseW = kFuseL + 2 * kFuseLsfR + 4;      // LDS floats per staged x position
 constexpr int kBwdParticles = 16;   // particles per backward work item (4 per wave)
 constexpr int kFinThreads = 256;
 constexpr int kVbParticles = 16384; // particles per Doppler-bound work item
@@ -47,6 +55,7 @@ enum Kind : int {
   K_PSFY,      // per (x column, y segment, lambda tile)
   K_PSFX,      // per (y row, x segment, lambda tile)
   K_COPY,      // per 64k floats of a cube (identity PSF/LSF)
+  K_FUSE,      // fused PSF+LSF, per (lambda tile of kFuseL bins, x segment of kFuseX)
   K_BINTAB,    // per 256 bin edges of a bin-mean job
   K_BWD,       // per kBwdParticles sorted particles
   K_FIN,       // per kFinThreads sorted particles
@@ -127,6 +136,9 @@ struct JobDev {
   float *pl_dst[3];
   const float *copy_src;
   float *copy_dst;
+  // fused PSF+LSF pass (replaces the three passes where the radii allow it)
+  const float *fuse_src;
+  float *fuse_dst;
   int64_t cube_elems;
   // backward I/O
   const float *grad_raw;

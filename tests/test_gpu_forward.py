@@ -220,6 +220,43 @@ def test_psf_lsf_on_seeded_random_cube():
                           what=f"psf/lsf {ny}x{nx}x{nl} psf={psf} lsf={lsf}")
 
 
+# (ny, nx, n_tel, PSF sigma [spaxels], LSF sigma [bins]): radii int(4 sigma + 0.5) on both sides
+# of the fused pass's bounds (PSF 1..8, LSF 0..22), grids smaller than its tiles and its PSF
+# radius, and grids of several tiles with ragged x and lambda tails
+FUSED_CASES = [(1, 1, 1, 0.3, 0.3), (2, 150, 64, 2.0, 2.16), (7, 17, 65, 1.0, 5.4),
+               (7, 17, 65, 1.0, 5.7), (9, 33, 129, 2.1, 1.0), (9, 33, 129, 2.2, 1.0),
+               (40, 50, 300, 1.5, 0.0), (23, 16, 640, 0.2, 3.0)]
+
+
+@pytest.mark.parametrize("ny,nx,nl,psf,lsf_bins", FUSED_CASES)
+def test_psf_lsf_fused_pass_bounds_and_tails(ny, nx, nl, psf, lsf_bins):
+    """The PSF+LSF operator on a seeded random cube vs the oracle's convolution, for radii inside
+    and just outside the range of the fused pass (the three 1-D passes take the others)."""
+    import torch
+    from paper_2412_08265_amd import ops
+    rng = np.random.default_rng(ny * 1000 + nx + nl)
+    step = 1.25
+    c = rng.normal(size=(ny, nx, nl)).astype(np.float32)
+    obs = ops.Observation((0, 0, 0), nx, ny, 1.0, 5000.0, step, nl, psf, lsf_bins * step)
+    buf = ops.JobBuffers.allocate(0, obs)
+    gal = ops.DeviceGalaxy({f: torch.empty(0, dtype=torch.float32, device="cuda")
+                            for f in ops.FIELDS})
+    job = ops.make_job(gal, obs, buf)
+    ws = ops.workspace(ops.rubix_workspace_size([job]))
+    cin = torch.from_numpy(c).cuda()
+    cout = torch.full_like(cin, float("nan"))
+    log(f"psf/lsf {ny}x{nx}x{nl} psf={psf} lsf={lsf_bins} bins")
+    ops.rubix_psf_lsf([job], [cin], [cout], ws)
+    torch.cuda.synchronize()
+    ssp = synth.cached_ssp(3, 3, 5000.0, step, 10)
+    cfg = O.OracleConfig((0, 0, 0), nx, ny, 1.0, 5000.0, step, nl, ssp.log_age_nodes,
+                         ssp.met_nodes, ssp.lam_start, ssp.lam_step, ssp.flux, psf,
+                         lsf_bins * step)
+    ref = O.psf_lsf(c.reshape(ny * nx, nl).astype(np.float64), cfg)
+    assert_cube_close(cout.cpu().numpy().reshape(ny * nx, nl), ref, tol=2e-6,
+                      what=f"psf/lsf {ny}x{nx}x{nl} psf={psf} lsf={lsf_bins} bins")
+
+
 def test_batch_equals_single_calls():
     """Jobs batched into one call give bitwise the results of separate calls."""
     import torch
