@@ -10,6 +10,8 @@
 // derivatives are formed per bin from differences of the FP32 template values at each node
 // (exact or nearly so) before they meet G, so no sum is a difference of nearly equal sums.
 //
+#include <type_traits>
+
 #include "rubix_internal.h"
 
 namespace rubix {
@@ -66,12 +68,6 @@ __device__ __forceinline__ void bwd_bin(float w0, float w1, float w2, float w3, 
   y = fmaf(g * lamf, dS, y);
 }
 
-// The value of the next lane (lane l receives lane l+1's; lane 63's result is not used).
-__device__ __forceinline__ float next_lane(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
-                                                               0x130, 0xf, 0xf, false));
-}
-
 __device__ __forceinline__ float4 ld_bintab(__amdgpu_buffer_rsrc_t rt, int j) {
   return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rt, j * 16, 0, 0));
 }
@@ -89,15 +85,15 @@ __device__ __forceinline__ float ld_grad(__amdgpu_buffer_rsrc_t rg, int j) {
 // contiguous run (n0 grows with the window's wavelength); for a particle whose span fits a
 // window (the forward kernel's decision, carried in the record's sign) the run takes a loop of
 // its own: the four corner rows are loaded with one coalesced load each (row base in scalar
-// registers) and lane l stages, at node n0 + l, the particle's spectrum, its slope to the next
-// node and its two cell directions in the wave's LDS rows, the slope and the directions formed
-// from differences of the FP32 node values (exact or nearly so) before they meet G; each bin then
-// interpolates the spectrum with the slope and the directions linearly. The
-// windows before and after the run, and every window of a particle that does not fit, gather each
-// lane's eight template values directly. Each lane accumulates its bins in increasing order; the
-// wave's sums are reduced in FP64.
+// registers) and lane l stages, at node n0 + l, the cell's four bilinear basis rows (the first
+// corner and three node-wise differences of corners) in the wave's LDS rows; each bin reads its
+// two nodes of every basis row and accumulates, per basis row, the gradient-weighted
+// interpolant and slope. The dots are linear in the rows, so the run's sums go back to the four
+// dots once per particle. The windows before and after the run, and every window of a particle
+// that does not fit, gather each lane's eight template values directly. Each lane accumulates its
+// bins in increasing order; the wave's sums are reduced in FP64.
 __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
-  __shared__ float rows[4][4][64];     // [wave][spectrum, slope, age, metallicity][node - n0]
+  __shared__ float rows[4][4][64];     // [wave][basis row U0..U3][node - n0]
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
   const float *__restrict__ flux = S.flux;
@@ -133,7 +129,6 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
       const int jo = __builtin_amdgcn_readfirstlane(r.pad);     // input index: where the dots go
       const float w0 = r.a[0], w1 = r.a[1], w2 = r.a[2], w3 = r.a[3];
       const float ta = w2 + w3, tz = w1 + w3;   // bilinear fractions recovered from the weights
-      const float omta = 1.f - ta, omtz = 1.f - tz;
       const bool fits = rrow >= 0;
       const int row = prep_row(rrow);
       // the particle's gradient row: loads past its last bin return 0
@@ -185,40 +180,74 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
           if (n0 >= 0 && n0 + 63 <= nl - 1) break;
           general(lamf, tau, k, gj);
         }
-        // the run: every lane's node k lies in [n0, n0 + 62], inside [0, n - 2]
-        for (; jw < J.n_tel; jw += kCubeWaveBins, Qx += step_x, lamd += step_l) {
-          // the lane offsets pass through an empty asm each iteration, so their widening to
-          // 64 bits stays next to the loads and the loads take the scalar-base form
-          asm volatile("" : "+v"(lo[0]), "+v"(lo[1]), "+v"(lo[2]), "+v"(lo[3]));
-          float lamf, tau, gj;
-          int k, n0;
-          locate(lamf, tau, k, n0, gj);
-          if (!(n0 >= 0 && n0 + 63 <= nl - 1)) break;
-          const GChar *wb = (const GChar *)flux + (uint32_t)(row + n0) * 4u;
-          float st[4];
+        // the run: every lane's node k lies in [n0, n0 + 62], inside [0, n - 2]. The four dots
+        // are linear in the template rows, so the run accumulates them per row of the cell's
+        // bilinear basis U0 = T0, U1 = T1 - T0 (metallicity), U2 = T2 - T0 (age),
+        // U3 = T3 - T2 - T1 + T0 (cross): S = U0 + tz U1 + ta U2 + ta tz U3, the age direction
+        // (1-tz)(T2-T0) + tz(T3-T1) = U2 + tz U3, the metallicity direction U1 + ta U3. Per
+        // basis row b the lane sums e_b = sum G (U_b(k) + tau dU_b) and f_b = sum G lam dU_b,
+        // dU_b = U_b(k+1) - U_b(k); the node differences are taken on FP32 node values before
+        // any sum (on fine grids the spectrum changes by 1e-3 of itself per node).
+        // One copy of the loop per grid kind (log grids: the Doppler factor of g is 1). Within the
+        // run a particle's node indices stay far inside the int range (its span fits a window,
+        // which bounds |lam g| by lam / dlam_tel), so the index is one floor-and-convert.
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f, e3 = 0.f, f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
+        auto run = [&](auto log_grid) {
+          for (; jw < J.n_tel; jw += kCubeWaveBins, Qx += step_x, lamd += step_l) {
+            // the lane offsets pass through an empty asm each iteration, so their widening to
+            // 64 bits stays next to the loads and the loads take the scalar-base form
+            asm volatile("" : "+v"(lo[0]), "+v"(lo[1]), "+v"(lo[2]), "+v"(lo[3]));
+            const int qi = (int)(Qx >> 40);
+            const float qf = (float)(uint32_t)((uint64_t)Qx >> 8) * 0x1p-32f;
+            const float lamf = decltype(log_grid)::value ? 1.0f : (float)lamd;
+            const float tq = fmaf(-lamf, g, qf);
+            const int k = qi + floor_i32(tq);
+            const int n0 = __builtin_amdgcn_readfirstlane(k);
+            if (!(n0 >= 0 && n0 + 63 <= nl - 1)) break;
+            const float tau = __builtin_amdgcn_fractf(tq);
+            // the gradient of the lane's bin: the window's offset as the load's scalar offset
+            const float gj = __builtin_bit_cast(
+                float, __builtin_amdgcn_raw_buffer_load_b32(rg, gofs, jw * 4, 0));
+            const GChar *wb = (const GChar *)flux + (uint32_t)(row + n0) * 4u;
+            float st[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) st[c] = *(const GFloat *)(wb + lo[c]);
-          // the slope to the next node from differences of the FP32 node values (the next
-          // node's values come from the next lane), not as a difference of two rounded spectra:
-          // on fine grids the spectrum changes by 1e-3 of itself per node
-          float d[4];
+            for (int c = 0; c < 4; ++c) st[c] = *(const GFloat *)(wb + lo[c]);
+            const float u1 = st[1] - st[0];
+            wr[lane] = st[0];
+            wr[64 + lane] = u1;
+            wr[128 + lane] = st[2] - st[0];
+            wr[192 + lane] = (st[3] - st[2]) - u1;
+            __builtin_amdgcn_wave_barrier();
+            const int i = k - n0;
+            float b0[4], b1[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) d[c] = next_lane(st[c]) - st[c];
-          wr[lane] = w0 * st[0] + w1 * st[1] + w2 * st[2] + w3 * st[3];
-          wr[64 + lane] = w0 * d[0] + w1 * d[1] + w2 * d[2] + w3 * d[3];
-          wr[128 + lane] = omtz * (st[2] - st[0]) + tz * (st[3] - st[1]);
-          wr[192 + lane] = omta * (st[1] - st[0]) + ta * (st[3] - st[2]);
-          __builtin_amdgcn_wave_barrier();
-          const int i = k - n0;
-          const float s0 = wr[i], dS = wr[64 + i];
-          const float a0 = wr[128 + i], a1 = wr[128 + i + 1];
-          const float z0 = wr[192 + i], z1 = wr[192 + i + 1];
-          __builtin_amdgcn_wave_barrier();
-          sm = fmaf(gj, fmaf(tau, dS, s0), sm);
-          sa = fmaf(gj, fmaf(tau, a1 - a0, a0), sa);
-          sz = fmaf(gj, fmaf(tau, z1 - z0, z0), sz);
-          y = fmaf(gj * lamf, dS, y);
-        }
+            for (int b = 0; b < 4; ++b) {
+              b0[b] = wr[64 * b + i];
+              b1[b] = wr[64 * b + i + 1];
+            }
+            __builtin_amdgcn_wave_barrier();
+            const float gl = gj * lamf;
+            float du[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) du[b] = b1[b] - b0[b];
+            e0 = fmaf(gj, fmaf(tau, du[0], b0[0]), e0);
+            e1 = fmaf(gj, fmaf(tau, du[1], b0[1]), e1);
+            e2 = fmaf(gj, fmaf(tau, du[2], b0[2]), e2);
+            e3 = fmaf(gj, fmaf(tau, du[3], b0[3]), e3);
+            f0 = fmaf(gl, du[0], f0);
+            f1 = fmaf(gl, du[1], f1);
+            f2 = fmaf(gl, du[2], f2);
+            f3 = fmaf(gl, du[3], f3);
+          }
+        };
+        if (loglam) run(std::true_type{});
+        else run(std::false_type{});
+        // back to the four dots (the bilinear fractions from the record's weights)
+        const float tt = ta * tz;
+        sm += fmaf(tt, e3, fmaf(ta, e2, fmaf(tz, e1, e0)));
+        sa += fmaf(tz, e3, e2);
+        sz += fmaf(ta, e3, e1);
+        y += fmaf(tt, f3, fmaf(ta, f2, fmaf(tz, f1, f0)));
       }
       // windows after the run, or every window of a particle that does not fit
       for (; jw < J.n_tel; jw += kCubeWaveBins, Qx += step_x, lamd += step_l) {

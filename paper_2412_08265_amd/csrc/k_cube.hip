@@ -7,11 +7,11 @@
 //             with several chunks get partial-sum slots.
 //   k_vbound  streams the particles in input order: the job's largest Doppler slope and window
 //             flag for the cube kernel, and a packed 16-byte (mass, age, [M/H], v_los) record each.
-//   k_prep_sorted  one block per kPrepBlock sorted in-field particles: orders them by (spaxel,
-//             SSP cell) in LDS, then for each position gathers the particle's packed record
-//             through perm, finds its SSP cell and writes a 32-byte record {flux row, Doppler
-//             slope g, 4 corner weights, window flag}; consecutive particles of a spaxel then
-//             share template rows (L1 hits in the cube kernel and the adjoint).
+//   k_prep_sorted  one block per kPrepBlock sorted in-field particles: gathers each one's packed
+//             record through perm once (into LDS), orders the block by (spaxel, SSP cell) in LDS,
+//             and writes in that order a 32-byte record {flux row, Doppler slope g, 4 corner
+//             weights, window flag}; consecutive particles of a spaxel then share template rows
+//             (L1 hits in the cube kernel and the adjoint).
 //   k_cube    one block per (lambda tile of kCubeTL bins, chunk); each wave owns 62 consecutive
 //             telescope bins and walks the chunk's particles, kCubeGroup at a time:
 //               stage    lane l computes the particle's bilinear spectrum at SSP node n0 + l,
@@ -88,12 +88,10 @@ __device__ __forceinline__ void doppler_slope(const JobDev &J, const SspDev &S, 
 // mode 0: forward weights flux_scale*m*J*w_c; mode 1: plain bilinear weights w_c.
 // The record of sorted particle i (mode 0: forward weights flux_scale*m*J*w_c, or
 // flux_scale*m*dlam_ssp/dlam_tel*w_c for the bin mean; mode 1: plain bilinear weights w_c).
-__device__ __forceinline__ PrepRec make_record(const JobDev &J, const SspDev &S, int64_t i,
-                                               int mode) {
-  const int j = J.perm[i];
-  // one 16-byte gather of the particle's (mass, age, [M/H], vlos), packed in input order by
-  // k_vbound (forward) or k_pack (backward)
-  const float4 pr = J.pay[j];
+// Record of the particle with input index j, packed properties pr (mass, age, [M/H], vlos; packed
+// in input order by k_vbound in the forward and k_pack in the backward) and spaxel key.
+__device__ __forceinline__ PrepRec make_record(const JobDev &J, const SspDev &S, int j, float4 pr,
+                                               int key, int mode) {
   const double m = pr.x, age = pr.y, met = pr.z, v = pr.w;
   const int ja = cell_of(S.age_thr, S.n_age, age);
   double ta;
@@ -124,7 +122,7 @@ __device__ __forceinline__ PrepRec make_record(const JobDev &J, const SspDev &S,
   r.a[1] = (float)(scale * (1.0 - ta) * tz);
   r.a[2] = (float)(scale * ta * (1.0 - tz));
   r.a[3] = (float)(scale * ta * tz);
-  r.spaxel = mode == 0 ? -1 : J.key[j];
+  r.spaxel = mode == 0 ? -1 : key;
   if (!fits) r.row = ~r.row;
   r.pad = mode == 0 ? 0 : j;     // backward: the particle's input index (where its dots go)
   return r;
@@ -262,6 +260,8 @@ typedef __attribute__((address_space(4))) const int CInt;         // read-only: 
 // each record is then built for its sorted position and written once.
 __global__ __launch_bounds__(256) void k_prep_sorted(const Table *__restrict__ T, int mode) {
   __shared__ uint64_t key[kPrepBlock];
+  __shared__ float4 spay[kPrepBlock];    // the block's packed properties, gathered once
+  __shared__ int sidx[kPrepBlock];       // and input indices, by position in sorted order
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
   const int t = threadIdx.x;
@@ -284,6 +284,8 @@ __global__ __launch_bounds__(256) void k_prep_sorted(const Table *__restrict__ T
         const int jz = cell_of(S.met, S.n_met, (double)pr.z);
         k = ((uint64_t)(J.key[j] - s0) << 32) | ((uint64_t)(ja * S.n_met + jz) << 12) |
             (uint64_t)i;
+        spay[i] = pr;
+        sidx[i] = j;
       }
       key[i] = k;
     }
@@ -299,9 +301,13 @@ __global__ __launch_bounds__(256) void k_prep_sorted(const Table *__restrict__ T
         __syncthreads();
       }
     }
-    for (int i = t; i < n; i += 256)
-      J.prep[p0 + i] = make_record(J, S, p0 + (int64_t)(key[i] & 4095u), mode);
-    __syncthreads();   // key[] is reused by the block's next item
+    // the records from the LDS copies: no second gather through the permutation
+    for (int i = t; i < n; i += 256) {
+      const uint64_t k = key[i];
+      const int src = (int)(k & 4095u);
+      J.prep[p0 + i] = make_record(J, S, sidx[src], spay[src], s0 + (int)(k >> 32), mode);
+    }
+    __syncthreads();   // the LDS arrays are reused by the block's next item
   }
 }
 
