@@ -42,7 +42,7 @@ __all__ = [
     "integral_linear", "linear_at", "bin_edge_indices", "bin_edge_indices_log",
     "integral_log_weighted", "particle_spectra", "cube_raw", "gaussian_weights",
     "convolve_axis", "psf_lsf", "forward", "loss", "loss_grad_cube", "adjoint",
-    "OracleConfig", "config_from_workload",
+    "OracleConfig", "config_from_workload", "ForkedPool",
 ]
 
 
@@ -512,6 +512,32 @@ def _cube_rows(args):
 _POOL_STATE: Dict = {}
 
 
+class ForkedPool:
+    """A fork-context process pool whose children run no garbage collection of the parent's
+    objects: the parent collects its garbage first and freezes the rest (a caller that holds
+    device resources, e.g. a GPU test, would otherwise see a child finalise them)."""
+
+    def __init__(self, ctx, workers):
+        import gc
+        gc.collect()
+        gc.freeze()
+        try:
+            self.pool = ctx.Pool(workers)
+        except BaseException:
+            gc.unfreeze()
+            raise
+
+    def __enter__(self):
+        return self.pool.__enter__()
+
+    def __exit__(self, *exc):
+        import gc
+        try:
+            return self.pool.__exit__(*exc)
+        finally:
+            gc.unfreeze()
+
+
 def cube_raw(p, key, perm, seg_off, vlos, cfg: OracleConfig, workers: Optional[int] = None,
              chunk: int = 1024, ties=None):
     """C_raw[s, j] = sum over particles with key s of f_i(lam_j), FP64, shape [ny*nx, n_tel].
@@ -547,8 +573,7 @@ def cube_raw(p, key, perm, seg_off, vlos, cfg: OracleConfig, workers: Optional[i
 
     if workers > 1 and len(tasks) > 1:
         import multiprocessing as mp
-        ctx = mp.get_context("fork")
-        with ctx.Pool(workers) as pool:
+        with ForkedPool(mp.get_context("fork"), workers) as pool:
             for res in pool.imap_unordered(_cube_rows, tasks):
                 put(res)
     else:
@@ -682,7 +707,7 @@ def adjoint(p, cfg: OracleConfig, G: np.ndarray, fw: Optional[Dict] = None,
         import multiprocessing as mp
         parts = np.array_split(idx, workers * 4)
         _POOL_STATE.update(adj=(p, cfg, G, fw, chunk, ties))
-        with mp.get_context("fork").Pool(workers) as pool:
+        with ForkedPool(mp.get_context("fork"), workers) as pool:
             res = pool.map(_adjoint_part, parts)
         _POOL_STATE.clear()
         keys = names if ties is None else names + tuple(f"{k}_{e}" for k in names

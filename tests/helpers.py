@@ -139,7 +139,7 @@ def oracle_rows_parallel(p, cfg, fw_or, spaxels, workers=WORKERS, ties=None, pie
     tasks.sort(key=lambda t: t[1] - t[2])
     acc = {s: np.zeros((3, cfg.n_tel)) for s in spaxels}
     n_tied = 0
-    with mp.get_context("fork").Pool(workers) as pool:
+    with O.ForkedPool(mp.get_context("fork"), workers) as pool:
         for s, (rows, nt) in pool.imap_unordered(_rows_task, tasks):
             acc[s] += rows
             n_tied += nt

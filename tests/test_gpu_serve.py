@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import TIES, WORKERS, assert_cube_in, log
+from helpers import TIES, assert_cube_in, log
 
 import oracle as O
 from paper_2412_08265_amd import ops, synth
@@ -155,7 +155,7 @@ def test_served_bin_mean_request_matches_oracle(ssp_grid, dssp):
     fut = s.submit(req)
     s.drain()
     cube = fut.result(timeout=0).cube.cpu().numpy().reshape(w.nx * w.ny, w.n_tel)
-    fo = O.forward(w.particles, O.config_from_workload(w), workers=WORKERS, ties=TIES)
+    fo = O.forward(w.particles, O.config_from_workload(w), workers=1, ties=TIES)
     assert_cube_in(cube, fo, "cube", what=f"served bin-mean cube ({w.particles.n} particles)")
 
 
@@ -167,7 +167,7 @@ def test_served_request_matches_oracle(ssp_grid, dssp):
     fut = s.submit(req)
     s.drain()
     cube = fut.result(timeout=0).cube.cpu().numpy().reshape(w.nx * w.ny, w.n_tel)
-    fo = O.forward(w.particles, O.config_from_workload(w), workers=WORKERS, ties=TIES)
+    fo = O.forward(w.particles, O.config_from_workload(w), workers=1, ties=TIES)
     assert_cube_in(cube, fo, "cube", what=f"served cube ({w.particles.n} particles)")
 
 
