@@ -190,14 +190,16 @@ def test_trace_through_scheduler_small_budget(ssp_grid, dssp):
         assert torch.equal(f.result(timeout=0).cube.cpu(), ref[k]), k
 
 
-@pytest.mark.parametrize("mode", ["native", "persistent"])
-def test_million_particle_request_in_a_mixed_batch(ssp_grid, dssp, mode):
-    """Request 4 of the serving trace (1.47e6 particles, 29x29 spaxels, 3669 bins) batched with
-    four small requests: its cube equals the plain entry points' bitwise alone and in the mix;
-    against the oracle, the C_raw rows of its 16 heaviest and 64 random spaxels in full and the
-    final cube of every spaxel on 64 interior bins (tie bounds), within 1e-5."""
+@pytest.mark.parametrize("mode,req", [("native", 4), ("persistent", 4), ("native", 207),
+                                      ("persistent", 207)])
+def test_million_particle_request_in_a_mixed_batch(ssp_grid, dssp, mode, req):
+    """A large request of the serving trace (request 4: 1.47e6 particles, 29x29 spaxels, 3669
+    bins; request 207, the trace's largest: 5.0e6 particles, 67x67 spaxels, 2889 bins) batched
+    with four small requests: its cube equals the plain entry points' bitwise alone and in the
+    mix; against the oracle, the C_raw rows of its 16 heaviest and 64 random spaxels in full and
+    the final cube of every spaxel on 64 interior bins (tie bounds), within 1e-5."""
     from helpers import gpu_forward, oracle_final_window, oracle_rows_parallel, outside
-    big = synth.serving_request(4, ssp_grid)
+    big = synth.serving_request(req, ssp_grid)
     assert big.particles.n >= 1_000_000
     ws = [big] + _workloads(ssp_grid, range(4))
     for w in ws:
