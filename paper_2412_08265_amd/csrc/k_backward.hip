@@ -205,9 +205,10 @@ __global__ __launch_bounds__(256) void k_bwd_dots(const Table *__restrict__ T) {
             const int n0 = __builtin_amdgcn_readfirstlane(k);
             if (!(n0 >= 0 && n0 + 63 <= nl - 1)) break;
             const float tau = __builtin_amdgcn_fractf(tq);
-            // the gradient of the lane's bin: the window's offset as the load's scalar offset
+            // the gradient of the lane's bin: the window's offset goes into the lane's offset,
+            // which the buffer's range check covers (bins past the row's end read 0)
             const float gj = __builtin_bit_cast(
-                float, __builtin_amdgcn_raw_buffer_load_b32(rg, gofs, jw * 4, 0));
+                float, __builtin_amdgcn_raw_buffer_load_b32(rg, gofs + (uint32_t)jw * 4u, 0, 0));
             const GChar *wb = (const GChar *)flux + (uint32_t)(row + n0) * 4u;
             float st[4];
 #pragma unroll
