@@ -13,11 +13,12 @@
 //   k_psf_lsf_fused (lambda tile of kFuseL bins, x segment of kFuseX spaxels): all three filters
 //            in one pass that reads the cube once and writes it once. The work item walks the y
 //            rows in order; per row it stages kFuseX + 2 kFuseR x positions by kFuseL + 2 r_lsf
-//            bins in LDS, filters them along lambda and then along x, and adds the row into a
-//            shift register of 2 kFuseR partial output rows per lane (the y filter), storing the
-//            output row that the new row completes. The next row's loads are in flight while the
-//            current row is filtered. Jobs whose radii exceed the fused bounds, and jobs with an
-//            LSF only, run the 1-D passes.
+//            bins in LDS, filters them along lambda and then along x, and adds the row into
+//            2 kFuseR partial output rows per lane held in registers (the y filter, updated in
+//            place: rows run in unrolled blocks of kFuseU, each compiled for its phase), storing
+//            the output row that the new row completes. The next row's loads are in flight
+//            while the current row is filtered. Jobs whose radii exceed the fused bounds, and
+//            jobs with an LSF only, run the 1-D passes.
 // The normalised FP32 weights come with the job table (computed on the host in FP64), padded with
 // kWPad zeros on both sides so a blocked filter needs no branch at the ends of its window.
 #include "rubix_internal.h"
@@ -198,6 +199,24 @@ __device__ __forceinline__ float fuse_weight(const float *w, int r, int m) {
 // other m in -4 .. 2 kFuseLsfR + 7, so a block of four outputs reads them as aligned float4s
 constexpr int kFuseWL = 2 * kFuseLsfR + 16;
 
+// One row of the y filter at phase ph (a compile-time constant after unrolling): partial k of
+// output row y - R + k lives in P[i][(k + ph) % 2R]. The complete partial (k = 0) takes
+// wpx[2R] t and leaves; each other partial k + 1 takes wpx[2R - 1 - k] t in place and becomes
+// partial k of the next row; the freed slot starts the new last partial with wpx[0] t. These
+// are the FMAs of a shift register, with the registers renamed instead of moved.
+__device__ __forceinline__ void fuse_y_step(int ph, float (&P)[4][2 * kFuseR], const float (&t)[4],
+                                            const float (&wpx)[2 * kFuseR + 1], float (&done)[4]) {
+  constexpr int L = 2 * kFuseR;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    done[i] = fmaf(wpx[L], t[i], P[i][ph]);
+    P[i][ph] = wpx[0] * t[i];
+#pragma unroll
+    for (int k = 0; k < L - 1; ++k)
+      P[i][(k + 1 + ph) % L] = fmaf(wpx[L - 1 - k], t[i], P[i][(k + 1 + ph) % L]);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_psf_lsf_fused(const Table *__restrict__ T) {
   __shared__ __attribute__((aligned(16))) float S[kFuseRows * kFuseW];   // staged input row
   __shared__ __attribute__((aligned(16))) float M[kFuseRows * kFuseL];   // after the LSF
@@ -205,7 +224,8 @@ __global__ __launch_bounds__(256) void k_psf_lsf_fused(const Table *__restrict__
   const JobDev *jobs = table_jobs(T);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int w = tid >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar x offsets
+  typedef __attribute__((address_space(1))) float GOut;     // global stores, scalar row base
   const int64_t total = T->h.total[K_FUSE];
   for (int64_t vb0 = blockIdx.x; vb0 < total; vb0 += gridDim.x) {
     const int64_t vb = xcd_run(vb0, total);
@@ -225,18 +245,18 @@ __global__ __launch_bounds__(256) void k_psf_lsf_fused(const Table *__restrict__
       WL[i] = (m >= 0 && m <= 2 * rl) ? J.lsf_w[kWPad + m] : 0.f;
     }
     // staging: wave w stages x positions x0 - kFuseR + w + 4 i (i = 0..7), lane l the bins
-    // l0 - rl + l and, for l + 64 < wc, l0 - rl + l + 64; the bin part of each offset is the
-    // lane's (clamped to the row, a mask zeroes bins outside it), the x part is wave-uniform
+    // l0 - rl + l and, for l + 64 < wc, l0 - rl + l + 64. A row is read through a buffer
+    // resource over its y plane (one with no bytes for x positions outside the cube), the x
+    // position's offset in the scalar offset and the bin's in the lane offset; lanes whose bin
+    // lies outside the spectrum or past the staged width take an offset past the plane (the
+    // router keeps planes below 2^31 bytes, so the sum cannot wrap), and all of these read 0
     uint32_t loff[2];
-    bool lin[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int c = lane + 64 * h;
       const int g = l0 - rl + c;
-      lin[h] = c < wc && g >= 0 && g < nt;
-      loff[h] = 4u * (uint32_t)min(max(g, 0), nt - 1);
+      loff[h] = (c < wc && g >= 0 && g < nt) ? 4u * (uint32_t)g : 0x80000000u;
     }
-    const bool second = lane + 64 < wc;
     // the x and y filters padded to radius kFuseR
     float wpx[2 * kFuseR + 1];
 #pragma unroll
@@ -247,7 +267,10 @@ __global__ __launch_bounds__(256) void k_psf_lsf_fused(const Table *__restrict__
     // outputs of this thread: x = x0 + 4 w + i (i = 0..3), bin l0 + lane
     const int lb = l0 + lane;
     const bool lok = lb < nt;
-    // P[i][k]: partial sum of output row y - kFuseR + k before row y is added
+    // P[i][.]: partial sums of output rows y - kFuseR .. y + kFuseR - 1 before row y is added.
+    // At the start of each block of kFuseU rows partial k (of output row y - kFuseR + k) sits in
+    // P[i][k], before the block's u-th row in P[i][(k + u) % 2 kFuseR]: each row updates every
+    // partial in place and only its phase u decides which one is complete
     float P[4][2 * kFuseR];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -255,92 +278,113 @@ __global__ __launch_bounds__(256) void k_psf_lsf_fused(const Table *__restrict__
       for (int k = 0; k < 2 * kFuseR; ++k) P[i][k] = 0.f;
     float pf[kFuseRows / 4][2];
     auto load_row = [&](int y) {
-      const GChar *rowp = (const GChar *)(src + (int64_t)y * plane);
+      const float *rowp = src + (int64_t)y * plane;
+      const __amdgpu_buffer_rsrc_t rin =
+          __builtin_amdgcn_make_buffer_rsrc((void *)rowp, (short)0, (int)(plane * 4), 0x00020000);
+      const __amdgpu_buffer_rsrc_t rout =
+          __builtin_amdgcn_make_buffer_rsrc((void *)rowp, (short)0, 0, 0x00020000);
 #pragma unroll
       for (int i = 0; i < kFuseRows / 4; ++i) {
-        const int gx = min(max(x0 - kFuseR + w + 4 * i, 0), nx - 1);
-        const GChar *xp = rowp + 4 * (int64_t)gx * nt;
-        uint32_t o0 = loff[0], o1 = loff[1];
-        asm volatile("" : "+v"(o0), "+v"(o1));
-        pf[i][0] = *(const GFloat *)(xp + o0);
-        pf[i][1] = second ? *(const GFloat *)(xp + o1) : 0.f;
+        const int gx = x0 - kFuseR + w + 4 * i;
+        const bool xin = gx >= 0 && gx < nx;
+        const __amdgpu_buffer_rsrc_t rx = xin ? rin : rout;
+        const int so = xin ? gx * nt * 4 : 0;
+        pf[i][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, loff[0], so, 0));
+        pf[i][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, loff[1], so, 0));
+      }
+    };
+    // one input row: stage it (its loads were issued one row earlier), issue the next row's
+    // loads, filter along lambda and then along x: t[i] = sum_m wpx[m] M[4w + i + m][lane]
+    auto filter_row = [&](int y, float (&t)[4]) {
+#pragma unroll
+      for (int i = 0; i < kFuseRows / 4; ++i) {
+        float *srow = S + (w + 4 * i) * kFuseW + lane;
+        srow[0] = pf[i][0];
+        if (lane < kFuseW - 64) srow[64] = pf[i][1];
+      }
+      if (y + 1 < ny) load_row(y + 1);
+      __syncthreads();
+      // LSF along lambda for staged x positions xx = tid/16 and tid/16 + 16, bins 4 (tid % 16)
+      // + 0..3: out_i = sum_o wl[o - i] S[xx][b4 + o], the weights read from LDS as float4s
+      {
+        const int b4 = 4 * (tid & 15);
+        const float *r0 = S + (tid >> 4) * kFuseW + b4;
+        const float *r1 = r0 + 16 * kFuseW;
+        float a[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        float4 wa = *reinterpret_cast<const float4 *>(WL);
+        for (int m = 0; m < nq; ++m) {
+          const float4 wb = *reinterpret_cast<const float4 *>(WL + 4 * m + 4);
+          const float4 xs[2] = {*reinterpret_cast<const float4 *>(r0 + 4 * m),
+                                *reinterpret_cast<const float4 *>(r1 + 4 * m)};
+#pragma unroll
+          for (int g = 0; g < 2; ++g) {
+            const float4 x = xs[g];
+            // wa = wl[o-4 .. o-1], wb = wl[o .. o+3] with o = 4m
+            a[g][0] = fmaf(wb.x, x.x, a[g][0]);
+            a[g][0] = fmaf(wb.y, x.y, a[g][0]);
+            a[g][0] = fmaf(wb.z, x.z, a[g][0]);
+            a[g][0] = fmaf(wb.w, x.w, a[g][0]);
+            a[g][1] = fmaf(wa.w, x.x, a[g][1]);
+            a[g][1] = fmaf(wb.x, x.y, a[g][1]);
+            a[g][1] = fmaf(wb.y, x.z, a[g][1]);
+            a[g][1] = fmaf(wb.z, x.w, a[g][1]);
+            a[g][2] = fmaf(wa.z, x.x, a[g][2]);
+            a[g][2] = fmaf(wa.w, x.y, a[g][2]);
+            a[g][2] = fmaf(wb.x, x.z, a[g][2]);
+            a[g][2] = fmaf(wb.y, x.w, a[g][2]);
+            a[g][3] = fmaf(wa.y, x.x, a[g][3]);
+            a[g][3] = fmaf(wa.z, x.y, a[g][3]);
+            a[g][3] = fmaf(wa.w, x.z, a[g][3]);
+            a[g][3] = fmaf(wb.x, x.w, a[g][3]);
+          }
+          wa = wb;
+        }
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+          *reinterpret_cast<float4 *>(M + ((tid >> 4) + 16 * g) * kFuseL + b4) =
+              make_float4(a[g][0], a[g][1], a[g][2], a[g][3]);
+      }
+      __syncthreads();
+      // PSF along x: t[i] = sum_m wpx[m] M[4w + i + m][lane]
+#pragma unroll
+      for (int o = 0; o < 2 * kFuseR + 4; ++o) {
+        const float v = M[(4 * w + o) * kFuseL + lane];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (o - i >= 0 && o - i <= 2 * kFuseR) t[i] = fmaf(wpx[o - i], v, t[i]);
       }
     };
     if (ny > 0) load_row(0);
-    for (int y = 0; y < ny + kFuseR; ++y) {
-      float t[4] = {0.f, 0.f, 0.f, 0.f};
-      if (y < ny) {                                                   // block-uniform
+    // rows in blocks of kFuseU: within a block the y update of its u-th row is compiled for
+    // phase u, so partials stay in place; one rotation per block restores the order
+    const int ysteps = ny + kFuseR;
+    for (int yb = 0; yb < ysteps; yb += kFuseU) {
 #pragma unroll
-        for (int i = 0; i < kFuseRows / 4; ++i) {
-          const int gx = x0 - kFuseR + w + 4 * i;
-          const bool xin = gx >= 0 && gx < nx;
-          float *srow = S + (w + 4 * i) * kFuseW + lane;
-          srow[0] = (xin && lin[0]) ? pf[i][0] : 0.f;
-          if (lane < kFuseW - 64) srow[64] = (xin && lin[1]) ? pf[i][1] : 0.f;
-        }
-        if (y + 1 < ny) load_row(y + 1);
-        __syncthreads();
-        // LSF along lambda for staged x positions xx = tid/16 and tid/16 + 16, bins 4 (tid % 16)
-        // + 0..3: out_i = sum_o wl[o - i] S[xx][b4 + o], the weights read from LDS as float4s
-        {
-          const int b4 = 4 * (tid & 15);
-          const float *r0 = S + (tid >> 4) * kFuseW + b4;
-          const float *r1 = r0 + 16 * kFuseW;
-          float a[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-          float4 wa = *reinterpret_cast<const float4 *>(WL);
-          for (int m = 0; m < nq; ++m) {
-            const float4 wb = *reinterpret_cast<const float4 *>(WL + 4 * m + 4);
-            const float4 xs[2] = {*reinterpret_cast<const float4 *>(r0 + 4 * m),
-                                  *reinterpret_cast<const float4 *>(r1 + 4 * m)};
+      for (int u = 0; u < kFuseU; ++u) {
+        const int y = yb + u;
+        if (y >= ysteps) break;                                      // block-uniform
+        float t[4] = {0.f, 0.f, 0.f, 0.f};
+        if (y < ny) filter_row(y, t);                               // block-uniform
+        // PSF along y: row y adds wpx[2R - k] t to output row y - R + k; row y - R is then
+        // complete
+        float done[4];
+        fuse_y_step(u, P, t, wpx, done);
+        const int yo = y - kFuseR;
 #pragma unroll
-            for (int g = 0; g < 2; ++g) {
-              const float4 x = xs[g];
-              // wa = wl[o-4 .. o-1], wb = wl[o .. o+3] with o = 4m
-              a[g][0] = fmaf(wb.x, x.x, a[g][0]);
-              a[g][0] = fmaf(wb.y, x.y, a[g][0]);
-              a[g][0] = fmaf(wb.z, x.z, a[g][0]);
-              a[g][0] = fmaf(wb.w, x.w, a[g][0]);
-              a[g][1] = fmaf(wa.w, x.x, a[g][1]);
-              a[g][1] = fmaf(wb.x, x.y, a[g][1]);
-              a[g][1] = fmaf(wb.y, x.z, a[g][1]);
-              a[g][1] = fmaf(wb.z, x.w, a[g][1]);
-              a[g][2] = fmaf(wa.z, x.x, a[g][2]);
-              a[g][2] = fmaf(wa.w, x.y, a[g][2]);
-              a[g][2] = fmaf(wb.x, x.z, a[g][2]);
-              a[g][2] = fmaf(wb.y, x.w, a[g][2]);
-              a[g][3] = fmaf(wa.y, x.x, a[g][3]);
-              a[g][3] = fmaf(wa.z, x.y, a[g][3]);
-              a[g][3] = fmaf(wa.w, x.z, a[g][3]);
-              a[g][3] = fmaf(wb.x, x.w, a[g][3]);
-            }
-            wa = wb;
-          }
-#pragma unroll
-          for (int g = 0; g < 2; ++g)
-            *reinterpret_cast<float4 *>(M + ((tid >> 4) + 16 * g) * kFuseL + b4) =
-                make_float4(a[g][0], a[g][1], a[g][2], a[g][3]);
-        }
-        __syncthreads();
-        // PSF along x: t[i] = sum_m wpx[m] M[4w + i + m][lane]
-#pragma unroll
-        for (int o = 0; o < 2 * kFuseR + 4; ++o) {
-          const float v = M[(4 * w + o) * kFuseL + lane];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (o - i >= 0 && o - i <= 2 * kFuseR) t[i] = fmaf(wpx[o - i], v, t[i]);
+        for (int i = 0; i < 4; ++i) {
+          const int x = x0 + 4 * w + i;
+          // the row base is wave-uniform (scalar registers), the lane's bin its offset
+          GOut *orow = (GOut *)(dst + (int64_t)yo * plane + (int64_t)x * nt + l0);
+          if (yo >= 0 && x < nx && lok) orow[lane] = done[i];
         }
       }
-      // PSF along y: row y adds wpx[2R - k] t to output row y - R + k; row y - R is then complete
-      const int yo = y - kFuseR;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float done = fmaf(wpx[2 * kFuseR], t[i], P[i][0]);
-        const int x = x0 + 4 * w + i;
-        if (yo >= 0 && x < nx && lok) dst[(int64_t)yo * plane + (int64_t)x * nt + lb] = done;
+        float r[2 * kFuseR];
 #pragma unroll
-        for (int k = 0; k < 2 * kFuseR - 1; ++k)
-          P[i][k] = fmaf(wpx[2 * kFuseR - 1 - k], t[i], P[i][k + 1]);
-        P[i][2 * kFuseR - 1] = wpx[0] * t[i];
+        for (int k = 0; k < 2 * kFuseR; ++k) r[k] = P[i][(k + kFuseU) % (2 * kFuseR)];
+#pragma unroll
+        for (int k = 0; k < 2 * kFuseR; ++k) P[i][k] = r[k];
       }
     }
     __syncthreads();

@@ -36,6 +36,7 @@ constexpr int kPsfSeg = 64;         // spaxels of a line per PSF work item (16 p
 constexpr int kFuseX = 16;
 constexpr int kFuseL = 64;
 constexpr int kFuseR = 8;
+constexpr int kFuseU = 4;          // fused pass: rows per unrolled block of the y update
 constexpr int kFuseLsfR = 22;
 constexpr int kFuseRows = kFuseX + 2 * kFuseR;          // staged x positions per row
 constexpr int kFuseW = kFuseL + 2 * kFuseLsfR + 4;      // LDS floats per staged x position
