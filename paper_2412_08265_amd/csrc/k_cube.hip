@@ -8,7 +8,8 @@
 //   k_vbound  streams the particles in input order: the job's largest Doppler slope and window
 //             flag for the cube kernel, and a packed 16-byte (mass, age, [M/H], v_los) record each.
 //   k_prep_sorted  one block per kPrepBlock sorted in-field particles: gathers each one's packed
-//             record through perm once (into LDS), orders the block by (spaxel, SSP cell) in LDS,
+//             record through perm once (into LDS), takes each position's spaxel from the segment
+//             offsets (no gather of keys), orders the block by (spaxel, SSP cell) in LDS,
 //             and writes in that order a 32-byte record {flux row, Doppler slope g, 4 corner
 //             weights, window flag}; consecutive particles of a spaxel then share template rows
 //             (L1 hits in the cube kernel and the adjoint).
@@ -90,19 +91,21 @@ __device__ __forceinline__ void doppler_slope(const JobDev &J, const SspDev &S, 
 // flux_scale*m*dlam_ssp/dlam_tel*w_c for the bin mean; mode 1: plain bilinear weights w_c).
 // Record of the particle with input index j, packed properties pr (mass, age, [M/H], vlos; packed
 // in input order by k_vbound in the forward and k_pack in the backward) and spaxel key.
+// The SSP cell (ja, jz) is cell_of's for the age and metallicity thresholds; the node arrays
+// (age thresholds, log10 age nodes, metallicity nodes) are the grid's, here copies in LDS.
 __device__ __forceinline__ PrepRec make_record(const JobDev &J, const SspDev &S, int j, float4 pr,
-                                               int key, int mode) {
+                                               int key, int mode, int ja, int jz,
+                                               const double *age_thr, const double *log_age,
+                                               const double *met_nodes) {
   const double m = pr.x, age = pr.y, met = pr.z, v = pr.w;
-  const int ja = cell_of(S.age_thr, S.n_age, age);
   double ta;
-  if (!(age > S.age_thr[0])) ta = 0.0;
-  else if (age >= S.age_thr[S.n_age - 1]) ta = 1.0;
-  else ta = clamp01((log10(age) - S.log_age[ja]) / (S.log_age[ja + 1] - S.log_age[ja]));
-  const int jz = cell_of(S.met, S.n_met, met);
+  if (!(age > age_thr[0])) ta = 0.0;
+  else if (age >= age_thr[S.n_age - 1]) ta = 1.0;
+  else ta = clamp01((log10(age) - log_age[ja]) / (log_age[ja + 1] - log_age[ja]));
   double tz;
-  if (!(met > S.met[0])) tz = 0.0;
-  else if (met >= S.met[S.n_met - 1]) tz = 1.0;
-  else tz = clamp01((met - S.met[jz]) / (S.met[jz + 1] - S.met[jz]));
+  if (!(met > met_nodes[0])) tz = 0.0;
+  else if (met >= met_nodes[S.n_met - 1]) tz = 1.0;
+  else tz = clamp01((met - met_nodes[jz]) / (met_nodes[jz + 1] - met_nodes[jz]));
   const double beta = v / kCkms;
   const double opz = 1.0 + J.z_sys;
   const double jac = 1.0 / (opz * (1.0 + beta));
@@ -271,9 +274,21 @@ __global__ __launch_bounds__(256) void k_prep_sorted(const Table *__restrict__ T
   __shared__ uint64_t key[kPrepBlock];
   __shared__ float4 spay[kPrepBlock];    // the block's packed properties, gathered once
   __shared__ int sidx[kPrepBlock];       // and input indices, by position in sorted order
+  __shared__ uint32_t srank[kPrepBlock]; // spaxel of each position, relative to the first one
+  __shared__ uint32_t scan_lds[256];
+  // the grid's node arrays, so the cell searches and weights read LDS instead of global memory
+  __shared__ double l_age_thr[RUBIX_MAX_AGE_NODES], l_log_age[RUBIX_MAX_AGE_NODES];
+  __shared__ double l_met[RUBIX_MAX_MET_NODES];
   const SspDev &S = T->h.ssp;
   const JobDev *jobs = table_jobs(T);
   const int t = threadIdx.x;
+  static_assert(kPrepBlock == 4 * 256, "four positions per thread in the spaxel scan");
+  for (int i = t; i < S.n_age; i += 256) {
+    l_age_thr[i] = S.age_thr[i];
+    l_log_age[i] = S.log_age[i];
+  }
+  for (int i = t; i < S.n_met; i += 256) l_met[i] = S.met[i];
+  __syncthreads();
   for (int64_t vb = blockIdx.x; vb < T->h.total[K_PREP]; vb += gridDim.x) {
     const int jj = find_job(T, K_PREP, vb);
     const JobDev &J = jobs[jj];
@@ -282,6 +297,31 @@ __global__ __launch_bounds__(256) void k_prep_sorted(const Table *__restrict__ T
     if (p0 >= n_in) continue;
     const int n = (int)min((int64_t)kPrepBlock, (int64_t)n_in - p0);
     const int s0 = J.key[J.perm[p0]];
+    // The spaxel of every position from the segment offsets rather than a gather of keys
+    // through perm: mark where each later spaxel's segment starts inside the block (an empty
+    // spaxel starts where the next one does), then a prefix sum gives the spaxel's offset from
+    // s0. Segments after s0 start past p0; seg_off[n_s] = n_in ends every thread's walk.
+    for (int i = t; i < kPrepBlock; i += 256) srank[i] = 0;
+    __syncthreads();
+    for (int s = s0 + 1 + t; s <= J.n_s; s += 256) {
+      const int b = J.seg_off[s];
+      if (b >= p0 + n) break;
+      atomicAdd(&srank[b - p0], 1u);
+    }
+    __syncthreads();
+    {
+      uint32_t c[4], run = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        run += srank[4 * t + q];
+        c[q] = run;
+      }
+      uint32_t excl;
+      block_exclusive_scan_256(run, scan_lds, excl);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) srank[4 * t + q] = excl + c[q];
+    }
+    __syncthreads();
     int np = 1;
     while (np < n) np <<= 1;
     for (int i = t; i < np; i += 256) {
@@ -289,10 +329,9 @@ __global__ __launch_bounds__(256) void k_prep_sorted(const Table *__restrict__ T
       if (i < n) {
         const int j = J.perm[p0 + i];
         const float4 pr = J.pay[j];
-        const int ja = cell_of(S.age_thr, S.n_age, (double)pr.y);
-        const int jz = cell_of(S.met, S.n_met, (double)pr.z);
-        k = ((uint64_t)(J.key[j] - s0) << 32) | ((uint64_t)(ja * S.n_met + jz) << 12) |
-            (uint64_t)i;
+        const int ja = cell_of(l_age_thr, S.n_age, (double)pr.y);
+        const int jz = cell_of(l_met, S.n_met, (double)pr.z);
+        k = ((uint64_t)srank[i] << 32) | ((uint64_t)(ja * S.n_met + jz) << 12) | (uint64_t)i;
         spay[i] = pr;
         sidx[i] = j;
       }
@@ -314,7 +353,10 @@ __global__ __launch_bounds__(256) void k_prep_sorted(const Table *__restrict__ T
     for (int i = t; i < n; i += 256) {
       const uint64_t k = key[i];
       const int src = (int)(k & 4095u);
-      J.prep[p0 + i] = make_record(J, S, sidx[src], spay[src], s0 + (int)(k >> 32), mode);
+      const int cell = (int)((k >> 12) & 0xfffffu);
+      const int ja = cell / S.n_met, jz = cell - ja * S.n_met;
+      J.prep[p0 + i] = make_record(J, S, sidx[src], spay[src], s0 + (int)(k >> 32), mode, ja, jz,
+                                   l_age_thr, l_log_age, l_met);
     }
     __syncthreads();   // the LDS arrays are reused by the block's next item
   }

@@ -108,25 +108,6 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const Table *__restrict__
   }
 }
 
-// Block-wide exclusive scan of one value per thread (256 threads); returns the block total.
-__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t *lds,
-                                                             uint32_t &excl) {
-  const int t = threadIdx.x;
-  lds[t] = v;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    uint32_t add = (t >= off) ? lds[t - off] : 0u;
-    __syncthreads();
-    lds[t] += add;
-    __syncthreads();
-  }
-  uint32_t incl = lds[t];
-  uint32_t total = lds[255];
-  __syncthreads();
-  excl = incl - v;
-  return total;
-}
-
 // Exclusive scan of hist[d][0..n_sort_tiles) in place, one work item per (job, digit d).
 __global__ __launch_bounds__(256) void k_scan(const Table *__restrict__ T, int pass) {
   __shared__ uint32_t lds[256];

@@ -302,4 +302,23 @@ int rotate_bin_kernel_kind(const void *func);
 int cube_kernel_kind(const void *func);
 int psf_lsf_kernel_kind(const void *func);
 
+// Block-wide exclusive scan of one value per thread (256 threads); returns the block total.
+__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t *lds,
+                                                             uint32_t &excl) {
+  const int t = threadIdx.x;
+  lds[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    uint32_t add = (t >= off) ? lds[t - off] : 0u;
+    __syncthreads();
+    lds[t] += add;
+    __syncthreads();
+  }
+  uint32_t incl = lds[t];
+  uint32_t total = lds[255];
+  __syncthreads();
+  excl = incl - v;
+  return total;
+}
+
 }  // namespace rubix
