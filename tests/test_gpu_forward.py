@@ -93,6 +93,24 @@ def test_three_pass_sort_large_grid():
     _check_rotate_bin(w, g)
 
 
+def test_sparse_grid_record_blocks_span_many_spaxels():
+    """300 x 300 spaxels of 0.1 kpc over a 1e5-particle galaxy: in the outskirts a block of 1024
+    sorted particles spans thousands of spaxels, most of them empty, so the record builder's
+    spaxel of each position (from the segment offsets) walks many segment starts per thread."""
+    p = synth.make_galaxy(100_000, seed=78)
+    w = _workload(p, nx=300, ny=300, s=0.1)
+    cfg = O.config_from_workload(w)
+    fo = O.forward(p, cfg, ties=TIES)
+    n_in = int(fo["seg_off"][-1])
+    ks = fo["key"][fo["perm"][:n_in]]
+    spans = [int(ks[min(p0 + 1023, n_in - 1)] - ks[p0] + 1) for p0 in range(0, n_in, 1024)]
+    assert max(spans) > 4096 and sum(sp > 256 for sp in spans) >= 16, spans
+    log(f"sparse 300x300 grid: {n_in} in field, largest block span {max(spans)} spaxels")
+    _, g = gpu_forward(w)
+    _check_rotate_bin(w, g, fo)
+    assert_cube_in(g["cube_raw"], fo, "cube_raw", what="sparse-grid cube_raw")
+
+
 def test_medium_full_size_matches_oracle():
     """The 1e6-particle workload (50x50x3000, SSP 100x12x3000, PSF 1.5 spx, LSF 2.5 A) in full."""
     w = synth.medium_workload()
